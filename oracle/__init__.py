@@ -1,0 +1,17 @@
+"""CPU FP64 oracle for the spherical-grid projector and its companions.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  It shares no code
+with the HIP path (``paper_2608_16960_amd``) and imports nothing from it;
+inputs are plain numpy arrays.
+
+Contents
+  - projector (C, ``tsp_oracle.c``): cone-beam rays, canonical segment lists by
+    the plain definition of the line integral (TomoSphero Sec. 2.1 Eqs. 3-5,
+    Sec. 3), forward and adjoint;
+  - ``reg``: anisotropic smoothed total variation and the Adam update;
+  - ``conv``: 3x3x3 convolution with circular azimuth padding (PyTorch CPU
+    conv3d in float64 as the library step).
+"""
+from .projector import (cone_rays, trace, forward, adjoint, project, num_threads,  # noqa: F401
+                        load_library)

@@ -1,0 +1,319 @@
+"""Pins of the CPU FP64 oracle against things other than itself.
+
+Each test ties the oracle to a fact fixed by the paper or by mathematics:
+closed-form chord lengths of spherical shells (the unit-sphere validation of
+TomoSphero Sec. 5.1 and its generalisation to radial objects), total length,
+hand-derived segment lists, a dense brute-force line integral with an
+independently written point classifier, exact symmetries of the grid, and the
+adjoint identity.  The goal is that a dropped term, a wrong sign, a swapped
+index or a transposed operand in the oracle fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2608_16960_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _unit(d):
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def _chord(starts, dirs, R):
+    """Length of {l >= 0 : |x + n l| < R} for rays starting outside R."""
+    n = _unit(dirs)
+    tc = -np.sum(starts * n, 1)
+    b2 = np.sum(np.cross(starts, n) ** 2, 1)
+    return np.where(tc > 0, 2.0 * np.sqrt(np.maximum(R * R - b2, 0.0)), 0.0)
+
+
+def _rays_of(ora, views):
+    return ora.cone_rays(views.pos, views.look, views.up, views.fov_deg, views.H, views.W)
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_radial_object_closed_form(ora):
+    """Radial-only object on a full-angle grid: y = sum_k rho_k [c(r_k+1) - c(r_k)],
+    c(R) = 2 sqrt(max(R^2 - b^2, 0)).  Tiny workload geometry, FP64 object."""
+    w = W.tiny(noise=0)
+    s, d = _rays_of(ora, w.views)
+    tr = ora.trace(w.grid.arrays(), s, d)
+    rb = w.grid.r_b
+    rc = 0.5 * (rb[1:] + rb[:-1])
+    rk = np.exp(-(rc - 3.0) / 4.0)
+    rho = np.broadcast_to(rk[:, None, None], w.grid.shape).copy()
+    y = ora.forward(tr, rho)
+    yc = sum(rk[k] * (_chord(s, d, rb[k + 1]) - _chord(s, d, rb[k])) for k in range(len(rk)))
+    assert np.all(np.abs(y - yc) <= 1e-12 * np.maximum(1.0, np.abs(yc)))
+    assert np.count_nonzero(yc) > 1000
+
+
+def test_total_length_is_chord_minus_hole(ora):
+    """Sum of a ray's segment lengths = c(r_b[Nr]) - c(r_b[0]) on full-angle grids."""
+    rng = np.random.default_rng(11)
+    for shape, log_r in (((20, 10, 12), True), ((7, 5, 9), False), ((3, 1, 1), False)):
+        g = W.uniform_grid(shape, log_r=log_r)
+        s, d = W.random_rays(3000, rng)
+        tr = ora.trace(g.arrays(), s, d)
+        tot = np.zeros(len(s))
+        np.add.at(tot, np.repeat(np.arange(len(s)), tr["counts"]), tr["len"])
+        ref = _chord(s, d, g.r_b[-1]) - _chord(s, d, g.r_b[0])
+        assert np.max(np.abs(tot - ref)) < 1e-11
+
+
+def test_unit_sphere(ora):
+    """Unit sphere on a (50, 50, 50) grid, rho = 1: y = 2 sqrt(1 - b^2) (Sec. 5.1, Fig. 11).
+    Odd detector: its central pixel passes exactly through the origin."""
+    g = W.uniform_grid((50, 50, 50), r=(0.0, 1.0))
+    v = W.views_at([[3.0, 0.0, 0.0], [0.0, -2.0, 1.5]], (50.0, 50.0), 41, 41)
+    s, d = _rays_of(ora, v)
+    tr = ora.trace(g.arrays(), s, d)
+    y = ora.forward(tr, np.ones(g.shape))
+    ref = _chord(s, d, 1.0)
+    hit = ref > 1e-3
+    assert np.max(np.abs(y - ref)[hit] / ref[hit]) < 1e-12
+    assert np.all(np.abs(y[~hit] - ref[~hit]) < 1e-9)
+    c = 20 * 41 + 20
+    assert abs(y[c] - 2.0) < 1e-14 and np.linalg.norm(np.cross(s[c], d[c])) == 0.0
+
+
+# ----------------------------------------------------------------- hand cases
+
+def _golden():
+    with open(os.path.join(HERE, "golden", "hand_cases.json")) as f:
+        return json.load(f)
+
+
+def _ev(expr):
+    return float(eval(expr, {"sqrt": math.sqrt, "pi": math.pi}))  # noqa: S307 (fixture)
+
+
+@pytest.mark.parametrize("case", _golden()["cases"], ids=lambda c: c["name"])
+def test_hand_derived_cases(ora, case):
+    gd = _golden()["grids"][case["grid"]]
+    grid = tuple(np.array([_ev(e) for e in gd[k].strip("[]").split(",")])
+                 for k in ("r_b", "e_b", "a_b"))
+    tr = ora.trace(grid, np.array([case["start"]]), np.array([case["dir"]]))
+    got = list(zip(tr["vox"].tolist(), tr["len"].tolist()))
+    exp = [(v, _ev(e)) for v, e in case["segments"]]
+    assert [g[0] for g in got] == [e[0] for e in exp]
+    for (_, gl), (_, el) in zip(got, exp):
+        assert abs(gl - el) < 1e-12
+
+
+# ------------------------------------------------------------ brute force
+
+def _classify_brute(p, rb, eb, ab, cyclic):
+    """Independent point classifier: arccos for colatitude, searchsorted."""
+    r = np.linalg.norm(p, axis=1)
+    th = np.arccos(np.clip(p[:, 2] / np.where(r > 0, r, 1), -1, 1))
+    ph = np.mod(np.arctan2(p[:, 1], p[:, 0]) - ab[0], 2 * np.pi)
+    ir = np.searchsorted(rb, r, side="right") - 1
+    ie = np.searchsorted(eb, th, side="right") - 1
+    # a full grid closes its last colatitude bin at pi (the -Z axis is inside)
+    ie = np.where((ie == len(eb) - 1) & (eb[-1] >= np.pi) & (th >= eb[-1]), len(eb) - 2, ie)
+    ia = np.searchsorted(ab - ab[0], ph, side="right") - 1
+    if cyclic:
+        ia = np.where(ia >= len(ab) - 1, 0, ia)
+    ok = (ir >= 0) & (ir < len(rb) - 1) & (ie >= 0) & (ie < len(eb) - 1) & (ia >= 0) & (
+        ia < len(ab) - 1)
+    v = (ir * (len(eb) - 1) + ie) * (len(ab) - 1) + ia
+    return np.where(ok, v, -1)
+
+
+BRUTE_GRIDS = {
+    "full_nonuniform": (np.array([0.6, 0.9, 1.3, 2.0]), np.array([0.0, 0.5, 1.4, 1.9, np.pi]),
+                        np.array([0.0, 1.0, 2.5, 4.0, 5.1, 2 * np.pi])),
+    "wedge": (np.array([0.5, 1.1, 2.0]), np.array([0.4, 0.9, 1.5708, 2.3]),
+              np.array([0.3, 0.9, 1.6, 2.2, 3.3])),
+    "full_from_origin": (np.array([0.0, 0.7, 2.0]), np.array([0.0, np.pi / 3, np.pi / 2, np.pi]),
+                         np.array([-1.0, 0.5, 2.0, -1.0 + 2 * np.pi])),
+}
+
+
+@pytest.mark.parametrize("gname", sorted(BRUTE_GRIDS))
+def test_brute_force_line_integral(ora, gname):
+    """Dense midpoint rule along each chord with an independent classifier.
+
+    |y - y_h| <= 2 h max|rho| (#breakpoints) and per-voxel length errors are
+    at most 2h per visit; h = 2e-4."""
+    rb, eb, ab = BRUTE_GRIDS[gname]
+    cyclic = abs(ab[-1] - ab[0] - 2 * np.pi) < 1e-12
+    rng = np.random.default_rng(sum(map(ord, gname)))
+    starts, dirs = W.random_rays(120, rng, r_start=(3.0, 6.0), aim=1.5)
+    V = (len(rb) - 1) * (len(eb) - 1) * (len(ab) - 1)
+    rho = rng.uniform(-1.0, 2.0, V)
+    tr = ora.trace((rb, eb, ab), starts, dirs)
+    y = ora.forward(tr, rho)
+    n = _unit(dirs)
+    h = 2e-4
+    Rmax = rb[-1]
+    nbreak = 2 * len(rb) + 2 * len(eb) + len(ab) + 2
+    for i in range(len(starts)):
+        tc = -starts[i] @ n[i]
+        b2 = np.sum(np.cross(starts[i], n[i]) ** 2)
+        if tc <= 0 or b2 >= Rmax * Rmax:
+            assert tr["counts"][i] == 0
+            continue
+        hh = math.sqrt(Rmax * Rmax - b2)
+        m = int(math.ceil(2 * hh / h))
+        ts = tc - hh + (np.arange(m) + 0.5) * (2 * hh / m)
+        vv = _classify_brute(starts[i] + ts[:, None] * n[i], rb, eb, ab, cyclic)
+        dl = 2 * hh / m
+        ok = vv >= 0
+        yh = np.sum(rho[vv[ok]]) * dl
+        assert abs(y[i] - yh) <= 2 * dl * 3.0 * nbreak
+        # per-voxel lengths
+        lo, hi = tr["row_ptr"][i], tr["row_ptr"][i + 1]
+        got = {}
+        for v_, l_ in zip(tr["vox"][lo:hi], tr["len"][lo:hi]):
+            got[int(v_)] = got.get(int(v_), 0.0) + l_
+        uv, cnt = np.unique(vv[ok], return_counts=True)
+        bf = dict(zip(uv.tolist(), (cnt * dl).tolist()))
+        for key in set(got) | set(bf):
+            assert abs(got.get(key, 0.0) - bf.get(key, 0.0)) <= 4 * dl + 1e-12, (i, key)
+
+
+# ------------------------------------------------------------- symmetries
+
+def test_rotation_about_z_shifts_azimuth_index(ora):
+    """Rotating every view by one azimuth bin about +Z maps voxel (r,e,a) to
+    (r,e,a+1 mod Na) with identical lengths (uniform cyclic grid)."""
+    w = W.tiny(noise=0)
+    g = w.grid
+    nr, ne, na = g.shape
+    ang = 2 * np.pi / na
+    c, s_ = np.cos(ang), np.sin(ang)
+    Rz = np.array([[c, -s_, 0], [s_, c, 0], [0, 0, 1]])
+    base = W.views_at(w.views.pos + np.array([0.0, 0.0, 7.0]), (30.0, 30.0), 24, 20)
+    rot = W.views_at(base.pos @ Rz.T, (30.0, 30.0), 24, 20, up=[0, 0, 1])
+    s0, d0 = _rays_of(ora, base)
+    s1, d1 = _rays_of(ora, rot)
+    t0 = ora.trace(g.arrays(), s0, d0)
+    t1 = ora.trace(g.arrays(), s1, d1)
+    ok = ~(t0["tie"] | t1["tie"])
+    assert ok.mean() > 0.98
+    assert np.array_equal(t0["counts"][ok], t1["counts"][ok])
+    for i in np.nonzero(ok)[0]:
+        a, b = slice(t0["row_ptr"][i], t0["row_ptr"][i + 1]), slice(t1["row_ptr"][i],
+                                                                    t1["row_ptr"][i + 1])
+        v0, v1 = t0["vox"][a], t1["vox"][b]
+        ia0 = v0 % na
+        assert np.array_equal(v0 - ia0 + (ia0 + 1) % na, v1)
+        assert np.allclose(t0["len"][a], t1["len"][b], rtol=0, atol=1e-11)
+
+
+def test_mirror_z_reverses_elevation_index(ora):
+    """Mirroring z -> -z maps elevation index e to Ne-1-e on symmetric e_b."""
+    g = W.uniform_grid((6, 8, 10))
+    nr, ne, na = g.shape
+    rng = np.random.default_rng(5)
+    s, d = W.random_rays(2000, rng)
+    m = np.array([1.0, 1.0, -1.0])
+    t0 = ora.trace(g.arrays(), s, d)
+    t1 = ora.trace(g.arrays(), s * m, d * m)
+    ok = ~(t0["tie"] | t1["tie"])
+    assert np.array_equal(t0["counts"][ok], t1["counts"][ok])
+    for i in np.nonzero(ok)[0][:800]:
+        a, b = slice(t0["row_ptr"][i], t0["row_ptr"][i + 1]), slice(t1["row_ptr"][i],
+                                                                    t1["row_ptr"][i + 1])
+        v0, v1 = t0["vox"][a], t1["vox"][b]
+        ia = v0 % na
+        ie = (v0 // na) % ne
+        ir = v0 // (na * ne)
+        assert np.array_equal((ir * ne + (ne - 1 - ie)) * na + ia, v1)
+        assert np.allclose(t0["len"][a], t1["len"][b], rtol=0, atol=1e-11)
+
+
+def test_wedge_indicators_sum_to_chord(ora):
+    """Sum over azimuth wedges (and over elevation cones) of wedge-indicator
+    projections equals the shell chord on a full-angle grid."""
+    g = W.uniform_grid((4, 6, 9))
+    nr, ne, na = g.shape
+    s, d = W.random_rays(1500, np.random.default_rng(8))
+    tr = ora.trace(g.arrays(), s, d)
+    ref = _chord(s, d, g.r_b[-1]) - _chord(s, d, g.r_b[0])
+    for axis, n_ in ((2, na), (1, ne)):
+        tot = np.zeros(len(s))
+        for k in range(n_):
+            rho = np.zeros(g.shape)
+            idx = [slice(None)] * 3
+            idx[axis] = k
+            rho[tuple(idx)] = 1.0
+            tot += ora.forward(tr, rho)
+        assert np.max(np.abs(tot - ref)) < 1e-11
+
+
+# --------------------------------------------------------------- adjoint
+
+def test_adjoint_identity_fp64(ora):
+    """<F x, y> = <x, F^T y> for the oracle's forward and adjoint."""
+    w = W.tiny(noise=0)
+    s, d = _rays_of(ora, w.views)
+    tr = ora.trace(w.grid.arrays(), s, d)
+    rng = np.random.default_rng(3)
+    V = w.grid.size
+    x = rng.normal(size=(2, V))
+    y = rng.normal(size=(2, len(s)))
+    Fx = ora.forward(tr, x)
+    FTy = ora.adjoint(tr, y, V)
+    for b in range(2):
+        lhs, rhs = float(Fx[b] @ y[b]), float(x[b] @ FTy[b])
+        assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1.0)
+
+
+def test_adjoint_is_transpose_columnwise(ora):
+    """F^T e_i (unit detector vector) equals row i of F scattered to voxels."""
+    w = W.tiny(noise=0)
+    s, d = _rays_of(ora, w.views)
+    tr = ora.trace(w.grid.arrays(), s, d)
+    V = w.grid.size
+    for i in (0, 100, 1500, 2047, 4000):
+        e = np.zeros(len(s))
+        e[i] = 1.0
+        x = ora.adjoint(tr, e, V)
+        ref = np.zeros(V)
+        lo, hi = tr["row_ptr"][i], tr["row_ptr"][i + 1]
+        np.add.at(ref, tr["vox"][lo:hi], tr["len"][lo:hi])
+        assert np.array_equal(x, ref)
+
+
+# ----------------------------------------------------------- degenerate LOS
+
+def test_degenerate_los_against_brute_force(ora):
+    """Rays in the equatorial plane, inside an azimuth half-plane, through the
+    polar axis, through the origin, tangent-ish to a shell and through the hole."""
+    rb, eb, ab = (np.array([0.5, 1.0, 2.0]), np.linspace(0, np.pi, 5), np.linspace(0, 2 * np.pi, 7))
+    starts = np.array([[-5.0, 0.3, 0.0],     # in the z=0 plane (a boundary cone)
+                       [-5.0, 0.0, 0.7],     # in the xz-plane: crosses the polar axis
+                       [0.0, 0.0, 5.0],      # along the polar axis
+                       [4.0, 4.0, 4.0],      # through the origin
+                       [-5.0, 0.9999, 0.0],  # nearly tangent to r=1 in the z=0 plane
+                       [3.0, -4.0, 0.25]])
+    dirs = np.array([[1.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, -1.0], [-1.0, -1.0, -1.0],
+                     [1.0, 0.0, 0.0], [-0.6, 0.8, 0.0]])
+    V = 2 * 4 * 6
+    rng = np.random.default_rng(2)
+    rho = rng.uniform(0.5, 1.5, V)
+    tr = ora.trace((rb, eb, ab), starts, dirs)
+    y = ora.forward(tr, rho)
+    n = _unit(dirs)
+    for i in range(len(starts)):
+        tc = -starts[i] @ n[i]
+        hh = math.sqrt(max(4.0 - np.sum(np.cross(starts[i], n[i]) ** 2), 0))
+        m = 400000
+        ts = tc - hh + (np.arange(m) + 0.5) * (2 * hh / m)
+        vv = _classify_brute(starts[i] + ts[:, None] * n[i], rb, eb, ab, True)
+        yh = np.sum(rho[vv[vv >= 0]]) * (2 * hh / m)
+        assert abs(y[i] - yh) < 1e-3, i
+        # total length = chord minus hole
+        tot = tr["len"][tr["row_ptr"][i]:tr["row_ptr"][i + 1]].sum()
+        b2 = np.sum(np.cross(starts[i], n[i]) ** 2)
+        ref = 2 * math.sqrt(max(4 - b2, 0)) - 2 * math.sqrt(max(0.25 - b2, 0))
+        assert abs(tot - ref) < 1e-12, i
