@@ -205,9 +205,20 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
         double C = x[2] * x[2] - c2 * xx;
         double rt[2], d, nm;
         int m = quad_roots(A, B, C, rt, &d, &nm);
-        if (fabs(d) <= 1e-9 * nm) {
-            /* grazing: the double root sits near -B/A when A != 0 */
-            if (A != 0 && INSIDE(-B / A)) is_tie = 1;
+        if (fabs(d) <= 1e-9 * nm && A != 0) {
+            /* near-double root at -B/A: a grazing pair when it lies on this
+             * cone's own nappe (a near-planar cone has its two roots on
+             * opposite nappes, which is no grazing) */
+            double tg = -B / A;
+            double zg = x[2] + n[2] * tg;
+            int same = 1;
+            if (m == 2) {
+                double z0 = x[2] + n[2] * rt[0], z1 = x[2] + n[2] * rt[1];
+                same = (z0 * c >= 0) && (z1 * c >= 0);
+            } else {
+                same = zg * c >= 0 || fabs(c) < 1e-6;
+            }
+            if (same && INSIDE(tg)) is_tie = 1;
         }
         for (int i = 0; i < m; i++) {
             double t = rt[i];
