@@ -1,0 +1,195 @@
+/*
+ * tsp.h -- spherical-grid tomographic projector for MI355X (gfx950), C ABI.
+ *
+ * The library computes the line-integral projector of TomoSphero
+ * (Sec. 2.1, Eqs. 1-5): for every detector ray x + n l, l >= 0,
+ *
+ *     y = F rho = sum_i rho[r_i, e_i, a_i] * dl_i                 (Eq. 5)
+ *
+ * over the voxels of a spherical grid (Sec. 2.2) that the ray crosses, and
+ * its adjoint x = F^T y.  Per ray the HIP kernels intersect the ray with the
+ * radial spheres, the colatitude cones and the azimuth half-planes
+ * (Sec. 3.1), turn each crossing into a region index by its direction
+ * (Sec. 3.2, Eqs. 11-13), merge the three ordered crossing streams and take
+ * lengths between consecutive crossings (Sec. 3.3, Table 2), and gather-sum
+ * the object (Sec. 3.4).  Steps 1-3 can be precomputed once per geometry and
+ * stored (Sec. 3, Sec. 4.4): TSP_MODE_CSR stores the segment lists on the
+ * device; TSP_MODE_ONTHEFLY recomputes them inside every forward/adjoint
+ * launch so that nothing proportional to the number of segments is stored.
+ *
+ * Conventions
+ *   - Grid: boundaries r_b[nr+1] (radii, strictly increasing, r_b[0] >= 0),
+ *     e_b[ne+1] (colatitude from +Z in radians, strictly increasing within
+ *     [0, pi]), a_b[na+1] (azimuth counter-clockwise about +Z from +X,
+ *     strictly increasing, a_b[na] - a_b[0] <= 2 pi; the grid is cyclic in
+ *     azimuth when the span is 2 pi within 1e-12).  The grid may be a wedge
+ *     (Sec. 2.2, Fig. 3-4); the object is zero outside it (Sec. 4.6).
+ *   - Voxel (ir, ie, ia) has linear index v = (ir*ne + ie)*na + ia; objects
+ *     are float32 arrays [batch][nr][ne][na] (row-major, contiguous).
+ *   - Rays: cone-beam views (Sec. 4.2, detector at the cone vertex, Sec. 4.6)
+ *     or explicit rays (Sec. 4.2, Listing 4).  Cone view v with detector
+ *     shape (H, W): w = unit(look - pos), u = unit(w x up) (up = +X if w is
+ *     parallel to up), v = u x w; pixel (i, j) looks along
+ *     unit(w + sx u + sy v), sx = (2 (j + 1/2)/W - 1) tan(fov_w/2),
+ *     sy = (2 (i + 1/2)/H - 1) tan(fov_h/2).  Ray id = (view*H + i)*W + j.
+ *     Measurements are float32 arrays [batch][n_rays].
+ *   - Every ray must start outside the outermost sphere (Sec. 4.6).
+ *
+ * Ownership and streams
+ *   - A geometry owns every device buffer it allocates (tables, view frames,
+ *     explicit rays, segment stores).  The caller owns rho, y and x: plain
+ *     contiguous device pointers (e.g. from PyTorch).  Outputs are
+ *     overwritten, never accumulated into.
+ *   - All device work is enqueued on the HIP stream passed as `stream`
+ *     (hipStream_t; NULL = the legacy default stream).  Calls return once
+ *     the work is enqueued, except tsp_trace, which synchronises `stream`
+ *     to learn the segment count it must allocate.
+ *   - After tsp_trace a geometry is immutable: tsp_forward and
+ *     tsp_backproject may run concurrently on different streams.  Calls
+ *     that mutate a geometry (tsp_trace, tsp_geometry_destroy) must not
+ *     overlap other calls on it.
+ *
+ * Errors
+ *   Every call returns a tsp_status; no C++ exception crosses the ABI.  On
+ *   failure tsp_last_error() returns a message for the calling thread.
+ *   Arguments are validated on the host before any launch.
+ */
+#ifndef TSP_H
+#define TSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum tsp_status {
+    TSP_OK = 0,
+    TSP_E_INVALID = 1,     /* bad argument (shape, boundaries, ray inside the grid, NULL) */
+    TSP_E_NOMEM = 2,       /* device allocation failed or exceeds TSP_MAX_DEVICE_BYTES */
+    TSP_E_HIP = 3,         /* a HIP runtime call failed (message carries the HIP error) */
+    TSP_E_STATE = 4,       /* call not valid in the geometry's state (e.g. forward before trace) */
+    TSP_E_UNSUPPORTED = 5  /* combination not implemented (e.g. deterministic adjoint on the fly) */
+} tsp_status;
+
+/* tsp_trace modes */
+#define TSP_MODE_CSR 1        /* precompute and store segment lists (Sec. 3, Sec. 4.4) */
+#define TSP_MODE_ONTHEFLY 2   /* store nothing; recompute per launch */
+#define TSP_TRACE_NO_CSC 0x10 /* CSR mode only: skip the voxel-major (transposed) store */
+
+/* tsp_backproject methods */
+#define TSP_ADJ_DETERMINISTIC 1 /* voxel-major store, fixed summation order, bitwise reproducible */
+#define TSP_ADJ_ATOMIC 2        /* ray-major scatter with float atomics (order varies run to run) */
+
+/* Grid boundaries (Sec. 2.2, Sec. 4.1).  Host pointers, read during
+ * tsp_geometry_create only. */
+typedef struct tsp_grid_desc {
+    int32_t nr, ne, na;
+    const double *r_b; /* nr + 1 radii */
+    const double *e_b; /* ne + 1 colatitudes, radians */
+    const double *a_b; /* na + 1 azimuths, radians */
+} tsp_grid_desc;
+
+/* One cone-beam view (Sec. 4.2, ConeRectGeom; Sec. 4.3 stacks views). */
+typedef struct tsp_cone_view {
+    double pos[3];     /* detector (= cone vertex) position, outside the grid */
+    double look[3];    /* point on the optical axis (the origin in the paper's examples) */
+    double up[3];      /* up hint; all zero means +Z */
+    double fov_deg[2]; /* full field of view along rows (H) and columns (W), degrees, in (0, 180) */
+    int32_t shape[2];  /* detector (H, W); equal for every view of a geometry (Sec. 4.6) */
+} tsp_cone_view;
+
+/* Sizes and state of a geometry. */
+typedef struct tsp_info {
+    int64_t n_rays;       /* R */
+    int64_t n_voxels;     /* V = nr*ne*na */
+    int64_t n_segments;   /* S: valid canonical segments over all rays (after tsp_trace) */
+    int64_t n_stored;     /* segment slots stored in the ray-major store, padding included */
+    int64_t max_per_ray;  /* longest segment list of any ray */
+    int64_t device_bytes; /* device memory currently owned by the geometry */
+    int32_t mode;         /* 0 before tsp_trace, else TSP_MODE_CSR or TSP_MODE_ONTHEFLY */
+    int32_t has_csc;      /* voxel-major store present */
+} tsp_info;
+
+typedef struct tsp_geometry tsp_geometry;
+
+/*
+ * Create a geometry from a grid and EITHER n_views cone views (views != NULL,
+ * ray_starts == ray_dirs == NULL) OR n_rays explicit rays (views == NULL;
+ * ray_starts, ray_dirs: host float64 arrays [n_rays][3]; directions of any
+ * non-zero length, normalised by the library; Sec. 4.2 Listing 4).
+ * Validates the grid (finite, strictly increasing, ranges above), the views
+ * (finite, pos outside the outer sphere, fov in (0, 180), equal shapes, pos
+ * != look) and the rays (finite, non-zero direction, start outside the outer
+ * sphere: TSP_E_INVALID otherwise).  Uploads boundary tables and per-view
+ * frames to the current HIP device.  *out receives the new geometry, owned
+ * by the caller and released with tsp_geometry_destroy.
+ */
+tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *views,
+                               int32_t n_views, const double *ray_starts, const double *ray_dirs,
+                               int64_t n_rays, tsp_geometry **out);
+
+/*
+ * Precompute steps 1-3 (Sec. 3.1-3.3) for every ray.
+ *   TSP_MODE_CSR: counts segments per ray, then stores the canonical segment
+ *     lists (voxel index int32 + length float32 per segment) in a ray-major
+ *     store, and unless TSP_TRACE_NO_CSC is set also a voxel-major
+ *     (transposed) store for the deterministic adjoint.  Needs about 8 bytes
+ *     per segment per store plus 20 bytes per segment of temporary space
+ *     while the transposed store is built.  TSP_E_NOMEM when that exceeds
+ *     the device or the cap in the environment variable TSP_MAX_DEVICE_BYTES
+ *     (the caller may then retry with TSP_MODE_ONTHEFLY).
+ *   TSP_MODE_ONTHEFLY: only counts segments (for tsp_query) and stores no
+ *     lists.
+ * May be called again to switch modes; previous stores are released.
+ * Synchronises `stream`.
+ */
+tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream);
+
+/*
+ * y[b][i] = sum over ray i's segments of len * rho[b][vox]   (Eq. 5)
+ * rho: device float32 [batch][V]; y: device float32 [batch][R], overwritten.
+ * batch >= 1.  TSP_E_STATE before tsp_trace.
+ */
+tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, float *y,
+                       void *stream);
+
+/*
+ * Adjoint: x[b][v] = sum over all segments in voxel v of len * y[b][ray].
+ * y: device float32 [batch][R]; x: device float32 [batch][V], overwritten.
+ * method TSP_ADJ_DETERMINISTIC (CSR mode with the transposed store:
+ * bitwise reproducible) or TSP_ADJ_ATOMIC (CSR or on-the-fly mode).
+ * TSP_E_UNSUPPORTED for a deterministic adjoint without a transposed store.
+ */
+tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
+                           int32_t method, void *stream);
+
+/*
+ * Export the canonical segment lists (the region index and length arrays of
+ * Sec. 4.4, ".regs"/".lens") in ray-major CSR form into caller device
+ * buffers: row_ptr int64 [R+1], vox int32 [S], len float32 [S]; ray i owns
+ * entries row_ptr[i] .. row_ptr[i+1]-1 in increasing distance.  Any of
+ * vox/len may be NULL.  CSR mode only (TSP_E_STATE otherwise).
+ */
+tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, float *len,
+                        void *stream);
+
+/* Write the rays the geometry traces (start, unit direction), device
+ * float64 [R][3] each; either pointer may be NULL. */
+tsp_status tsp_rays(const tsp_geometry *g, double *starts, double *dirs, void *stream);
+
+/* Sizes and state; valid at any time after creation. */
+tsp_status tsp_query(const tsp_geometry *g, tsp_info *info);
+
+/* Release the geometry and all its device memory (NULL is a no-op). Waits
+ * for work already enqueued on the device to finish first. */
+void tsp_geometry_destroy(tsp_geometry *g);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *tsp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSP_H */

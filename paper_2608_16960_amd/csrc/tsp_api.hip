@@ -1,0 +1,628 @@
+// C ABI of the projector library (declared in include/tsp.h): host-side
+// validation, view frames, device memory management and kernel orchestration.
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "tsp.h"
+#include "tsp_internal.h"
+
+using namespace tsp;
+
+namespace {
+
+thread_local std::string g_err;
+
+tsp_status fail(tsp_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define TSP_HIP(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(TSP_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+const double kTwoPi = 6.283185307179586476925286766559;
+
+// Keeps the caller's current device and switches to the geometry's.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int64_t device_cap() {
+    const char *s = std::getenv("TSP_MAX_DEVICE_BYTES");
+    if (!s || !*s) return -1;
+    char *end = nullptr;
+    long long v = std::strtoll(s, &end, 10);
+    return (end && *end == '\0' && v > 0) ? (int64_t)v : -1;
+}
+
+}  // namespace
+
+struct tsp_geometry {
+    int device = 0;
+    TabDesc T{};
+    double *d_tab = nullptr;
+    RayDesc rd{};
+    double *d_frames = nullptr, *d_starts = nullptr, *d_dirs = nullptr;
+    int64_t V = 0, R = 0;
+    int mode = 0;
+    int64_t S = 0, max_per_ray = 0, n_stored = 0;
+    // ray-major sliced store
+    int32_t *d_perm = nullptr, *d_cnt_sorted = nullptr, *d_slice_len = nullptr;
+    int64_t *d_slice_ptr = nullptr;
+    int32_t *d_vox = nullptr;
+    float *d_len = nullptr;
+    int64_t *d_row_ptr = nullptr;
+    // voxel-major store
+    int64_t *d_col_ptr = nullptr;
+    int32_t *d_col_ray = nullptr;
+    float *d_col_len = nullptr;
+    int64_t bytes = 0;
+    std::vector<std::pair<void *, int64_t>> allocs;
+};
+
+namespace {
+
+tsp_status dalloc(tsp_geometry *g, void **p, int64_t bytes, const char *what) {
+    *p = nullptr;
+    if (bytes <= 0) bytes = 16;
+    const int64_t cap = device_cap();
+    if (cap > 0 && g->bytes + bytes > cap) {
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "%s: %lld bytes would exceed TSP_MAX_DEVICE_BYTES=%lld",
+                      what, (long long)bytes, (long long)cap);
+        return fail(TSP_E_NOMEM, buf);
+    }
+    hipError_t e = hipMalloc(p, (size_t)bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        char buf[256];
+        std::snprintf(buf, sizeof buf, "%s: hipMalloc(%lld) failed: %s", what, (long long)bytes,
+                      hipGetErrorString(e));
+        return fail(TSP_E_NOMEM, buf);
+    }
+    g->bytes += bytes;
+    g->allocs.push_back({*p, bytes});
+    return TSP_OK;
+}
+
+template <class T>
+tsp_status dalloc_n(tsp_geometry *g, T **p, int64_t n, const char *what) {
+    void *q = nullptr;
+    tsp_status s = dalloc(g, &q, n * (int64_t)sizeof(T), what);
+    *p = (T *)q;
+    return s;
+}
+
+void dfree(tsp_geometry *g, void *p) {
+    if (!p) return;
+    for (size_t i = 0; i < g->allocs.size(); i++) {
+        if (g->allocs[i].first == p) {
+            g->bytes -= g->allocs[i].second;
+            g->allocs.erase(g->allocs.begin() + (long)i);
+            break;
+        }
+    }
+    (void)hipFree(p);
+}
+
+template <class T>
+void dfree_p(tsp_geometry *g, T *&p) {
+    dfree(g, (void *)p);
+    p = nullptr;
+}
+
+void release_stores(tsp_geometry *g) {
+    dfree_p(g, g->d_perm);
+    dfree_p(g, g->d_cnt_sorted);
+    dfree_p(g, g->d_slice_len);
+    dfree_p(g, g->d_slice_ptr);
+    dfree_p(g, g->d_vox);
+    dfree_p(g, g->d_len);
+    dfree_p(g, g->d_row_ptr);
+    dfree_p(g, g->d_col_ptr);
+    dfree_p(g, g->d_col_ray);
+    dfree_p(g, g->d_col_len);
+    g->mode = 0;
+    g->S = g->max_per_ray = g->n_stored = 0;
+}
+
+bool finite3(const double *v) {
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+tsp_status check_increasing(const double *b, int n, const char *name) {
+    if (!b) return fail(TSP_E_INVALID, std::string(name) + " is NULL");
+    for (int i = 0; i <= n; i++)
+        if (!std::isfinite(b[i])) return fail(TSP_E_INVALID, std::string(name) + " not finite");
+    for (int i = 0; i < n; i++)
+        if (!(b[i + 1] > b[i]))
+            return fail(TSP_E_INVALID, std::string(name) + " not strictly increasing");
+    return TSP_OK;
+}
+
+int bits_for(int64_t v) {  // bits needed to hold values 0..v-1
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < v) b++;
+    return b < 1 ? 1 : b;
+}
+
+tsp_status sync_stream(hipStream_t st) {
+    TSP_HIP(hipStreamSynchronize(st));
+    return TSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tsp_last_error(void) { return g_err.c_str(); }
+
+tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *views,
+                               int32_t n_views, const double *ray_starts, const double *ray_dirs,
+                               int64_t n_rays, tsp_geometry **out) {
+    g_err.clear();
+    if (!out) return fail(TSP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!grid) return fail(TSP_E_INVALID, "grid is NULL");
+    const int nr = grid->nr, ne = grid->ne, na = grid->na;
+    if (nr < 1 || ne < 1 || na < 1) return fail(TSP_E_INVALID, "grid shape must be >= 1");
+    tsp_status s;
+    if ((s = check_increasing(grid->r_b, nr, "r_b")) != TSP_OK) return s;
+    if ((s = check_increasing(grid->e_b, ne, "e_b")) != TSP_OK) return s;
+    if ((s = check_increasing(grid->a_b, na, "a_b")) != TSP_OK) return s;
+    if (grid->r_b[0] < 0) return fail(TSP_E_INVALID, "r_b[0] < 0");
+    if (grid->e_b[0] < 0 || grid->e_b[ne] > M_PI)
+        return fail(TSP_E_INVALID, "e_b outside [0, pi]");
+    const double span = grid->a_b[na] - grid->a_b[0];
+    if (span > kTwoPi + 1e-12) return fail(TSP_E_INVALID, "a_b spans more than 2 pi");
+    const int64_t V = (int64_t)nr * ne * na;
+    if (V >= ((int64_t)1 << 31)) return fail(TSP_E_INVALID, "too many voxels (>= 2^31)");
+    const double Rout = grid->r_b[nr];
+
+    const bool use_views = views != nullptr;
+    if (use_views == (ray_starts != nullptr || ray_dirs != nullptr))
+        return fail(TSP_E_INVALID, "give either cone views or explicit rays");
+    int H = 0, W = 0;
+    int64_t R = 0;
+    std::vector<double> frames, starts, dirs;
+    if (use_views) {
+        if (n_views < 1) return fail(TSP_E_INVALID, "n_views < 1");
+        H = views[0].shape[0];
+        W = views[0].shape[1];
+        if (H < 1 || W < 1) return fail(TSP_E_INVALID, "detector shape must be >= 1");
+        R = (int64_t)n_views * H * W;
+        frames.assign((size_t)n_views * 16, 0.0);
+        for (int v = 0; v < n_views; v++) {
+            const tsp_cone_view &cv = views[v];
+            if (cv.shape[0] != H || cv.shape[1] != W)
+                return fail(TSP_E_INVALID, "all views must share one detector shape");
+            if (!finite3(cv.pos) || !finite3(cv.look) || !finite3(cv.up))
+                return fail(TSP_E_INVALID, "view vectors not finite");
+            for (int k = 0; k < 2; k++)
+                if (!(cv.fov_deg[k] > 0 && cv.fov_deg[k] < 180))
+                    return fail(TSP_E_INVALID, "fov must lie in (0, 180) degrees");
+            const double *P = cv.pos;
+            if (std::sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) <= Rout)
+                return fail(TSP_E_INVALID, "detector inside the grid's outer sphere");
+            double w[3] = {cv.look[0] - P[0], cv.look[1] - P[1], cv.look[2] - P[2]};
+            const double wn = std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            if (!(wn > 0)) return fail(TSP_E_INVALID, "view pos equals look");
+            for (int i = 0; i < 3; i++) w[i] /= wn;
+            double up[3] = {cv.up[0], cv.up[1], cv.up[2]};
+            if (up[0] == 0 && up[1] == 0 && up[2] == 0) up[2] = 1.0;
+            double u[3] = {w[1] * up[2] - w[2] * up[1], w[2] * up[0] - w[0] * up[2],
+                           w[0] * up[1] - w[1] * up[0]};
+            double un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            if (un < 1e-12) {
+                up[0] = 1;
+                up[1] = 0;
+                up[2] = 0;
+                u[0] = w[1] * up[2] - w[2] * up[1];
+                u[1] = w[2] * up[0] - w[0] * up[2];
+                u[2] = w[0] * up[1] - w[1] * up[0];
+                un = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            }
+            for (int i = 0; i < 3; i++) u[i] /= un;
+            const double vv[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
+                                  u[0] * w[1] - u[1] * w[0]};
+            double *f = frames.data() + 16 * v;
+            for (int i = 0; i < 3; i++) {
+                f[0 + i] = P[i];
+                f[3 + i] = w[i];
+                f[6 + i] = u[i];
+                f[9 + i] = vv[i];
+            }
+            f[12] = std::tan(cv.fov_deg[0] * M_PI / 360.0);
+            f[13] = std::tan(cv.fov_deg[1] * M_PI / 360.0);
+        }
+    } else {
+        if (!ray_starts || !ray_dirs) return fail(TSP_E_INVALID, "ray arrays are NULL");
+        if (n_rays < 1) return fail(TSP_E_INVALID, "n_rays < 1");
+        R = n_rays;
+        starts.assign(ray_starts, ray_starts + 3 * n_rays);
+        dirs.resize((size_t)(3 * n_rays));
+        for (int64_t i = 0; i < n_rays; i++) {
+            const double *x = ray_starts + 3 * i, *d = ray_dirs + 3 * i;
+            if (!finite3(x) || !finite3(d)) return fail(TSP_E_INVALID, "ray not finite");
+            const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(dn > 0)) return fail(TSP_E_INVALID, "zero ray direction");
+            if (std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) <= Rout) {
+                char buf[128];
+                std::snprintf(buf, sizeof buf, "ray %lld starts inside the grid's outer sphere",
+                              (long long)i);
+                return fail(TSP_E_INVALID, buf);
+            }
+            for (int k = 0; k < 3; k++) dirs[3 * i + k] = d[k] / dn;
+        }
+    }
+    if (R >= ((int64_t)1 << 31) - 1) return fail(TSP_E_INVALID, "too many rays (>= 2^31)");
+
+    tsp_geometry *g = new tsp_geometry();
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return fail(TSP_E_HIP, "hipGetDevice failed (no GPU?)");
+    }
+    g->V = V;
+    g->R = R;
+
+    // boundary tables
+    const bool cyclic = std::fabs(span - kTwoPi) <= 1e-12;
+    const int np = cyclic ? na : na + 1;
+    TabDesc &T = g->T;
+    T.ab0 = grid->a_b[0];
+    T.nr = nr;
+    T.ne = ne;
+    T.na = na;
+    T.np = np;
+    T.cyclic = cyclic ? 1 : 0;
+    T.off_rb = 0;
+    T.off_ce = T.off_rb + nr + 1;
+    T.off_ca = T.off_ce + ne + 1;
+    T.off_sa = T.off_ca + np;
+    T.off_ab = T.off_sa + np;
+    T.n_tab = T.off_ab + na + 1;
+    std::vector<double> tab((size_t)T.n_tab);
+    for (int k = 0; k <= nr; k++) tab[T.off_rb + k] = grid->r_b[k];
+    for (int k = 0; k <= ne; k++) tab[T.off_ce + k] = std::cos(grid->e_b[k]);
+    for (int k = 0; k < np; k++) {
+        tab[T.off_ca + k] = std::cos(grid->a_b[k]);
+        tab[T.off_sa + k] = std::sin(grid->a_b[k]);
+    }
+    for (int k = 0; k <= na; k++) tab[T.off_ab + k] = grid->a_b[k] - grid->a_b[0];
+
+    RayDesc &rd = g->rd;
+    rd.R = R;
+    if (use_views) {
+        rd.n_views = n_views;
+        rd.H = H;
+        rd.W = W;
+        rd.tiles_h = (H + kTile - 1) / kTile;
+        rd.tiles_w = (W + kTile - 1) / kTile;
+        rd.n_slots = (int64_t)n_views * rd.tiles_h * rd.tiles_w * kWindow;
+        rd.explicit_rays = 0;
+    } else {
+        rd.explicit_rays = 1;
+        rd.n_slots = (R + kWindow - 1) / kWindow * kWindow;
+    }
+
+    auto cleanup = [&](tsp_status st) {
+        tsp_geometry_destroy(g);
+        return st;
+    };
+    if ((s = dalloc_n(g, &g->d_tab, T.n_tab, "tables")) != TSP_OK) return cleanup(s);
+    hipError_t e = hipMemcpy(g->d_tab, tab.data(), tab.size() * sizeof(double),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return cleanup(fail(TSP_E_HIP, hipGetErrorString(e)));
+    if (use_views) {
+        if ((s = dalloc_n(g, &g->d_frames, (int64_t)frames.size(), "frames")) != TSP_OK)
+            return cleanup(s);
+        e = hipMemcpy(g->d_frames, frames.data(), frames.size() * sizeof(double),
+                      hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(fail(TSP_E_HIP, hipGetErrorString(e)));
+        rd.frames = g->d_frames;
+    } else {
+        if ((s = dalloc_n(g, &g->d_starts, 3 * R, "ray starts")) != TSP_OK) return cleanup(s);
+        if ((s = dalloc_n(g, &g->d_dirs, 3 * R, "ray dirs")) != TSP_OK) return cleanup(s);
+        e = hipMemcpy(g->d_starts, starts.data(), starts.size() * sizeof(double),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(g->d_dirs, dirs.data(), dirs.size() * sizeof(double),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return cleanup(fail(TSP_E_HIP, hipGetErrorString(e)));
+        rd.starts = g->d_starts;
+        rd.dirs = g->d_dirs;
+    }
+    *out = g;
+    return TSP_OK;
+}
+
+void tsp_geometry_destroy(tsp_geometry *g) {
+    if (!g) return;
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();
+    for (auto &a : g->allocs) (void)hipFree(a.first);
+    g->allocs.clear();
+    delete g;
+}
+
+tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    const int base_mode = mode & 0x0f;
+    const bool want_csc = (mode & TSP_TRACE_NO_CSC) == 0;
+    if (base_mode != TSP_MODE_CSR && base_mode != TSP_MODE_ONTHEFLY)
+        return fail(TSP_E_INVALID, "mode must be TSP_MODE_CSR or TSP_MODE_ONTHEFLY");
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    TSP_HIP(hipStreamSynchronize(st));
+    release_stores(g);
+    const RayDesc &rd = g->rd;
+    const int64_t ns = rd.n_slots;
+    tsp_status s;
+
+    // pass 1: count canonical segments per ray
+    int32_t *cnt_nat = nullptr;
+    int64_t *counters = nullptr;  // [0] total (u64), [1] max count (int), [2] fill error (int)
+    if ((s = dalloc_n(g, &cnt_nat, ns, "counts")) != TSP_OK) return s;
+    if ((s = dalloc_n(g, &counters, 4, "counters")) != TSP_OK) {
+        dfree(g, cnt_nat);
+        return s;
+    }
+    auto free_tmp = [&]() {
+        dfree(g, cnt_nat);
+        dfree(g, counters);
+    };
+    hipError_t e = hipMemsetAsync(counters, 0, 4 * sizeof(int64_t), st);
+    if (e == hipSuccess)
+        e = launch_count(g->T, g->d_tab, rd, cnt_nat, (unsigned long long *)counters,
+                         (int *)(counters + 1), st);
+    int64_t host_ctr[4] = {0, 0, 0, 0};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_ctr, counters, sizeof host_ctr, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        free_tmp();
+        return fail(TSP_E_HIP, std::string("trace count: ") + hipGetErrorString(e));
+    }
+    g->S = host_ctr[0];
+    g->max_per_ray = (int64_t)(int32_t)(host_ctr[1] & 0xffffffff);
+
+    if (base_mode == TSP_MODE_ONTHEFLY) {
+        free_tmp();
+        g->mode = TSP_MODE_ONTHEFLY;
+        return TSP_OK;
+    }
+
+    // window ordering and slice offsets
+    const int64_t n_slices = ns / kWave;
+    int64_t *scan_tmp = nullptr;
+    const int64_t scan_elems = scan_tmp_elems(ns > g->R + 1 ? ns : g->R + 1);
+    if ((s = dalloc_n(g, &g->d_perm, ns, "perm")) != TSP_OK ||
+        (s = dalloc_n(g, &g->d_cnt_sorted, ns, "sorted counts")) != TSP_OK ||
+        (s = dalloc_n(g, &g->d_slice_len, n_slices, "slice lengths")) != TSP_OK ||
+        (s = dalloc_n(g, &g->d_slice_ptr, n_slices + 1, "slice offsets")) != TSP_OK ||
+        (s = dalloc_n(g, &scan_tmp, scan_elems, "scan scratch")) != TSP_OK) {
+        free_tmp();
+        dfree(g, scan_tmp);
+        release_stores(g);
+        return s;
+    }
+    auto abort_all = [&](tsp_status st2) {
+        free_tmp();
+        dfree(g, scan_tmp);
+        release_stores(g);
+        return st2;
+    };
+    e = launch_window_sort(rd, cnt_nat, g->d_perm, g->d_cnt_sorted, g->d_slice_len, st);
+    if (e == hipSuccess)
+        e = launch_scan_i32(g->d_slice_len, n_slices, kWave, g->d_slice_ptr, scan_tmp, st);
+    int64_t n_stored = 0;
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&n_stored, g->d_slice_ptr + n_slices, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return abort_all(fail(TSP_E_HIP, hipGetErrorString(e)));
+    g->n_stored = n_stored;
+
+    // pass 2: fill the sliced ray-major store
+    if ((s = dalloc_n(g, &g->d_vox, n_stored, "segment voxels")) != TSP_OK) return abort_all(s);
+    if ((s = dalloc_n(g, &g->d_len, n_stored, "segment lengths")) != TSP_OK) return abort_all(s);
+    e = launch_fill(g->T, g->d_tab, rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                    g->d_slice_len, g->d_vox, g->d_len, (int *)(counters + 2), st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_ctr, counters, sizeof host_ctr, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return abort_all(fail(TSP_E_HIP, hipGetErrorString(e)));
+    if ((int32_t)(host_ctr[2] & 0xffffffff) != 0)
+        return abort_all(fail(TSP_E_HIP, "internal: fill pass disagreed with count pass"));
+
+    // canonical row offsets (ray order)
+    int32_t *cnt_ray = nullptr;
+    if ((s = dalloc_n(g, &cnt_ray, g->R, "ray counts")) != TSP_OK) return abort_all(s);
+    if ((s = dalloc_n(g, &g->d_row_ptr, g->R + 1, "row offsets")) != TSP_OK) {
+        dfree(g, cnt_ray);
+        return abort_all(s);
+    }
+    e = launch_scatter_counts(g->d_perm, g->d_cnt_sorted, ns, cnt_ray, st);
+    if (e == hipSuccess) e = launch_scan_i32(cnt_ray, g->R, 1, g->d_row_ptr, scan_tmp, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    dfree(g, cnt_ray);
+    if (e != hipSuccess) return abort_all(fail(TSP_E_HIP, hipGetErrorString(e)));
+    free_tmp();
+    dfree(g, scan_tmp);
+    scan_tmp = nullptr;
+
+    if (want_csc) {
+        const int64_t S = g->S;
+        int32_t *k1 = nullptr, *k2 = nullptr;
+        uint64_t *v1 = nullptr, *v2 = nullptr;
+        void *ws = nullptr;
+        auto free_sort = [&]() {
+            dfree(g, k1);
+            dfree(g, k2);
+            dfree(g, v1);
+            dfree(g, v2);
+            dfree(g, ws);
+        };
+        if ((s = dalloc_n(g, &k1, S, "sort keys")) != TSP_OK ||
+            (s = dalloc_n(g, &k2, S, "sort keys")) != TSP_OK ||
+            (s = dalloc_n(g, &v1, S, "sort values")) != TSP_OK ||
+            (s = dalloc_n(g, &v2, S, "sort values")) != TSP_OK ||
+            (s = dalloc(g, &ws, (int64_t)radix_ws_bytes(S), "sort workspace")) != TSP_OK) {
+            free_sort();
+            release_stores(g);
+            return s;
+        }
+        int in_second = 0;
+        e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len, ns,
+                          g->d_row_ptr, k1, v1, nullptr, nullptr, st);
+        if (e == hipSuccess)
+            e = launch_radix_sort(k1, v1, k2, v2, S, bits_for(g->V), ws, &in_second, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            free_sort();
+            release_stores(g);
+            return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
+        }
+        int32_t *ks = in_second ? k2 : k1;
+        uint64_t *vs = in_second ? v2 : v1;
+        // release what the result does not live in before allocating the store
+        if (in_second) {
+            dfree_p(g, k1);
+            dfree_p(g, v1);
+        } else {
+            dfree_p(g, k2);
+            dfree_p(g, v2);
+        }
+        dfree_p(g, ws);
+        if ((s = dalloc_n(g, &g->d_col_ptr, g->V + 1, "column offsets")) != TSP_OK ||
+            (s = dalloc_n(g, &g->d_col_ray, S, "column rays")) != TSP_OK ||
+            (s = dalloc_n(g, &g->d_col_len, S, "column lengths")) != TSP_OK) {
+            free_sort();
+            release_stores(g);
+            return s;
+        }
+        e = launch_col_ptr(ks, S, g->V, g->d_col_ptr, st);
+        if (e == hipSuccess) e = launch_split_vals(vs, S, g->d_col_ray, g->d_col_len, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        free_sort();
+        if (e != hipSuccess) {
+            release_stores(g);
+            return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
+        }
+    }
+    g->mode = TSP_MODE_CSR;
+    return TSP_OK;
+}
+
+tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, float *y,
+                       void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (!rho || !y) return fail(TSP_E_INVALID, "rho or y is NULL");
+    if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
+    if (g->mode == 0) return fail(TSP_E_STATE, "tsp_forward before tsp_trace");
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (g->mode == TSP_MODE_CSR)
+        e = launch_forward_sell(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
+                                g->d_vox, g->d_len, g->rd.n_slots, rho, batch, g->V, g->R, y, st);
+    else
+        e = launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
+    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("forward: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
+                           int32_t method, void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (!x || !y) return fail(TSP_E_INVALID, "y or x is NULL");
+    if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
+    if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC)
+        return fail(TSP_E_INVALID, "method must be TSP_ADJ_DETERMINISTIC or TSP_ADJ_ATOMIC");
+    if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject before tsp_trace");
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (method == TSP_ADJ_DETERMINISTIC) {
+        if (g->mode != TSP_MODE_CSR || !g->d_col_ptr)
+            return fail(TSP_E_UNSUPPORTED,
+                        "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
+        e = launch_adjoint_csc(g->d_col_ptr, g->d_col_ray, g->d_col_len, g->V, y, batch, g->R, x,
+                               st);
+    } else {
+        e = launch_zero_f32(x, (int64_t)batch * g->V, st);
+        if (e == hipSuccess) {
+            if (g->mode == TSP_MODE_CSR)
+                e = launch_adjoint_atomic(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox,
+                                          g->d_len, g->rd.n_slots, y, batch, g->V, g->R, x, st);
+            else
+                e = launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+        }
+    }
+    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, float *len,
+                        void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (g->mode != TSP_MODE_CSR) return fail(TSP_E_STATE, "segments exist only in CSR mode");
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (row_ptr) e = launch_copy_i64(g->d_row_ptr, row_ptr, g->R + 1, st);
+    if (e == hipSuccess && (vox || len))
+        e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
+                          g->rd.n_slots, g->d_row_ptr, nullptr, nullptr, vox, len, st);
+    if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_rays(const tsp_geometry *g, double *starts, double *dirs, void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    DeviceGuard dg(g->device);
+    hipError_t e = launch_rays(g->rd, starts, dirs, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_query(const tsp_geometry *g, tsp_info *info) {
+    g_err.clear();
+    if (!g || !info) return fail(TSP_E_INVALID, "NULL argument");
+    info->n_rays = g->R;
+    info->n_voxels = g->V;
+    info->n_segments = g->S;
+    info->n_stored = g->n_stored;
+    info->max_per_ray = g->max_per_ray;
+    info->device_bytes = g->bytes;
+    info->mode = g->mode;
+    info->has_csc = g->d_col_ptr != nullptr;
+    return TSP_OK;
+}
+
+}  // extern "C"

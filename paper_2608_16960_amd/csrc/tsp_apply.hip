@@ -1,0 +1,233 @@
+// Step 4 of TomoSphero (Sec. 3.4, Eq. 5) and its adjoint from the stored
+// segment lists, on gfx950.
+//
+// Forward: one lane per ray slot of a 64-ray slice of the ray-major store.
+// Every step a wavefront reads one coalesced 256-byte row of voxel indices and
+// one of lengths, gathers rho (the object stays in L2 / Infinity Cache), and
+// accumulates len * rho in FP32 with FMA.  No reduction across lanes.
+//
+// Deterministic adjoint: one wavefront per voxel of the voxel-major store.
+// Lane l sums entries l, l+64, ... of the voxel's list (ray order) and a fixed
+// butterfly adds the 64 partial sums, so the result is bitwise reproducible.
+//
+// Atomic adjoint: ray-major like the forward, scattering len * y into x with
+// hardware float atomics.
+
+#include "tsp_internal.h"
+
+namespace tsp {
+namespace {
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ perm,
+                                                   const int32_t *__restrict__ cnt_sorted,
+                                                   const int64_t *__restrict__ slice_ptr,
+                                                   const int32_t *__restrict__ slice_len,
+                                                   const int32_t *__restrict__ vox,
+                                                   const float *__restrict__ len, int64_t n_slots,
+                                                   const float *__restrict__ rho, int nb,
+                                                   int64_t V, int64_t R, float *__restrict__ y) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int64_t s = slot >> 6;
+    const int lane = (int)(slot & 63);
+    const int32_t ray = perm[slot];
+    const int c = cnt_sorted[slot];
+    const int m = slice_len[s];
+    const int32_t *vp = vox + slice_ptr[s] + lane;
+    const float *lp = len + slice_ptr[s] + lane;
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) acc[b] = 0.0f;
+    int j = 0;
+    for (; j + 8 <= m; j += 8) {
+        int32_t vv[8];
+        float ll[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            const bool ok = j + u < c;
+            vv[u] = ok ? vp[(int64_t)(j + u) * kWave] : 0;
+            ll[u] = ok ? lp[(int64_t)(j + u) * kWave] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+            if (j + u < c) {
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    if (b < nb) acc[b] = fmaf(ll[u], rho[b * V + vv[u]], acc[b]);
+            }
+        }
+    }
+    for (; j < m; j++) {
+        if (j < c) {
+            const int32_t v = vp[(int64_t)j * kWave];
+            const float l = lp[(int64_t)j * kWave];
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                if (b < nb) acc[b] = fmaf(l, rho[b * V + v], acc[b]);
+        }
+    }
+    if (ray >= 0) {
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) y[b * R + ray] = acc[b];
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
+                                                  const int32_t *__restrict__ col_ray,
+                                                  const float *__restrict__ col_len, int64_t V,
+                                                  const float *__restrict__ y, int nb, int64_t R,
+                                                  float *__restrict__ x) {
+    const int64_t v = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (v >= V) return;
+    const int64_t lo = col_ptr[v], hi = col_ptr[v + 1];
+    float acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) acc[b] = 0.0f;
+    for (int64_t k = lo + lane; k < hi; k += kWave) {
+        const int32_t r = col_ray[k];
+        const float l = col_len[k];
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) acc[b] = fmaf(l, y[b * R + r], acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc[b] += __shfl_xor(acc[b], o, kWave);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) x[b * V + v] = acc[b];
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ cnt_sorted,
+                                                     const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ vox,
+                                                     const float *__restrict__ len,
+                                                     int64_t n_slots, const float *__restrict__ y,
+                                                     int nb, int64_t V, int64_t R, float *x) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t ray = perm[slot];
+    if (ray < 0) return;
+    const int c = cnt_sorted[slot];
+    const int64_t base = slice_ptr[slot >> 6] + (slot & 63);
+    float yv[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) yv[b] = (b < nb) ? y[b * R + ray] : 0.0f;
+    for (int j = 0; j < c; j++) {
+        const int32_t v = vox[base + (int64_t)j * kWave];
+        const float l = len[base + (int64_t)j * kWave];
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) atomicAdd(x + b * V + v, l * yv[b]);
+    }
+}
+
+__global__ void k_zero(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+__global__ void k_copy_i64(const int64_t *s, int64_t *d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
+                               const int64_t *slice_ptr, const int32_t *slice_len,
+                               const int32_t *vox, const float *len, int64_t n_slots,
+                               const float *rho, int B, int64_t V, int64_t R, float *y,
+                               hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *r = rho + (int64_t)b0 * V;
+        float *yy = y + (int64_t)b0 * R;
+        const dim3 g(blocks_for(n_slots, 256));
+        if (nb == 1)
+            hipLaunchKernelGGL(k_fwd_sell<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+        else if (nb == 2)
+            hipLaunchKernelGGL(k_fwd_sell<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+        else
+            hipLaunchKernelGGL(k_fwd_sell<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
+                              int64_t V, const float *y, int B, int64_t R, float *x,
+                              hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *yy = y + (int64_t)b0 * R;
+        float *xx = x + (int64_t)b0 * V;
+        const dim3 g(blocks_for(V * kWave, 256));
+        if (nb == 1)
+            hipLaunchKernelGGL(k_adj_csc<1>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+                               yy, nb, R, xx);
+        else if (nb == 2)
+            hipLaunchKernelGGL(k_adj_csc<2>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+                               yy, nb, R, xx);
+        else
+            hipLaunchKernelGGL(k_adj_csc<4>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+                               yy, nb, R, xx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
+                                 const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                                 int64_t n_slots, const float *y, int B, int64_t V, int64_t R,
+                                 float *x, hipStream_t st) {
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *yy = y + (int64_t)b0 * R;
+        float *xx = x + (int64_t)b0 * V;
+        const dim3 g(blocks_for(n_slots, 256));
+        if (nb == 1)
+            hipLaunchKernelGGL(k_adj_atomic<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               vox, len, n_slots, yy, nb, V, R, xx);
+        else if (nb == 2)
+            hipLaunchKernelGGL(k_adj_atomic<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               vox, len, n_slots, yy, nb, V, R, xx);
+        else
+            hipLaunchKernelGGL(k_adj_atomic<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
+                               vox, len, n_slots, yy, nb, V, R, xx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_i64, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace tsp

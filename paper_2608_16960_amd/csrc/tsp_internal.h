@@ -1,0 +1,106 @@
+// Internal declarations of the projector library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tsp {
+
+constexpr int kWave = 64;     // CDNA wavefront
+constexpr int kWindow = 256;  // ray slots per window: one 16x16 detector tile
+constexpr int kTile = 16;
+
+// Packed FP64 boundary tables, staged into LDS by every trace kernel.
+//   rb[nr+1]    radii
+//   ce[ne+1]    cos(e_b), decreasing
+//   ca[np], sa[np]  cos/sin of the np distinct azimuth half-planes
+//   ab[na+1]    a_b[k] - a_b[0]
+struct TabDesc {
+    double ab0;  // a_b[0]
+    int nr, ne, na, np, cyclic;
+    int off_rb, off_ce, off_ca, off_sa, off_ab, n_tab;
+};
+
+// Where rays come from: cone views (frames) or explicit arrays.
+struct RayDesc {
+    int n_views, H, W, tiles_h, tiles_w;
+    const double *frames;  // per view 16 doubles: pos(3) w(3) u(3) v(3) tan_h tan_w 0 0
+    const double *starts;  // explicit: [R][3]
+    const double *dirs;    // explicit: [R][3], unit
+    int explicit_rays;
+    int64_t R;
+    int64_t n_slots;       // multiple of kWindow
+};
+
+// Slot -> ray id in the natural order: windows of 16x16 pixels of one view,
+// split into four 8x8 wavefront blocks; -1 for slots past the detector edge.
+// Explicit rays: slot i is ray i.
+__device__ __forceinline__ int32_t natural_ray(const RayDesc &rd, int64_t slot) {
+    if (rd.explicit_rays) return (slot < rd.R) ? (int32_t)slot : -1;
+    const int64_t wdw = slot / kWindow;
+    const int lane = (int)(slot % kWindow);
+    const int per_view = rd.tiles_h * rd.tiles_w;
+    const int view = (int)(wdw / per_view);
+    const int t = (int)(wdw % per_view);
+    const int ti = t / rd.tiles_w, tj = t % rd.tiles_w;
+    const int w = lane >> 6, l = lane & 63;
+    const int i = ti * kTile + (w >> 1) * 8 + (l >> 3);
+    const int j = tj * kTile + (w & 1) * 8 + (l & 7);
+    if (view >= rd.n_views || i >= rd.H || j >= rd.W) return -1;
+    return (view * rd.H + i) * rd.W + j;
+}
+
+// ---- launchers (tsp_trace.hip) ----
+hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
+                        unsigned long long *total, int *maxcnt, hipStream_t st);
+hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
+                       const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                       const int32_t *slice_len, int32_t *vox, float *len, int *err,
+                       hipStream_t st);
+hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
+                              const float *rho, int B, int64_t V, float *y, hipStream_t st);
+hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
+                              const float *y, int B, int64_t V, float *x, hipStream_t st);
+hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st);
+
+// ---- launchers (tsp_sort.hip) ----
+hipError_t launch_window_sort(const RayDesc &rd, const int32_t *cnt_nat, int32_t *perm,
+                              int32_t *cnt_sorted, int32_t *slice_len, hipStream_t st);
+// exclusive scan of n int32 values (times `mul`) into out[0..n] (int64, out[n] = total)
+hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *out,
+                           int64_t *tmp, hipStream_t st);
+int64_t scan_tmp_elems(int64_t n);
+hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
+                                 int32_t *cnt_ray, hipStream_t st);
+hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                         const int32_t *vox, const float *len, int64_t n_slots,
+                         const int64_t *row_ptr, int32_t *keys, uint64_t *vals,
+                         int32_t *out_vox, float *out_len, hipStream_t st);
+// stable LSD radix sort of (key, val) by key (key < 2^key_bits); result lands in
+// (keys, vals) or (keys2, vals2): returns through *in_second whether it is the second.
+hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
+                             int64_t n, int key_bits, void *ws, int *in_second, hipStream_t st);
+size_t radix_ws_bytes(int64_t n);
+hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int64_t *col_ptr,
+                          hipStream_t st);
+hipError_t launch_split_vals(const uint64_t *vals, int64_t n, int32_t *ray, float *len,
+                             hipStream_t st);
+
+// ---- launchers (tsp_apply.hip) ----
+hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
+                               const int64_t *slice_ptr, const int32_t *slice_len,
+                               const int32_t *vox, const float *len, int64_t n_slots,
+                               const float *rho, int B, int64_t V, int64_t R, float *y,
+                               hipStream_t st);
+hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
+                              int64_t V, const float *y, int B, int64_t R, float *x,
+                              hipStream_t st);
+hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
+                                 const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                                 int64_t n_slots, const float *y, int B, int64_t V, int64_t R,
+                                 float *x, hipStream_t st);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
+
+}  // namespace tsp

@@ -1,0 +1,364 @@
+// Building the segment stores on gfx950: per-window ordering of ray slots,
+// prefix sums, and the stable transposition of the ray-major segment lists
+// into the voxel-major store used by the deterministic adjoint.
+//
+// Ray-major store ("sliced"): the 256 ray slots of a 16x16 detector window
+// are ordered by decreasing segment count and cut into four 64-ray slices;
+// slice s stores segment j of its lane l at slice_ptr[s] + 64 j + l, padded
+// to the slice's longest list.  A wavefront then reads one coalesced 256-byte
+// row of indices and of lengths per step.
+//
+// Voxel-major store: the canonical (ray-ordered) segments are sorted by voxel
+// with a stable LSD radix sort (8-bit digits), so every voxel's entries keep
+// increasing ray order; the adjoint then sums each voxel in a fixed order.
+
+#include "tsp_internal.h"
+
+namespace tsp {
+namespace {
+
+// ------------------------------------------------------------ window sort
+
+__global__ __launch_bounds__(256) void k_window_sort(RayDesc rd, const int32_t *cnt_nat,
+                                                      int32_t *perm, int32_t *cnt_sorted,
+                                                      int32_t *slice_len) {
+    __shared__ uint64_t key[256];
+    const int t = threadIdx.x;
+    const int64_t slot = (int64_t)blockIdx.x * 256 + t;
+    const int32_t ray = natural_ray(rd, slot);
+    const int32_t c = cnt_nat[slot];
+    // ascending key = (descending count, ascending ray, empty slots last)
+    const uint32_t hi = 0x7fffffffu - (uint32_t)c;
+    const uint32_t lo = (ray >= 0) ? (uint32_t)ray : 0xffffffffu;
+    key[t] = ((uint64_t)hi << 32) | lo;
+    __syncthreads();
+    for (int k = 2; k <= 256; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int p = t ^ j;
+            if (p > t) {
+                const uint64_t a = key[t], b = key[p];
+                const bool up = (t & k) == 0;
+                if ((a > b) == up) {
+                    key[t] = b;
+                    key[p] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const uint64_t mine = key[t];
+    const int32_t cs = (int32_t)(0x7fffffffu - (uint32_t)(mine >> 32));
+    const uint32_t r = (uint32_t)(mine & 0xffffffffu);
+    perm[slot] = (r == 0xffffffffu) ? -1 : (int32_t)r;
+    cnt_sorted[slot] = cs;
+    if ((t & 63) == 0) slice_len[slot >> 6] = cs;  // longest list of the slice
+}
+
+// ------------------------------------------------------------ scan (int32 -> int64)
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = 256 * kScanItems;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t *total) {
+    __shared__ int64_t ws[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) ws[w] = incl;
+    __syncthreads();
+    int64_t wpre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        if (i < w) wpre += ws[i];
+        tot += ws[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return wpre + incl - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const int32_t *in, int64_t n, int64_t mul,
+                                                      int64_t *blk) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++)
+        if (base + i < n) s += (int64_t)in[base + i] * mul;
+    int64_t tot;
+    block_exclusive_scan(s, &tot);
+    if (threadIdx.x == 0) blk[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_blocks(int64_t *blk, int64_t nb) {
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t v = (i < nb) ? blk[i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, &tot);
+        if (i < nb) blk[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) blk[nb] = carry;
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const int32_t *in, int64_t n, int64_t mul,
+                                                     const int64_t *blk, int64_t *out) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = (base + i < n) ? (int64_t)in[base + i] * mul : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t run = blk[blockIdx.x] + block_exclusive_scan(s, &tot);
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) out[base + i] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = blk[gridDim.x];
+}
+
+// ------------------------------------------------------------ canonical order
+
+__global__ void k_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
+                                 int32_t *cnt_ray) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t r = perm[slot];
+    if (r >= 0) cnt_ray[r] = cnt_sorted[slot];
+}
+
+__global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32_t *cnt_sorted,
+                                                 const int64_t *slice_ptr, const int32_t *vox,
+                                                 const float *len, int64_t n_slots,
+                                                 const int64_t *row_ptr, int32_t *keys,
+                                                 uint64_t *vals, int32_t *out_vox,
+                                                 float *out_len) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t r = perm[slot];
+    if (r < 0) return;
+    const int c = cnt_sorted[slot];
+    const int64_t src = slice_ptr[slot >> 6] + (slot & 63);
+    const int64_t dst = row_ptr[r];
+    for (int j = 0; j < c; j++) {
+        const int32_t v = vox[src + (int64_t)j * kWave];
+        const float l = len[src + (int64_t)j * kWave];
+        if (keys) {
+            keys[dst + j] = v;
+            vals[dst + j] = (uint64_t)(uint32_t)r | ((uint64_t)__float_as_uint(l) << 32);
+        }
+        if (out_vox) out_vox[dst + j] = v;
+        if (out_len) out_len[dst + j] = l;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+
+constexpr int kRsItems = 16;                // items per thread
+constexpr int kRsTile = 256 * kRsItems;     // items per block
+constexpr int kRsWaveItems = 64 * kRsItems;
+
+__global__ __launch_bounds__(256) void k_rs_hist(const int32_t *keys, int64_t n, int shift,
+                                                  int32_t *hist, int64_t nblk) {
+    __shared__ unsigned cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRsTile;
+    for (int i = threadIdx.x; i < kRsTile; i += 256) {
+        const int64_t idx = base + i;
+        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = (int32_t)cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin, const uint64_t *vin,
+                                                     int32_t *kout, uint64_t *vout, int64_t n,
+                                                     int shift, const int64_t *offs,
+                                                     int64_t nblk) {
+    __shared__ unsigned run[4][256];
+    __shared__ unsigned wbase[4][256];
+    __shared__ int64_t goff[256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < 1024; i += 256) (&run[0][0])[i] = 0;
+    goff[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t wb = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveItems;
+    for (int c = 0; c < kRsItems; c++) {
+        const int64_t idx = wb + c * 64 + lane;
+        if (idx < n) atomicAdd(&run[w][(kin[idx] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    {
+        unsigned acc = 0;
+#pragma unroll
+        for (int ww = 0; ww < 4; ww++) {
+            const unsigned cc = run[ww][tid];
+            wbase[ww][tid] = acc;
+            acc += cc;
+            run[ww][tid] = 0;
+        }
+    }
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int c = 0; c < kRsItems; c++) {
+        const int64_t idx = wb + c * 64 + lane;
+        const bool valid = idx < n;
+        const int32_t k = valid ? kin[idx] : 0;
+        const uint64_t v = valid ? vin[idx] : 0ull;
+        const int d = (k >> shift) & 255;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int bbit = 0; bbit < 8; bbit++) {
+            const bool bitset = (d >> bbit) & 1;
+            const uint64_t m = __ballot(bitset);
+            match &= bitset ? m : ~m;
+        }
+        const unsigned rank = (unsigned)__popcll(match & below);
+        const unsigned before = run[w][d];
+        if (valid) {
+            const int64_t pos = goff[d] + wbase[w][d] + before + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        const bool leader = valid && ((match >> lane) == 1ull);
+        __builtin_amdgcn_wave_barrier();
+        if (leader) run[w][d] = before + (unsigned)__popcll(match);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+__global__ void k_col_ptr(const int32_t *keys, int64_t n, int64_t V, int64_t *col_ptr) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > V) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {  // first index with key >= v
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    col_ptr[v] = lo;
+}
+
+__global__ void k_split(const uint64_t *vals, int64_t n, int32_t *ray, float *len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t v = vals[i];
+    ray[i] = (int32_t)(uint32_t)(v & 0xffffffffull);
+    len[i] = __uint_as_float((uint32_t)(v >> 32));
+}
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+}  // namespace
+
+hipError_t launch_window_sort(const RayDesc &rd, const int32_t *cnt_nat, int32_t *perm,
+                              int32_t *cnt_sorted, int32_t *slice_len, hipStream_t st) {
+    hipLaunchKernelGGL(k_window_sort, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
+                       cnt_nat, perm, cnt_sorted, slice_len);
+    return hipGetLastError();
+}
+
+int64_t scan_tmp_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *out,
+                           int64_t *tmp, hipStream_t st) {
+    const int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb == 0) {
+        hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, st, tmp, (int64_t)0);
+        return hipMemcpyAsync(out, tmp, sizeof(int64_t), hipMemcpyDeviceToDevice, st);
+    }
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, st, in, n, mul, tmp);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(256), 0, st, tmp, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, st, in, n, mul,
+                       (const int64_t *)tmp, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
+                                 int32_t *cnt_ray, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_counts, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, perm,
+                       cnt_sorted, n_slots, cnt_ray);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                         const int32_t *vox, const float *len, int64_t n_slots,
+                         const int64_t *row_ptr, int32_t *keys, uint64_t *vals,
+                         int32_t *out_vox, float *out_len, hipStream_t st) {
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, perm,
+                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, keys, vals, out_vox,
+                       out_len);
+    return hipGetLastError();
+}
+
+static int64_t rs_blocks(int64_t n) { return (n + kRsTile - 1) / kRsTile; }
+
+size_t radix_ws_bytes(int64_t n) {
+    const int64_t nb = rs_blocks(n);
+    const int64_t h = 256 * nb;
+    return sizeof(int32_t) * (size_t)h + sizeof(int64_t) * (size_t)(h + 1) +
+           sizeof(int64_t) * (size_t)scan_tmp_elems(h) + 256;
+}
+
+hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
+                             int64_t n, int key_bits, void *ws, int *in_second, hipStream_t st) {
+    *in_second = 0;
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = rs_blocks(n);
+    const int64_t h = 256 * nb;
+    char *p = (char *)ws;
+    int32_t *hist = (int32_t *)p;
+    p += sizeof(int32_t) * (size_t)h;
+    p = (char *)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    int64_t *offs = (int64_t *)p;
+    p += sizeof(int64_t) * (size_t)(h + 1);
+    int64_t *tmp = (int64_t *)p;
+    int32_t *ka = keys, *kb = keys2;
+    uint64_t *va = vals, *vb = vals2;
+    int passes = 0;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)nb), dim3(256), 0, st, ka, n, shift, hist,
+                           nb);
+        hipError_t e = launch_scan_i32(hist, h, 1, offs, tmp, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(256), 0, st, ka, va, kb, vb, n,
+                           shift, offs, nb);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        int32_t *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint64_t *tv = va;
+        va = vb;
+        vb = tv;
+        passes++;
+    }
+    *in_second = passes & 1;
+    return hipSuccess;
+}
+
+hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int64_t *col_ptr,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_col_ptr, dim3(blocks_for(V + 1, 256)), dim3(256), 0, st, sorted_keys, n,
+                       V, col_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_vals(const uint64_t *vals, int64_t n, int32_t *ray, float *len,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_split, dim3(blocks_for(n, 256)), dim3(256), 0, st, vals, n, ray, len);
+    return hipGetLastError();
+}
+
+}  // namespace tsp

@@ -1,0 +1,326 @@
+// Ray tracing through a spherical grid on gfx950: steps 1-3 of TomoSphero
+// (Sec. 3.1 intersections, Sec. 3.2 crossing directions, Sec. 3.3 ordering
+// and lengths) fused per ray, plus the on-the-fly forward / adjoint that feed
+// every segment straight into step 4 (Sec. 3.4, Eq. 5).
+//
+// One ray per lane.  Instead of materialising the padded crossing arrays of
+// Sec. 3.1 and sorting them (Sec. 3.3), each lane walks three crossing
+// streams that are already ordered by distance:
+//   radial      spheres r_b[k]: inbound roots in decreasing k, then outbound
+//               roots in increasing k; every inbound crossing is "negative"
+//               and every outbound one "positive" (Eq. 11), so the region
+//               index becomes k-1 or k;
+//   elevation   cones cos(theta) = cos(e_b[k]); along a line the colatitude
+//               has at most one turning point, at the distance where Eq. 12's
+//               m.n vanishes, so the crossings form at most two monotone runs;
+//               the regions at the run ends fix which cones are crossed, and
+//               Eq. 12's sign at each root picks the root of the cone's
+//               quadratic that belongs to the run;
+//   azimuth     half-planes a_b[k]: the azimuth is monotone along a line, in
+//               the direction of (p x n)_z (Eq. 13), sweeping less than pi.
+// The lane merges the three streams by distance (ties: radial, elevation,
+// azimuth), updates one index per crossing as in Table 2(b), skips rows with
+// an invalid index (Table 2(c)), and merges touching pieces of the same voxel
+// into one canonical segment.
+//
+// The lane classifies the ray's entry point on the outermost sphere (the
+// region of the start point of Table 2(a), advanced past the crossings that
+// lie outside the grid, which cannot contribute).
+//
+// All geometry is FP64; boundary tables are staged in LDS.  The file is
+// compiled with -ffp-contract=off so that the counting and the filling
+// kernels, which re-trace the same ray, evaluate identical arithmetic.
+
+#include <cmath>
+
+#include "tsp_internal.h"
+#include "tsp_trace_core.h"
+
+namespace tsp {
+namespace {
+
+using namespace core;
+
+__device__ __forceinline__ void ray_of(const RayDesc &rd, int32_t ray, V3 &x, V3 &n) {
+    if (rd.explicit_rays) {
+        const double *s = rd.starts + 3 * (int64_t)ray;
+        const double *d = rd.dirs + 3 * (int64_t)ray;
+        x = {s[0], s[1], s[2]};
+        n = {d[0], d[1], d[2]};
+        return;
+    }
+    const int hw = rd.H * rd.W;
+    const int view = ray / hw;
+    const int rem = ray - view * hw;
+    const int i = rem / rd.W, j = rem - (rem / rd.W) * rd.W;
+    const double *f = rd.frames + 16 * view;
+    const double sy = (2.0 * (i + 0.5) / rd.H - 1.0) * f[12];
+    const double sx = (2.0 * (j + 0.5) / rd.W - 1.0) * f[13];
+    double d0 = f[3] + sx * f[6] + sy * f[9];
+    double d1 = f[4] + sx * f[7] + sy * f[10];
+    double d2 = f[5] + sx * f[8] + sy * f[11];
+    const double dn = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    x = {f[0], f[1], f[2]};
+    n = {d0 / dn, d1 / dn, d2 / dn};
+}
+
+// ---------------------------------------------------------------- visitors
+
+struct CountVis {
+    int n = 0;
+    __device__ void seg(int, double) { n++; }
+};
+
+struct FillVis {
+    int32_t *vox;
+    float *len;
+    int cap;
+    int n = 0;
+    __device__ void seg(int v, double l) {
+        if (n < cap) {
+            vox[(int64_t)n * kWave] = v;
+            len[(int64_t)n * kWave] = (float)l;
+        }
+        n++;
+    }
+};
+
+template <int NB>
+struct FwdVis {
+    const float *rho;
+    int64_t V;
+    int nb;
+    float acc[NB];
+    __device__ void seg(int v, double l) {
+        const float lf = (float)l;
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) acc[b] = fmaf(lf, rho[b * V + v], acc[b]);
+    }
+};
+
+template <int NB>
+struct AdjVis {
+    float *x;
+    int64_t V;
+    int nb;
+    float yv[NB];
+    __device__ void seg(int v, double l) {
+        const float lf = (float)l;
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+            if (b < nb) atomicAdd(x + b * V + v, lf * yv[b]);
+    }
+};
+
+// ---------------------------------------------------------------- kernels
+
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, RayDesc rd,
+                                                int32_t *cnt_nat, unsigned long long *total,
+                                                int *maxcnt) {
+    extern __shared__ double lds[];
+    stage_tables(D, tab, lds);
+    const Tab T = make_tab(D, lds);
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int c = 0;
+    if (slot < rd.n_slots) {
+        const int32_t ray = natural_ray(rd, slot);
+        if (ray >= 0) {
+            V3 x, n;
+            ray_of(rd, ray, x, n);
+            CountVis vis;
+            trace_ray(T, x, n, vis);
+            c = vis.n;
+        }
+        cnt_nat[slot] = c;
+    }
+    const int s = wave_sum_i(c);
+    const int m = wave_max_i(c);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(total, (unsigned long long)s);
+        atomicMax(maxcnt, m);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill(TabDesc D, const double *tab, RayDesc rd,
+                                               const int32_t *perm, const int32_t *cnt_sorted,
+                                               const int64_t *slice_ptr,
+                                               const int32_t *slice_len, int32_t *vox,
+                                               float *len, int *err) {
+    extern __shared__ double lds[];
+    stage_tables(D, tab, lds);
+    const Tab T = make_tab(D, lds);
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= rd.n_slots) return;
+    const int64_t s = slot / kWave;
+    const int lane = (int)(slot % kWave);
+    const int32_t ray = perm[slot];
+    const int cap = cnt_sorted[slot];
+    const int m = slice_len[s];
+    const int64_t base = slice_ptr[s] + lane;
+    int n = 0;
+    if (ray >= 0) {
+        V3 x, nn;
+        ray_of(rd, ray, x, nn);
+        FillVis vis{vox + base, len + base, cap};
+        trace_ray(T, x, nn, vis);
+        n = vis.n;
+        if (n != cap) atomicOr(err, 1);
+    }
+    for (int j = min(n, cap); j < m; j++) {
+        vox[base + (int64_t)j * kWave] = 0;
+        len[base + (int64_t)j * kWave] = 0.0f;
+    }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *tab, RayDesc rd,
+                                                      const float *rho, int nb, int64_t V,
+                                                      float *y) {
+    extern __shared__ double lds[];
+    stage_tables(D, tab, lds);
+    const Tab T = make_tab(D, lds);
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= rd.n_slots) return;
+    const int32_t ray = natural_ray(rd, slot);
+    if (ray < 0) return;
+    V3 x, n;
+    ray_of(rd, ray, x, n);
+    FwdVis<NB> vis;
+    vis.rho = rho;
+    vis.V = V;
+    vis.nb = nb;
+#pragma unroll
+    for (int b = 0; b < NB; b++) vis.acc[b] = 0.0f;
+    trace_ray(T, x, n, vis);
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+        if (b < nb) y[b * rd.R + ray] = vis.acc[b];
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
+                                                      const float *y, int nb, int64_t V,
+                                                      float *x_out) {
+    extern __shared__ double lds[];
+    stage_tables(D, tab, lds);
+    const Tab T = make_tab(D, lds);
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= rd.n_slots) return;
+    const int32_t ray = natural_ray(rd, slot);
+    if (ray < 0) return;
+    AdjVis<NB> vis;
+    vis.x = x_out;
+    vis.V = V;
+    vis.nb = nb;
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        vis.yv[b] = (b < nb) ? y[b * rd.R + ray] : 0.0f;
+        any |= (vis.yv[b] != 0.0f);
+    }
+    if (!any) return;  // a zero measurement contributes nothing
+    V3 x, n;
+    ray_of(rd, ray, x, n);
+    trace_ray(T, x, n, vis);
+}
+
+__global__ void k_rays(RayDesc rd, double *starts, double *dirs) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rd.R) return;
+    V3 x, n;
+    ray_of(rd, (int32_t)r, x, n);
+    if (starts) {
+        starts[3 * r + 0] = x.x;
+        starts[3 * r + 1] = x.y;
+        starts[3 * r + 2] = x.z;
+    }
+    if (dirs) {
+        dirs[3 * r + 0] = n.x;
+        dirs[3 * r + 1] = n.y;
+        dirs[3 * r + 2] = n.z;
+    }
+}
+
+inline unsigned grid_of(int64_t n_slots) { return (unsigned)((n_slots + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
+                        unsigned long long *total, int *maxcnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_count, dim3(grid_of(rd.n_slots)), dim3(256), T.n_tab * sizeof(double),
+                       st, T, tab, rd, cnt_nat, total, maxcnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
+                       const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                       const int32_t *slice_len, int32_t *vox, float *len, int *err,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(grid_of(rd.n_slots)), dim3(256), T.n_tab * sizeof(double), st,
+                       T, tab, rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
+                              const float *rho, int B, int64_t V, float *y, hipStream_t st) {
+    const size_t sh = T.n_tab * sizeof(double);
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *r = rho + (int64_t)b0 * V;
+        float *yy = y + (int64_t)b0 * rd.R;
+        if (nb == 1)
+            hipLaunchKernelGGL(k_otf_forward<1>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, r, nb, V, yy);
+        else if (nb == 2)
+            hipLaunchKernelGGL(k_otf_forward<2>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, r, nb, V, yy);
+        else
+            hipLaunchKernelGGL(k_otf_forward<4>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, r, nb, V, yy);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
+                              const float *y, int B, int64_t V, float *x, hipStream_t st) {
+    const size_t sh = T.n_tab * sizeof(double);
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *yy = y + (int64_t)b0 * rd.R;
+        float *xx = x + (int64_t)b0 * V;
+        if (nb == 1)
+            hipLaunchKernelGGL(k_otf_adjoint<1>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, yy, nb, V, xx);
+        else if (nb == 2)
+            hipLaunchKernelGGL(k_otf_adjoint<2>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, yy, nb, V, xx);
+        else
+            hipLaunchKernelGGL(k_otf_adjoint<4>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
+                               tab, rd, yy, nb, V, xx);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st) {
+    hipLaunchKernelGGL(k_rays, dim3((unsigned)((rd.R + 255) / 256)), dim3(256), 0, st, rd, starts,
+                       dirs);
+    return hipGetLastError();
+}
+
+}  // namespace tsp

@@ -1,0 +1,378 @@
+// Per-ray core of the spherical-grid tracer (see tsp_trace.hip for the
+// method).  Functions are host+device so that the identical code can also be
+// exercised in a CPU build; the library itself runs them only on the GPU.
+#pragma once
+
+#include <cmath>
+
+#include "tsp_internal.h"
+
+#define TSP_HD __host__ __device__ inline
+
+namespace tsp {
+namespace core {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kPi = 3.14159265358979323846264338327950;
+
+struct V3 {
+    double x, y, z;
+};
+
+struct Tab {
+    const double *rb, *ce, *ca, *sa, *ab;
+    double ab0;
+    int nr, ne, na, np, cyclic;
+};
+
+TSP_HD Tab make_tab(const TabDesc &D, const double *lds) {
+    Tab T;
+    T.rb = lds + D.off_rb;
+    T.ce = lds + D.off_ce;
+    T.ca = lds + D.off_ca;
+    T.sa = lds + D.off_sa;
+    T.ab = lds + D.off_ab;
+    T.ab0 = D.ab0;
+    T.nr = D.nr;
+    T.ne = D.ne;
+    T.na = D.na;
+    T.np = D.np;
+    T.cyclic = D.cyclic;
+    return T;
+}
+
+__device__ __forceinline__ void stage_tables(const TabDesc &D, const double *tab, double *lds) {
+    for (int k = threadIdx.x; k < D.n_tab; k += blockDim.x) lds[k] = tab[k];
+    __syncthreads();
+}
+
+// number of a[k] <= v in an increasing array of length m
+TSP_HD int count_le(const double *a, int m, double v) {
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] <= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// number of a[k] >= v in a decreasing array of length m
+TSP_HD int count_ge_dec(const double *a, int m, double v) {
+    int lo = 0, hi = m;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (a[mid] >= v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Elevation region of a point with cos(colatitude) = u: e_b[ie] <= theta < e_b[ie+1]
+// (-1 or ne outside a wedge; a point at theta = pi belongs to the last bin when
+// e_b ends at pi).
+TSP_HD int class_e(const Tab &T, double u) {
+    u = fmin(fmax(u, -1.0), 1.0);
+    int ie = count_ge_dec(T.ce, T.ne + 1, u) - 1;
+    if (ie == T.ne && T.ce[T.ne] <= -1.0) ie = T.ne - 1;
+    return ie;
+}
+
+// Azimuth region of (px, py) measured from a_b[0] in [0, 2 pi); the region
+// past the last boundary is 0 on a cyclic grid, else the outside region na.
+TSP_HD int class_a(const Tab &T, double px, double py, double *phi) {
+    double p0 = atan2(py, px);
+    *phi = p0;
+    double ph = fmod(p0 - T.ab0, kTwoPi);
+    if (ph < 0) ph += kTwoPi;
+    if (ph >= kTwoPi) ph -= kTwoPi;
+    int ia = count_le(T.ab, T.na + 1, ph) - 1;
+    if (ia >= T.na) ia = T.cyclic ? 0 : T.na;
+    return ia;
+}
+
+// Root of cone k's quadratic that lies on the current monotone run of the
+// colatitude.  u_incr: cos(theta) increases across the crossing (Eq. 12
+// "negative").  Roots on the other nappe (z c < 0) and roots where m.n has
+// the wrong sign belong elsewhere.  Falls back to `fb` when rounding leaves
+// no admissible root (a grazing crossing at the run's turning point).
+TSP_HD double cone_root(const Tab &T, int k, bool u_incr, const V3 &x,
+                                            const V3 &n, double xx, double xn, double lo,
+                                            double hi, double fb) {
+    const double c = T.ce[k];
+    double t = fb;
+    if (fabs(c) < 1e-12) {  // the plane z = 0
+        if (n.z != 0.0) t = -x.z / n.z;
+    } else {
+        const double c2 = c * c;
+        const double A = n.z * n.z - c2;
+        const double B = x.z * n.z - c2 * xn;
+        const double C = x.z * x.z - c2 * xx;
+        const double disc = B * B - A * C;
+        if (disc >= 0.0) {
+            const double s = sqrt(disc);
+            const double q = -(B + copysign(s, B));
+            double r[2];
+            r[0] = (A != 0.0) ? q / A : INFINITY;
+            r[1] = (q != 0.0) ? C / q : ((A != 0.0) ? -B / A : INFINITY);
+            double best = INFINITY, bestd = INFINITY;
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                const double tr = r[i];
+                if (!(fabs(tr) < INFINITY)) continue;
+                const double pz = x.z + n.z * tr;
+                if (pz * c < 0.0) continue;  // other nappe
+                const double px = x.x + n.x * tr, py = x.y + n.y * tr;
+                const double pp = px * px + py * py + pz * pz;
+                const double pn = xn + tr;
+                const double dudt = n.z * pp - pz * pn;  // Eq. 12: m . n
+                if (u_incr ? (dudt < 0.0) : (dudt > 0.0)) continue;
+                const double d = (tr < lo) ? lo - tr : ((tr > hi) ? tr - hi : 0.0);
+                if (d < bestd) {
+                    bestd = d;
+                    best = tr;
+                }
+            }
+            if (bestd < INFINITY) t = best;
+        }
+    }
+    return fmin(fmax(t, lo), hi);
+}
+
+TSP_HD double plane_t(const Tab &T, int k, const V3 &x, const V3 &n,
+                                          double lo) {
+    const double xm = -x.x * T.sa[k] + x.y * T.ca[k];
+    const double nm = -n.x * T.sa[k] + n.y * T.ca[k];
+    return (nm != 0.0) ? -xm / nm : lo;
+}
+
+// Walk one ray; calls vis.seg(voxel, length) once per canonical segment in
+// increasing distance.
+template <class Vis>
+TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
+    const int nr = T.nr, ne = T.ne, na = T.na, np = T.np;
+    const double xx = x.x * x.x + x.y * x.y + x.z * x.z;
+    const double xn = x.x * n.x + x.y * n.y + x.z * n.z;
+    const double cx = x.y * n.z - x.z * n.y;
+    const double cy = x.z * n.x - x.x * n.z;
+    const double cz = x.x * n.y - x.y * n.x;  // (x cross n)_z, constant along the ray
+    const double b2 = cx * cx + cy * cy + cz * cz;
+    const double Ro = T.rb[nr];
+    const double tc = -xn;
+    if (!(tc > 0.0) || !(b2 < Ro * Ro)) return;  // moving away, or misses the grid
+    const double b = sqrt(b2);
+    const double hch = sqrt((Ro - b) * (Ro + b));
+    const double tin = tc - hch, tout = tc + hch;
+
+    // ---------------- radial stream (Eq. 11)
+    const int kb = count_le(T.rb, nr + 1, b);  // shells kb..nr-1 are crossed twice
+    int ir = nr - 1;
+    int rk = nr - 1;
+    int rstage;  // 0 inbound, 1 outbound, 2 next event is the exit at tout
+    double t_r;
+    if (kb <= nr - 1) {
+        rstage = 0;
+        t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+    } else {
+        rstage = 2;
+        t_r = tout;
+    }
+
+    // ---------------- classification at entry and exit of the outer sphere
+    const V3 pin = {x.x + n.x * tin, x.y + n.y * tin, x.z + n.z * tin};
+    const V3 pout = {x.x + n.x * tout, x.y + n.y * tout, x.z + n.z * tout};
+    const double rin = sqrt(pin.x * pin.x + pin.y * pin.y + pin.z * pin.z);
+    const double rout = sqrt(pout.x * pout.x + pout.y * pout.y + pout.z * pout.z);
+    int ie = class_e(T, pin.z / rin);
+    const int ie_out = class_e(T, pout.z / rout);
+    double phi_in, phi_out;
+    int ia = class_a(T, pin.x, pin.y, &phi_in);
+    const int ia_out = class_a(T, pout.x, pout.y, &phi_out);
+
+    // ---------------- elevation stream (Eq. 12)
+    // estage: 0 first run, 1 second run, 3 jump pending at tc (ray through the
+    // origin: the colatitude jumps from theta to pi - theta), 2 done.
+    int estage = 0, etgt;
+    double elo = tin, ehi = tout, ts = 0.0;
+    bool two = false;
+    if (b2 == 0.0) {
+        etgt = ie;
+        estage = (ie_out != ie) ? 3 : 2;
+    } else {
+        const double den = n.z * xn - x.z;
+        const double num = x.z * xn - n.z * xx;
+        if (den != 0.0) {
+            ts = num / den;
+            two = (ts > tin) && (ts < tout);
+        }
+        if (two) {
+            const V3 ps = {x.x + n.x * ts, x.y + n.y * ts, x.z + n.z * ts};
+            const double rs = sqrt(ps.x * ps.x + ps.y * ps.y + ps.z * ps.z);
+            etgt = class_e(T, ps.z / rs);
+            ehi = ts;
+        } else {
+            etgt = ie_out;
+        }
+    }
+    double t_e = INFINITY;
+    double elast = tin;
+    // compute the next elevation event (or INFINITY)
+    auto next_e = [&]() {
+        for (;;) {
+            if (estage == 0 || estage == 1) {
+                if (ie != etgt) {
+                    const bool down = etgt < ie;  // colatitude decreasing, cos increasing
+                    const int k = down ? ie : ie + 1;
+                    const double lo = fmax(elo, elast);
+                    const double fb = two ? ts : fmin(fmax(elo, lo), ehi);
+                    t_e = cone_root(T, k, down, x, n, xx, xn, lo, ehi, fb);
+                    return;
+                }
+                if (estage == 0 && two) {
+                    estage = 1;
+                    elo = ts;
+                    ehi = tout;
+                    etgt = ie_out;
+                    continue;
+                }
+                estage = 2;
+            }
+            if (estage == 3) {
+                t_e = tc;
+                return;
+            }
+            t_e = INFINITY;
+            return;
+        }
+    };
+    next_e();
+
+    // ---------------- azimuth stream (Eq. 13)
+    int aleft = 0, adir = 0;
+    bool ajump = false;
+    double t_a = INFINITY;
+    double alast = tin;
+    if (cz != 0.0) {
+        adir = (cz > 0.0) ? 1 : -1;
+        int cnt = (adir > 0) ? (ia_out - ia + np) % np : (ia - ia_out + np) % np;
+        double dph = (adir > 0) ? phi_out - phi_in : phi_in - phi_out;
+        dph = fmod(dph, kTwoPi);
+        if (dph < 0) dph += kTwoPi;
+        if (dph > kPi) {
+            cnt = 0;  // the sweep is tiny and rounding reversed it
+        } else if (cnt == 0 && dph > 0.0) {
+            // Same region at both ends.  A region wider than pi can be left
+            // and re-entered the other way round: then every plane is crossed.
+            double rel = fmod(phi_in - T.ab0, kTwoPi);
+            if (rel < 0) rel += kTwoPi;
+            const double edge = (adir > 0) ? ((ia + 1 <= na) ? T.ab[ia + 1] : kTwoPi) : T.ab[ia];
+            const double dist = (adir > 0) ? edge - rel : rel - edge;
+            if (dph > dist) cnt = np;
+        }
+        aleft = cnt;
+    } else {
+        const double nxy2 = n.x * n.x + n.y * n.y;
+        if (nxy2 > 0.0) {  // the xy-projection passes through the axis: azimuth jumps by pi
+            const double tax = -(x.x * n.x + x.y * n.y) / nxy2;
+            if (tax > tin && tax < tout && ia_out != ia) {
+                ajump = true;
+                t_a = tax;
+            }
+        }
+    }
+    auto next_a = [&]() {
+        if (aleft > 0) {
+            const int k = (adir > 0) ? ((ia + 1) % np) : ia;
+            const double lo = fmax(alast, tin);
+            t_a = fmin(fmax(plane_t(T, k, x, n, lo), lo), tout);
+        } else if (!ajump) {
+            t_a = INFINITY;
+        }
+    };
+    next_a();
+
+    // ---------------- merge
+    double tcur = tin;
+    int pv = -1;
+    double plen = 0.0;
+    bool gap = false;
+    for (;;) {
+        double tm = t_r;
+        int fam = 0;
+        if (t_e < tm) {
+            tm = t_e;
+            fam = 1;
+        }
+        if (t_a < tm) {
+            tm = t_a;
+            fam = 2;
+        }
+        if (tm > tcur) {
+            const bool valid = (ir >= 0) && (ir < nr) && (ie >= 0) && (ie < ne) && (ia >= 0) &&
+                               (ia < na);
+            if (valid) {
+                const int v = (ir * ne + ie) * na + ia;
+                if (v == pv && !gap) {
+                    plen += tm - tcur;
+                } else {
+                    if (pv >= 0) vis.seg(pv, plen);
+                    pv = v;
+                    plen = tm - tcur;
+                }
+                gap = false;
+            } else {
+                gap = true;
+            }
+            tcur = tm;
+        }
+        if (fam == 0) {
+            if (rstage == 2) break;
+            if (rstage == 0) {
+                ir = rk - 1;
+                if (rk > kb) {
+                    rk--;
+                    t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                } else {
+                    rstage = 1;
+                    t_r = tc + sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                }
+            } else {
+                ir = rk;
+                rk++;
+                if (rk <= nr - 1) {
+                    t_r = tc + sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                } else {
+                    rstage = 2;
+                    t_r = tout;
+                }
+            }
+        } else if (fam == 1) {
+            if (estage == 3) {
+                ie = ie_out;
+                estage = 2;
+            } else {
+                ie = (etgt < ie) ? ie - 1 : ie + 1;
+            }
+            elast = t_e;
+            next_e();
+        } else {
+            if (ajump) {
+                ia = ia_out;
+                ajump = false;
+                t_a = INFINITY;
+            } else {
+                ia = (adir > 0) ? (ia + 1) % np : (ia - 1 + np) % np;
+                aleft--;
+                alast = t_a;
+                next_a();
+            }
+        }
+    }
+    if (pv >= 0) vis.seg(pv, plen);
+}
+
+// ---------------------------------------------------------------- rays
+
+
+}  // namespace core
+}  // namespace tsp

@@ -1,0 +1,184 @@
+"""Python face of the projector: geometry, forward, adjoint, autograd.
+
+The HIP library does all the work; this layer converts arrays, picks the
+stream and shapes outputs.  PyTorch is used only for device memory and
+streams.
+
+    P = Projector(grid, views)                  # steps 1-3 precomputed (TomoSphero Sec. 3, 4.4)
+    y = P.forward(rho)                          # Eq. 5, rho: (B, Nr, Ne, Na) float32 on cuda
+    x = P.backproject(y)                        # adjoint, deterministic by default
+    y = ProjectorFn.apply(rho, P)               # differentiable: backward = adjoint
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native as N
+
+MODES = {"csr": N.TSP_MODE_CSR, "onthefly": N.TSP_MODE_ONTHEFLY}
+ADJ = {"deterministic": N.TSP_ADJ_DETERMINISTIC, "atomic": N.TSP_ADJ_ATOMIC}
+
+
+def _grid_arrays(grid):
+    if hasattr(grid, "arrays"):
+        return tuple(np.ascontiguousarray(a, np.float64) for a in grid.arrays())
+    return tuple(np.ascontiguousarray(a, np.float64) for a in grid)
+
+
+class Projector:
+    """Spherical-grid line-integral projector y = F rho on one GPU.
+
+    grid   Grid (or (r_b, e_b, a_b))
+    views  ConeViews (cone beam, detector at the vertex), or
+    rays   (starts, dirs) explicit rays (float64 (R, 3) each)
+    mode   "csr" (precomputed segment lists) or "onthefly" (recomputed per call)
+    csc    build the voxel-major store for the deterministic adjoint (csr mode)
+    """
+
+    def __init__(self, grid, views=None, rays=None, mode="csr", csc=True, device=None):
+        if (views is None) == (rays is None):
+            raise ValueError("give either views or rays")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        rb, eb, ab = _grid_arrays(grid)
+        self.shape = (len(rb) - 1, len(eb) - 1, len(ab) - 1)
+        self._keep = (rb, eb, ab)
+        gd = N.tsp_grid_desc(self.shape[0], self.shape[1], self.shape[2],
+                             rb.ctypes.data_as(N._dp), eb.ctypes.data_as(N._dp),
+                             ab.ctypes.data_as(N._dp))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            if views is not None:
+                V = views.pos.shape[0]
+                arr = (N.tsp_cone_view * V)()
+                for v in range(V):
+                    arr[v].pos[:] = [float(a) for a in views.pos[v]]
+                    arr[v].look[:] = [float(a) for a in views.look[v]]
+                    arr[v].up[:] = [float(a) for a in views.up[v]]
+                    arr[v].fov_deg[:] = [float(a) for a in views.fov_deg[v]]
+                    arr[v].shape[:] = [int(views.H), int(views.W)]
+                N.check(N.lib.tsp_geometry_create(ctypes.byref(gd), arr, V, None, None, 0,
+                                                  ctypes.byref(handle)))
+                self.out_shape = (V, int(views.H), int(views.W))
+            else:
+                s = np.ascontiguousarray(rays[0], np.float64).reshape(-1, 3)
+                d = np.ascontiguousarray(rays[1], np.float64).reshape(-1, 3)
+                if s.shape != d.shape:
+                    raise ValueError("starts and dirs must have the same shape")
+                N.check(N.lib.tsp_geometry_create(ctypes.byref(gd), None, 0,
+                                                  s.ctypes.data_as(N._dp),
+                                                  d.ctypes.data_as(N._dp), s.shape[0],
+                                                  ctypes.byref(handle)))
+                self.out_shape = (s.shape[0],)
+        self._h = handle
+        self.mode = mode
+        self.retrace(mode, csc)
+
+    # ------------------------------------------------------------------ state
+    def retrace(self, mode="csr", csc=True):
+        m = MODES[mode] | (0 if csc or mode != "csr" else N.TSP_TRACE_NO_CSC)
+        with torch.cuda.device(self.device):
+            N.check(N.lib.tsp_trace(self._h, m, N.stream_handle()))
+        self.mode = mode
+
+    def info(self):
+        inf = N.tsp_info()
+        N.check(N.lib.tsp_query(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in N.tsp_info._fields_}
+
+    @property
+    def n_rays(self):
+        return int(np.prod(self.out_shape))
+
+    @property
+    def n_voxels(self):
+        return int(np.prod(self.shape))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.lib.tsp_geometry_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 (interpreter shutdown)
+            pass
+
+    # ------------------------------------------------------------------ checks
+    def _dev_f32(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device != self.device:
+            raise ValueError(f"{name} must be a torch tensor on {self.device}")
+        if t.dtype != torch.float32:
+            raise ValueError(f"{name} must be float32")
+        return t.contiguous()
+
+    # ------------------------------------------------------------------ compute
+    def forward(self, rho, out=None):
+        """y = F rho.  rho: (..., Nr, Ne, Na) float32 on the projector's GPU.
+        Returns (..., *out_shape) float32."""
+        rho = self._dev_f32(rho, "rho")
+        if tuple(rho.shape[-3:]) != self.shape:
+            raise ValueError(f"rho must end in {self.shape}, got {tuple(rho.shape)}")
+        lead = rho.shape[:-3]
+        B = int(np.prod(lead)) if lead else 1
+        y = out if out is not None else torch.empty((*lead, *self.out_shape),
+                                                    dtype=torch.float32, device=self.device)
+        if B:
+            N.check(N.lib.tsp_forward(self._h, N.ptr(rho), B, N.ptr(y), N.stream_handle()))
+        return y
+
+    def backproject(self, y, method="deterministic", out=None):
+        """x = F^T y.  y: (..., *out_shape) float32.  method: deterministic | atomic."""
+        y = self._dev_f32(y, "y")
+        k = len(self.out_shape)
+        if tuple(y.shape[y.dim() - k:]) != self.out_shape:
+            raise ValueError(f"y must end in {self.out_shape}, got {tuple(y.shape)}")
+        lead = y.shape[:y.dim() - k]
+        B = int(np.prod(lead)) if lead else 1
+        x = out if out is not None else torch.empty((*lead, *self.shape), dtype=torch.float32,
+                                                    device=self.device)
+        if self.mode == "onthefly":
+            method = "atomic"
+        if B:
+            N.check(N.lib.tsp_backproject(self._h, N.ptr(y), B, N.ptr(x), ADJ[method],
+                                          N.stream_handle()))
+        return x
+
+    __call__ = forward
+
+    def segments(self):
+        """Canonical per-ray segment lists (Sec. 4.4 .regs/.lens) as CSR:
+        row_ptr int64 (R+1), vox int32 (S), len float32 (S)."""
+        inf = self.info()
+        S = inf["n_segments"]
+        rp = torch.empty(self.n_rays + 1, dtype=torch.int64, device=self.device)
+        vox = torch.empty(max(S, 1), dtype=torch.int32, device=self.device)
+        ln = torch.empty(max(S, 1), dtype=torch.float32, device=self.device)
+        N.check(N.lib.tsp_segments(self._h, N.ptr(rp), N.ptr(vox), N.ptr(ln), N.stream_handle()))
+        return rp, vox[:S], ln[:S]
+
+    def rays(self):
+        """(starts, unit dirs) float64 (R, 3) as traced by the kernels."""
+        s = torch.empty((self.n_rays, 3), dtype=torch.float64, device=self.device)
+        d = torch.empty((self.n_rays, 3), dtype=torch.float64, device=self.device)
+        N.check(N.lib.tsp_rays(self._h, N.ptr(s), N.ptr(d), N.stream_handle()))
+        return s, d
+
+
+class ProjectorFn(torch.autograd.Function):
+    """Differentiable y = F rho.  F is linear, so the gradient with respect
+    to rho is F^T grad_y, computed by the hand-written adjoint kernel; autograd
+    never sees the ray tracer."""
+
+    @staticmethod
+    def forward(ctx, rho, proj, method="deterministic"):
+        ctx.proj = proj
+        ctx.method = method
+        return proj.forward(rho)
+
+    @staticmethod
+    def backward(ctx, gy):
+        gx = ctx.proj.backproject(gy.contiguous(), method=ctx.method)
+        return gx, None, None

@@ -1,0 +1,243 @@
+"""GPU parity of the HIP projector against the CPU FP64 oracle.
+
+Bars (stated once here, used throughout):
+  - rays: start and unit direction within 1e-13 (both sides build them in FP64);
+  - segment lists: per-ray counts and voxel indices bit-exact for every ray the
+    oracle does not flag as a tie (boundary events within 1e-9 r_max, grazing
+    roots); lengths within 2^-23 relative (FP32 storage of an FP64 length);
+  - projections: |y_gpu - y_ora| <= 1e-5 sum_k |rho_vk| len_k + 1e-7
+    (rel 1e-5 in FP32, measured against the absolute integrand so that small
+    negative noise in rho does not blow up the ratio);
+  - adjoint: |x_gpu - x_ora| <= 1e-5 sum_k |y_ray_k| len_k + 1e-7 per voxel;
+  - the deterministic adjoint is bitwise identical across runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2608_16960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FWD_RTOL = 1e-5
+LEN_RTOL = 2.0 ** -23
+
+
+def _P():
+    from paper_2608_16960_amd.projector import Projector
+    return Projector
+
+
+def _oracle_rays(ora, views):
+    return ora.cone_rays(views.pos, views.look, views.up, views.fov_deg, views.H, views.W)
+
+
+def _abs_integrand(tr, a, R):
+    """sum_k |a_{vox_k}| len_k per ray (a: (V,))."""
+    out = np.zeros(R)
+    seg_ray = np.repeat(np.arange(R), tr["counts"])
+    np.add.at(out, seg_ray, np.abs(a[tr["vox"]]) * tr["len"])
+    return out
+
+
+def _abs_adjoint(tr, y, V):
+    out = np.zeros(V)
+    R = len(tr["counts"])
+    seg_ray = np.repeat(np.arange(R), tr["counts"])
+    np.add.at(out, tr["vox"], np.abs(y[seg_ray]) * tr["len"])
+    return out
+
+
+def _compare_segments(tr, P):
+    rp, vox, ln = (t.cpu().numpy() for t in P.segments())
+    R = len(tr["counts"])
+    cg = np.diff(rp)
+    ok = ~tr["tie"]
+    assert ok.mean() > 0.99, f"too many tie rays: {1 - ok.mean():.4f}"
+    bad = np.nonzero(cg[ok] != tr["counts"][ok])[0]
+    assert bad.size == 0, f"count mismatch on {bad.size} rays, first ray {np.nonzero(ok)[0][bad[0]]}"
+    mo = ok[np.repeat(np.arange(R), tr["counts"])]
+    mg = ok[np.repeat(np.arange(R), cg)]
+    assert np.array_equal(vox[mg], tr["vox"][mo])
+    lo = tr["len"][mo]
+    assert np.all(np.abs(ln[mg] - lo) <= LEN_RTOL * lo + 1e-9)
+    # tie rays: total length still agrees
+    tot_g = np.add.reduceat(ln, rp[:-1]) if ln.size else np.zeros(R)
+    tot_g = np.where(cg > 0, tot_g, 0.0)
+    tot_o = np.zeros(R)
+    np.add.at(tot_o, np.repeat(np.arange(R), tr["counts"]), tr["len"])
+    assert np.all(np.abs(tot_g - tot_o) <= 1e-5 * tot_o + 1e-6)
+    return ok
+
+
+def _check_all(ora, grid, P, starts, dirs, rho, B_y_seed=7):
+    """Full element-wise parity for a small geometry (every ray, every voxel)."""
+    dev = P.device
+    tr = ora.trace(grid.arrays() if hasattr(grid, "arrays") else grid, starts, dirs)
+    # rays
+    s_g, d_g = (t.cpu().numpy() for t in P.rays())
+    assert np.max(np.abs(s_g - starts)) < 1e-13
+    assert np.max(np.abs(d_g - dirs / np.linalg.norm(dirs, axis=1, keepdims=True))) < 1e-13
+    info = P.info()
+    assert info["n_segments"] == int(tr["counts"].sum()) or np.any(tr["tie"])
+    if P.mode == "csr":
+        _compare_segments(tr, P)
+    # forward, batch of 2
+    B = rho.shape[0]
+    rho_t = torch.from_numpy(np.ascontiguousarray(rho, np.float32)).to(dev)
+    y = P.forward(rho_t).reshape(B, -1).cpu().numpy().astype(np.float64)
+    R = y.shape[1]
+    V = int(np.prod(rho.shape[1:]))
+    yo = ora.forward(tr, rho.reshape(B, V).astype(np.float64))
+    for b in range(B):
+        tol = FWD_RTOL * _abs_integrand(tr, rho[b].reshape(-1).astype(np.float64), R) + 1e-7
+        err = np.abs(y[b] - yo[b])
+        assert np.all(err <= tol), f"forward b={b}: worst ray {np.argmax(err - tol)}"
+    # adjoints
+    rng = np.random.default_rng(B_y_seed)
+    yy = rng.normal(size=(B, R)).astype(np.float32)
+    y_t = torch.from_numpy(yy).to(dev).reshape(B, *P.out_shape)
+    xo = ora.adjoint(tr, yy.astype(np.float64), V)
+    methods = ["deterministic", "atomic"] if P.mode == "csr" else ["atomic"]
+    for m in methods:
+        x = P.backproject(y_t, method=m).reshape(B, V).cpu().numpy().astype(np.float64)
+        for b in range(B):
+            tol = FWD_RTOL * _abs_adjoint(tr, yy[b].astype(np.float64), V) + 1e-7
+            err = np.abs(x[b] - xo[b])
+            assert np.all(err <= tol), f"adjoint {m} b={b}: worst voxel {np.argmax(err - tol)}"
+    if P.mode == "csr":
+        x1 = P.backproject(y_t, method="deterministic")
+        x2 = P.backproject(y_t, method="deterministic")
+        assert torch.equal(x1, x2)
+    return tr
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda", 0)
+
+
+@pytest.mark.parametrize("mode", ["csr", "onthefly"])
+def test_tiny_workload(ora, dev, mode):
+    """Tiny: 20 log shells x 10 x 12, 4 views 32x32, rho = exp + noise (and a
+    second, unrelated object in the same batch)."""
+    w = W.tiny()
+    s, d = _oracle_rays(ora, w.views)
+    P = _P()(w.grid, views=w.views, mode=mode)
+    rho = np.concatenate([w.rho, np.random.default_rng(4).uniform(-1, 2, (1, *w.grid.shape))])
+    _check_all(ora, w.grid, P, s, d, rho.astype(np.float32))
+
+
+@pytest.mark.parametrize("mode", ["csr", "onthefly"])
+def test_ragged_wedge_grid(ora, dev, mode):
+    """Detector 37x29 (ragged 16x16 windows), 3 views, non-uniform wedge grid."""
+    g = W.Grid(np.array([2.0, 2.7, 3.1, 4.4, 6.0, 9.5]), np.array([0.3, 0.8, 1.2, 1.5708, 2.0, 2.9]),
+               np.array([-0.4, 0.3, 1.0, 1.9, 2.2, 3.0, 4.1]))
+    pos = np.array([[20.0, 3.0, 5.0], [-4.0, 18.0, -7.0], [2.0, -3.0, 22.0]])
+    v = W.views_at(pos, (45.0, 38.0), 37, 29, look=[0.5, -0.2, 0.1])
+    s, d = _oracle_rays(ora, v)
+    P = _P()(g, views=v, mode=mode)
+    rho = np.random.default_rng(9).uniform(0, 1, (3, *g.shape)).astype(np.float32)
+    _check_all(ora, g, P, s, d, rho)
+
+
+def test_explicit_rays_with_degenerate_lines(ora, dev):
+    """Explicit (Listing 4 style, un-normalised) rays plus hand-picked degenerate
+    lines: in the equatorial plane, in an azimuth half-plane, along the polar
+    axis, exactly through the origin, through the inner hole."""
+    g = W.uniform_grid((6, 8, 12), r=(1.0, 5.0))
+    rng = np.random.default_rng(21)
+    s, d = W.random_rays(3000, rng, r_start=(8.0, 20.0), aim=4.0)
+    extra_s = np.array([[-9.0, 0.3, 0.0], [-9.0, 0.0, 0.7], [0.0, 0.0, 9.0], [6.0, 6.0, 6.0],
+                        [9.0, 0.5, 0.2], [0.0, -9.0, 2.0], [7.0, 0.0, 0.0]])
+    extra_d = np.array([[1.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, -2.0], [-1.0, -1.0, -1.0],
+                        [-1.0, 0.0, 0.0], [0.0, 1.0, -0.2], [-1.0, 0.0, 0.0]])
+    s = np.concatenate([s, extra_s])
+    d = np.concatenate([d, extra_d])
+    P = _P()(g, rays=(s, d))
+    rho = rng.uniform(-0.5, 1.5, (1, *g.shape)).astype(np.float32)
+    _check_all(ora, g, P, s, d, rho)
+
+
+def test_unit_sphere_fp32(dev):
+    """Unit sphere on (50,50,50), rho = 1: y = 2 sqrt(1 - b^2) (Sec. 5.1, Fig. 11)."""
+    g = W.uniform_grid((50, 50, 50), r=(0.0, 1.0))
+    v = W.views_at([[3.0, 0.0, 0.0], [0.0, -2.0, 1.5]], (50.0, 50.0), 41, 41)
+    P = _P()(g, views=v)
+    y = P.forward(torch.ones(g.shape, device=dev)).cpu().numpy().reshape(-1).astype(np.float64)
+    s, d = (t.cpu().numpy() for t in P.rays())
+    b2 = np.sum(np.cross(s, d) ** 2, 1)
+    ref = 2 * np.sqrt(np.maximum(1 - b2, 0))
+    hit = ref > 1e-2
+    assert np.max(np.abs(y - ref)[hit] / ref[hit]) < 1e-6
+    assert np.all(np.abs(y[~hit] - ref[~hit]) < 1e-5)
+
+
+def test_medium_full_size(ora, dev):
+    """Medium workload (50^3, 30 views 256x256) at full size in the configuration
+    the benchmark times: sampled rays against the oracle, adjoint by the
+    adjoint identity and by columns of F, deterministic vs atomic."""
+    w = W.medium()
+    P = _P()(w.grid, views=w.views)
+    info = P.info()
+    R, V = info["n_rays"], info["n_voxels"]
+    s, d = _oracle_rays(ora, w.views)
+    rng = np.random.default_rng(12)
+    idx = np.sort(rng.choice(R, 6000, replace=False))
+    tr = ora.trace(w.grid.arrays(), s[idx], d[idx])
+    rho = torch.from_numpy(w.rho).to(dev)
+    y = P.forward(rho).reshape(-1).cpu().numpy().astype(np.float64)
+    yo = ora.forward(tr, w.rho[0].astype(np.float64))
+    tol = FWD_RTOL * _abs_integrand(tr, w.rho[0].reshape(-1).astype(np.float64), len(idx)) + 1e-7
+    assert np.all(np.abs(y[idx] - yo) <= tol)
+    # sampled segment lists
+    rp, vox, ln = (t.cpu().numpy() for t in P.segments())
+    assert rp[-1] == info["n_segments"]
+    ok = ~tr["tie"]
+    for k in np.nonzero(ok)[0][:2000]:
+        i = idx[k]
+        a, b = rp[i], rp[i + 1]
+        o0, o1 = tr["row_ptr"][k], tr["row_ptr"][k + 1]
+        assert np.array_equal(vox[a:b], tr["vox"][o0:o1]), i
+        assert np.all(np.abs(ln[a:b] - tr["len"][o0:o1]) <= LEN_RTOL * tr["len"][o0:o1] + 1e-9)
+    # adjoint identity <F x, y> = <x, F^T y> on random x, y (FP64 sums on the host)
+    xr = torch.rand((1, *w.grid.shape), device=dev)
+    yr = torch.rand((1, *P.out_shape), device=dev)
+    Fx = P.forward(xr).double()
+    FTy_d = P.backproject(yr, "deterministic").double()
+    FTy_a = P.backproject(yr, "atomic").double()
+    lhs = float((Fx * yr.double()).sum())
+    for FTy in (FTy_d, FTy_a):
+        rhs = float((xr.double() * FTy).sum())
+        assert abs(lhs - rhs) <= 1e-5 * abs(lhs)
+    # columns of F: (F^T y)_v = <F e_v, y> for sampled voxels
+    for v in rng.choice(V, 8, replace=False):
+        e = torch.zeros(V, device=dev)
+        e[v] = 1.0
+        col = P.forward(e.reshape(1, *w.grid.shape)).double()
+        ref = float((col * yr.double()).sum())
+        got = float(FTy_d.reshape(-1)[v])
+        scale = float((col.abs() * yr.double().abs()).sum())
+        assert abs(got - ref) <= 1e-5 * scale + 1e-7
+    # deterministic vs atomic
+    assert torch.allclose(FTy_d, FTy_a, rtol=1e-5, atol=1e-5 * float(FTy_d.abs().max()))
+    x1 = P.backproject(yr, "deterministic")
+    x2 = P.backproject(yr, "deterministic")
+    assert torch.equal(x1, x2)
+
+
+def test_onthefly_matches_csr_medium(dev):
+    """On-the-fly forward/adjoint equal the stored-list path at full Medium size."""
+    w = W.medium()
+    Pc = _P()(w.grid, views=w.views, csc=False)
+    Po = _P()(w.grid, views=w.views, mode="onthefly")
+    assert Pc.info()["n_segments"] == Po.info()["n_segments"]
+    rho = torch.from_numpy(np.concatenate([w.rho, w.rho * 0.5 + 0.1])).to(dev)
+    yc = Pc.forward(rho)
+    yo = Po.forward(rho)
+    assert torch.allclose(yc, yo, rtol=1e-5, atol=1e-6)
+    yr = torch.rand((2, *Pc.out_shape), device=dev)
+    xc = Pc.backproject(yr, "atomic")
+    xo = Po.backproject(yr, "atomic")
+    assert torch.allclose(xc, xo, rtol=1e-4, atol=1e-5 * float(xc.abs().max()))
