@@ -89,7 +89,9 @@ def trace(grid, starts, dirs):
 
     Returns a dict with row_ptr (R+1,) int64, vox (S,) int32 linear index
     (ir*Ne + ie)*Na + ia, len (S,) float64, t0 (S,) float64 segment start
-    distance, tie (R,) bool, counts (R,) int32.
+    distance, tie (R,) bool (index list not decided robustly in FP64),
+    sensitive (R,) bool (lengths ill-conditioned beyond FP32 rounding; implied
+    by tie), counts (R,) int32.
     """
     lib = load_library()
     keep, gargs = _grid_args(grid)
@@ -112,8 +114,8 @@ def trace(grid, starts, dirs):
     if err:
         raise RuntimeError(f"oracle fill failed ({err})")
     del keep
-    return dict(row_ptr=row_ptr, vox=vox[:S], len=ln[:S], t0=t0[:S], tie=ties.astype(bool),
-                counts=counts)
+    return dict(row_ptr=row_ptr, vox=vox[:S], len=ln[:S], t0=t0[:S], tie=(ties & 1) > 0,
+                sensitive=(ties & 2) > 0, counts=counts)
 
 
 def forward(tr, rho):

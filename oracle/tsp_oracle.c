@@ -49,7 +49,12 @@
  * the grid's outer sphere closer than 1e-9 * r_max, a grazing sphere or cone
  * (normalised discriminant below 1e-9), a half-plane met at a grazing angle
  * or next to the axis, or a cone root next to the origin.  Index lists are
- * compared bit-exactly only for rays that are not ties.
+ * compared bit-exactly only for rays that are not ties.  A second, looser
+ * flag marks rays whose segment lengths are ill-conditioned beyond FP32
+ * rounding (normalised discriminant below 1e-6, breakpoints within
+ * 1e-7 * r_max): a root's sensitivity to one-ulp changes of the ray grows
+ * like eps * l * scale / discriminant, so lengths there are compared with a
+ * conditioning-sized tolerance.  Flag byte: bit 0 tie, bit 1 sensitive.
  *
  * Build: gcc -O3 -march=native -fopenmp -shared -fPIC (see build.py here).
  */
@@ -161,7 +166,8 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
     double xx = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
     double xn = x[0] * n[0] + x[1] * n[1] + x[2] * n[2];
     int nt = 0;
-    int is_tie = 0;
+    int is_tie = 0;   /* index list not decided robustly */
+    int is_sens = 0;  /* lengths ill-conditioned beyond FP32 rounding */
     double *T = buf->t;
     const double tol = g->tol_t;
 
@@ -181,6 +187,7 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
         double r2[2], d, nm;
         int m = quad_roots(1.0, xn, xx - R * R, r2, &d, &nm);
         if (fabs(d) <= 1e-9 * R * R && R > 0 && INSIDE(-xn)) is_tie = 1;
+        if (fabs(d) <= 1e-6 * R * R && R > 0 && INSIDE(-xn)) is_sens = 1;
         for (int i = 0; i < m; i++)
             if (r2[i] > 0) T[nt++] = r2[i];
     }
@@ -220,6 +227,7 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
             }
             if (same && INSIDE(tg)) is_tie = 1;
         }
+        if (fabs(d) <= 1e-6 * nm && A != 0 && INSIDE(-B / A)) is_sens = 1;
         for (int i = 0; i < m; i++) {
             double t = rt[i];
             if (!(t > 0) || !isfinite(t)) continue;
@@ -265,7 +273,10 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
      * than tol (different surfaces meeting, or a double root) */
     for (int j = 0; j + 1 < nt; j++) {
         double a = T[j], b = T[j + 1];
-        if (b - a < tol && a > tin - tol && b < tout + tol) { is_tie = 1; break; }
+        if (a > tin - tol && b < tout + tol) {
+            if (b - a < tol) is_tie = 1;
+            if (b - a < 100.0 * tol) is_sens = 1;
+        }
     }
 
     int64_t nseg = 0;
@@ -294,7 +305,7 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
         last_end = tb;
         nseg++;
     }
-    if (tie) *tie = (uint8_t)is_tie;
+    if (tie) *tie = (uint8_t)(is_tie | ((is_tie | is_sens) << 1));
     return nseg;
 }
 
