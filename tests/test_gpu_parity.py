@@ -4,7 +4,10 @@ Bars (stated once here, used throughout):
   - rays: start and unit direction within 1e-13 (both sides build them in FP64);
   - segment lists: per-ray counts and voxel indices bit-exact for every ray the
     oracle does not flag as a tie (boundary events within 1e-9 r_max, grazing
-    roots); lengths within 2^-23 relative (FP32 storage of an FP64 length);
+    roots); lengths within 2^-23 relative + 1e-9 (FP32 storage of an FP64
+    length), or 1e-5 relative + 1e-7 r_max on rays the oracle marks
+    length-sensitive (near-grazing roots, whose FP64 lengths move by
+    eps * l * scale / discriminant under one-ulp changes of the ray);
   - projections: |y_gpu - y_ora| <= 1e-5 sum_k |rho_vk| len_k + 1e-7
     (rel 1e-5 in FP32, measured against the absolute integrand so that small
     negative noise in rho does not blow up the ratio);
@@ -60,10 +63,18 @@ def _compare_segments(tr, P):
     mg = ok[np.repeat(np.arange(R), cg)]
     assert np.array_equal(vox[mg], tr["vox"][mo])
     lo = tr["len"][mo]
-    assert np.all(np.abs(ln[mg] - lo) <= LEN_RTOL * lo + 1e-9)
+    sens = tr["sensitive"][np.repeat(np.arange(R), tr["counts"])][mo]
+    rmax = float(P._keep[0][-1])
+    tol = np.where(sens, 1e-5 * lo + 1e-7 * rmax, LEN_RTOL * lo + 1e-9)
+    exc = np.abs(ln[mg] - lo) - tol
+    if np.any(exc > 0):
+        seg_ray = np.repeat(np.arange(R), tr["counts"])[mo]
+        k = np.argsort(-exc)[:5]
+        rows = [(int(seg_ray[i]), float(ln[mg][i]), float(lo[i])) for i in k]
+        raise AssertionError(f"{int(np.sum(exc > 0))} lengths off; worst (ray, gpu, oracle): {rows}")
     # tie rays: total length still agrees
-    tot_g = np.add.reduceat(ln, rp[:-1]) if ln.size else np.zeros(R)
-    tot_g = np.where(cg > 0, tot_g, 0.0)
+    tot_g = np.zeros(R)
+    np.add.at(tot_g, np.repeat(np.arange(R), cg), ln)
     tot_o = np.zeros(R)
     np.add.at(tot_o, np.repeat(np.arange(R), tr["counts"]), tr["len"])
     assert np.all(np.abs(tot_g - tot_o) <= 1e-5 * tot_o + 1e-6)
@@ -200,7 +211,9 @@ def test_medium_full_size(ora, dev):
         a, b = rp[i], rp[i + 1]
         o0, o1 = tr["row_ptr"][k], tr["row_ptr"][k + 1]
         assert np.array_equal(vox[a:b], tr["vox"][o0:o1]), i
-        assert np.all(np.abs(ln[a:b] - tr["len"][o0:o1]) <= LEN_RTOL * tr["len"][o0:o1] + 1e-9)
+        lo = tr["len"][o0:o1]
+        tol = (1e-5 * lo + 1e-7 * 25.0) if tr["sensitive"][k] else (LEN_RTOL * lo + 1e-9)
+        assert np.all(np.abs(ln[a:b] - lo) <= tol), i
     # adjoint identity <F x, y> = <x, F^T y> on random x, y (FP64 sums on the host)
     xr = torch.rand((1, *w.grid.shape), device=dev)
     yr = torch.rand((1, *P.out_shape), device=dev)
