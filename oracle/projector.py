@@ -49,6 +49,10 @@ def load_library():
     lib.ora_project.restype = ctypes.c_int
     lib.ora_project.argtypes = grid_args + [_dp, _dp, ctypes.c_int64, _dp, ctypes.c_int, _dp,
                                             _i64p]
+    lib.ora_cone_data_grad.restype = ctypes.c_int
+    lib.ora_cone_data_grad.argtypes = grid_args + [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int,
+                                                   ctypes.c_int, _dp, _dp, ctypes.c_int, _i64p,
+                                                   _dp, _dp, _dp, _i64p]
     _LIB = lib
     return lib
 
@@ -177,3 +181,48 @@ def project(grid, starts, dirs, rho):
         raise MemoryError("oracle project failed")
     del keep
     return y, int(tot.value)
+
+
+def voxel_bounding_spheres(grid, targets):
+    """Conservative bounding sphere (centre, radius) of each target voxel:
+    5x5x5 samples over its (r, colatitude, azimuth) box, radius x 1.1."""
+    rb, eb, ab = (np.asarray(a, np.float64) for a in grid)
+    ne, na = len(eb) - 1, len(ab) - 1
+    out = np.empty((len(targets), 4))
+    s = np.linspace(0.0, 1.0, 5)
+    for n, v in enumerate(targets):
+        ir, ie, ia = v // (ne * na), (v // na) % ne, v % na
+        r = rb[ir] + s * (rb[ir + 1] - rb[ir])
+        th = eb[ie] + s * (eb[ie + 1] - eb[ie])
+        ph = ab[ia] + s * (ab[ia + 1] - ab[ia])
+        R, T, Ph = np.meshgrid(r, th, ph, indexing="ij")
+        P = np.stack([R * np.sin(T) * np.cos(Ph), R * np.sin(T) * np.sin(Ph), R * np.cos(T)],
+                     -1).reshape(-1, 3)
+        c = P.mean(0)
+        out[n, :3] = c
+        out[n, 3] = 1.1 * np.sqrt(((P - c) ** 2).sum(1)).max() + 1e-9
+    return out
+
+
+def cone_data_grad(grid, pos, look, up, fov_deg, H, W, rho, y, targets):
+    """Gradient of ||F rho - y||^2 at the target voxels for cone views, FP64,
+    rays generated and traced on the fly (no segment storage).  Returns
+    (grad, bound, rays traced); bound scales the FP32 rounding of the same
+    quantity (2 sum_i (sum_k |rho| len + |y_i|) len_iv)."""
+    lib = load_library()
+    keep, gargs = _grid_args(grid)
+    pos, look, up, fov = _f64(pos), _f64(look), _f64(up), _f64(fov_deg)
+    rho = _f64(np.asarray(rho).reshape(-1))
+    y = _f64(np.asarray(y).reshape(-1))
+    t = np.ascontiguousarray(targets, np.int64)
+    bs = _f64(voxel_bounding_spheres(grid, t))
+    g = np.empty(len(t))
+    b = np.empty(len(t))
+    n = ctypes.c_int64(0)
+    err = lib.ora_cone_data_grad(*gargs, pos.shape[0], _p(pos, _dp), _p(look, _dp), _p(up, _dp),
+                                 _p(fov, _dp), int(H), int(W), _p(rho, _dp), _p(y, _dp), len(t),
+                                 _p(t, _i64p), _p(bs, _dp), _p(g, _dp), _p(b, _dp), ctypes.byref(n))
+    if err:
+        raise MemoryError("oracle data gradient failed")
+    del keep
+    return g, b, int(n.value)

@@ -331,43 +331,67 @@ int ora_num_threads(void) {
  * sy = (2 (i + 1/2) / H - 1) tan(fov_h / 2).  Ray id = (view H + i) W + j.
  * fov_deg holds (fov_h, fov_w) per view, full angles in degrees.
  */
+/* Frame of one view: w, u, v (see ora_cone_rays). */
+static void cone_frame(const double *P, const double *Lk, const double *U, double w[3], double u[3],
+                       double vv[3]) {
+    w[0] = Lk[0] - P[0]; w[1] = Lk[1] - P[1]; w[2] = Lk[2] - P[2];
+    double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    for (int i = 0; i < 3; i++) w[i] /= wn;
+    double up3[3] = {U[0], U[1], U[2]};
+    if (up3[0] == 0 && up3[1] == 0 && up3[2] == 0) up3[2] = 1.0;
+    u[0] = w[1] * up3[2] - w[2] * up3[1];
+    u[1] = w[2] * up3[0] - w[0] * up3[2];
+    u[2] = w[0] * up3[1] - w[1] * up3[0];
+    double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (un < 1e-12) {
+        up3[0] = 1; up3[1] = 0; up3[2] = 0;
+        u[0] = w[1] * up3[2] - w[2] * up3[1];
+        u[1] = w[2] * up3[0] - w[0] * up3[2];
+        u[2] = w[0] * up3[1] - w[1] * up3[0];
+        un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    }
+    for (int i = 0; i < 3; i++) u[i] /= un;
+    vv[0] = u[1] * w[2] - u[2] * w[1];
+    vv[1] = u[2] * w[0] - u[0] * w[2];
+    vv[2] = u[0] * w[1] - u[1] * w[0];
+}
+
+/* Unit direction of pixel (i, j) of an H x W detector. */
+static void cone_dir(const double w[3], const double u[3], const double vv[3], double th, double tw,
+                     int i, int j, int H, int W, double d[3]) {
+    double sy = (2.0 * (i + 0.5) / H - 1.0) * th;
+    double sx = (2.0 * (j + 0.5) / W - 1.0) * tw;
+    for (int k = 0; k < 3; k++) d[k] = w[k] + sx * u[k] + sy * vv[k];
+    double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    for (int k = 0; k < 3; k++) d[k] /= dn;
+}
+
+/*
+ * Cone-beam rays (Sec. 4.2, detector at the cone vertex, Sec. 4.6), pinhole
+ * reading: w = unit(look - pos); u = unit(w x up) (up = +Z when all zero,
+ * +X when w is parallel to up); v = u x w; pixel (i, j) of an H x W detector
+ * looks along unit(w + sx u + sy v) with sx = (2 (j + 1/2) / W - 1)
+ * tan(fov_w / 2), sy = (2 (i + 1/2) / H - 1) tan(fov_h / 2).
+ * Ray id = (view H + i) W + j.  fov_deg holds (fov_h, fov_w) per view, full
+ * angles in degrees.
+ */
 void ora_cone_rays(int nv, const double *pos, const double *look, const double *up,
                    const double *fov_deg, int H, int W, double *starts, double *dirs) {
     for (int v = 0; v < nv; v++) {
-        const double *P = pos + 3 * v, *Lk = look + 3 * v, *U = up + 3 * v;
-        double w[3] = {Lk[0] - P[0], Lk[1] - P[1], Lk[2] - P[2]};
-        double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-        for (int i = 0; i < 3; i++) w[i] /= wn;
-        double up3[3] = {U[0], U[1], U[2]};
-        double u[3] = {w[1] * up3[2] - w[2] * up3[1], w[2] * up3[0] - w[0] * up3[2],
-                       w[0] * up3[1] - w[1] * up3[0]};
-        double un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        if (un < 1e-12) {
-            up3[0] = 1; up3[1] = 0; up3[2] = 0;
-            u[0] = w[1] * up3[2] - w[2] * up3[1];
-            u[1] = w[2] * up3[0] - w[0] * up3[2];
-            u[2] = w[0] * up3[1] - w[1] * up3[0];
-            un = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-        }
-        for (int i = 0; i < 3; i++) u[i] /= un;
-        double vv[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2],
-                        u[0] * w[1] - u[1] * w[0]};
+        double w[3], u[3], vv[3];
+        cone_frame(pos + 3 * v, look + 3 * v, up + 3 * v, w, u, vv);
         double th = tan(fov_deg[2 * v + 0] * M_PI / 360.0);
         double tw = tan(fov_deg[2 * v + 1] * M_PI / 360.0);
-        for (int i = 0; i < H; i++) {
-            double sy = (2.0 * (i + 0.5) / H - 1.0) * th;
+        for (int i = 0; i < H; i++)
             for (int j = 0; j < W; j++) {
-                double sx = (2.0 * (j + 0.5) / W - 1.0) * tw;
                 int64_t id = ((int64_t)v * H + i) * W + j;
                 double d[3];
-                for (int k = 0; k < 3; k++) d[k] = w[k] + sx * u[k] + sy * vv[k];
-                double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                cone_dir(w, u, vv, th, tw, i, j, H, W, d);
                 for (int k = 0; k < 3; k++) {
-                    starts[3 * id + k] = P[k];
-                    dirs[3 * id + k] = d[k] / dn;
+                    starts[3 * id + k] = pos[3 * v + k];
+                    dirs[3 * id + k] = d[k];
                 }
             }
-        }
     }
 }
 
@@ -496,5 +520,90 @@ int ora_project(const double *rb, int nr, const double *eb, int ne, const double
         free(sl);
     }
     if (nseg_total) *nseg_total = total;
+    return err;
+}
+
+/*
+ * Gradient of the data term ||F rho - y||^2 (Sec. 4.5, Eq. 6) at selected
+ * voxels, g_v = 2 sum_i (F rho - y)_i |ray_i inside v|, for a stack of cone
+ * views, without storing segment lists.  Rays are generated on the fly; a ray
+ * is traced only if it passes within the bounding sphere (bsph: centre xyz,
+ * radius per target) of some target voxel, which cannot change the result.
+ * bound_v = 2 sum_i (sum_k |rho_k| len_k + |y_i|) |ray_i inside v| scales the
+ * rounding error of an FP32 evaluation.  Returns 0 on success.
+ */
+int ora_cone_data_grad(const double *rb, int nr, const double *eb, int ne, const double *ab, int na,
+                       int nv, const double *pos, const double *look, const double *up,
+                       const double *fov_deg, int H, int W, const double *rho, const double *y,
+                       int nt, const int64_t *targets, const double *bsph, double *grad,
+                       double *bound, int64_t *n_traced) {
+    ogrid g;
+    ogrid_init(&g, rb, nr, eb, ne, ab, na);
+    int kmax = max_breakpoints(&g);
+    int err = 0;
+    int64_t traced = 0;
+    int64_t R = (int64_t)nv * H * W;
+    for (int k = 0; k < nt; k++) grad[k] = bound[k] = 0.0;
+#pragma omp parallel reduction(+ : traced)
+    {
+        obuf b;
+        b.cap = kmax;
+        b.t = (double *)malloc(sizeof(double) * (size_t)kmax);
+        int32_t *sv = (int32_t *)malloc(sizeof(int32_t) * (size_t)kmax);
+        double *sl = (double *)malloc(sizeof(double) * (size_t)kmax);
+        double *gl = (double *)calloc((size_t)nt, sizeof(double));
+        double *bl = (double *)calloc((size_t)nt, sizeof(double));
+        if (!b.t || !sv || !sl || !gl || !bl) {
+#pragma omp atomic write
+            err = 1;
+        } else {
+#pragma omp for schedule(dynamic, 4096)
+            for (int64_t id = 0; id < R; id++) {
+                int v = (int)(id / ((int64_t)H * W));
+                int rem = (int)(id % ((int64_t)H * W));
+                int i = rem / W, j = rem % W;
+                double w[3], u[3], vv[3], d[3];
+                cone_frame(pos + 3 * v, look + 3 * v, up + 3 * v, w, u, vv);
+                cone_dir(w, u, vv, tan(fov_deg[2 * v] * M_PI / 360.0),
+                         tan(fov_deg[2 * v + 1] * M_PI / 360.0), i, j, H, W, d);
+                const double *x = pos + 3 * v;
+                int near = 0;
+                for (int k = 0; k < nt && !near; k++) {
+                    const double *c = bsph + 4 * k;
+                    double cx = c[0] - x[0], cy = c[1] - x[1], cz = c[2] - x[2];
+                    double tt = cx * d[0] + cy * d[1] + cz * d[2];
+                    if (tt < 0) tt = 0;
+                    double qx = cx - tt * d[0], qy = cy - tt * d[1], qz = cz - tt * d[2];
+                    if (qx * qx + qy * qy + qz * qz <= c[3] * c[3]) near = 1;
+                }
+                if (!near) continue;
+                traced++;
+                int64_t m = trace_ray(&g, x, d, &b, sv, sl, NULL, kmax, NULL);
+                double f = 0, a = 0;
+                for (int64_t q = 0; q < m; q++) {
+                    f += sl[q] * rho[sv[q]];
+                    a += sl[q] * fabs(rho[sv[q]]);
+                }
+                double r = f - y[id];
+                for (int64_t q = 0; q < m; q++)
+                    for (int k = 0; k < nt; k++)
+                        if (targets[k] == sv[q]) {
+                            gl[k] += 2.0 * r * sl[q];
+                            bl[k] += 2.0 * (a + fabs(y[id])) * sl[q];
+                        }
+            }
+#pragma omp critical
+            for (int k = 0; k < nt; k++) {
+                grad[k] += gl[k];
+                bound[k] += bl[k];
+            }
+        }
+        free(b.t);
+        free(sv);
+        free(sl);
+        free(gl);
+        free(bl);
+    }
+    if (n_traced) *n_traced = traced;
     return err;
 }

@@ -1,0 +1,733 @@
+// Companions of the projector on gfx950 (include/tspnn.h): total variation,
+// Adam, and the layers of a small 3-D CNN on the spherical grid.
+//
+// 32 -> 32 convolutions are implicit GEMMs on v_mfma_f32_16x16x32_bf16:
+//   forward / input gradient: M = 16 voxels along azimuth, N = 16 output
+//     channels, K = 32 input channels of one of the 27 taps; each lane loads
+//     8 consecutive channels of one voxel (16 bytes, channels last);
+//   weight gradient: M = 16 output channels, N = 16 input channels, K = 32
+//     voxels of one azimuth row; rows of dz and of the (shifted) neighbour
+//     rows of x are staged transposed in LDS so that each lane reads its 8
+//     consecutive voxels with one 16-byte LDS load.
+// MFMA lane layout used (16x16x32, wave64): lane l supplies A[l % 16][8 (l/16)
+// .. +7] and B[8 (l/16) .. +7][l % 16] and receives D[4 (l/16) + i][l % 16],
+// i = 0..3.
+// All reductions (weight / bias gradients, TV value) write per-block partial
+// sums and add them in a fixed order.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <string>
+
+#include "tspnn.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+tspnn_status fail(tspnn_status s, const std::string &m) {
+    g_err = m;
+    return s;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int C = 32;  // channels of the hidden layers
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+struct Dims {
+    int N, D0, D1, D2;
+    __host__ __device__ __forceinline__ int64_t vox() const { return (int64_t)N * D0 * D1 * D2; }
+};
+
+// neighbour of voxel (n, i, j, k) at offset tap t; -1 when outside in r or e
+__device__ __forceinline__ int64_t neighbour(const Dims &d, int n, int i, int j, int k, int t) {
+    const int dr = t / 9 - 1, de = (t / 3) % 3 - 1, da = t % 3 - 1;
+    const int ii = i + dr, jj = j + de;
+    if (ii < 0 || ii >= d.D0 || jj < 0 || jj >= d.D1) return -1;
+    int kk = k + da;
+    kk = kk < 0 ? kk + d.D2 : (kk >= d.D2 ? kk - d.D2 : kk);
+    return (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + kk;
+}
+
+__device__ __forceinline__ void unflatten(const Dims &d, int64_t p, int &n, int &i, int &j,
+                                          int &k) {
+    k = (int)(p % d.D2);
+    int64_t q = p / d.D2;
+    j = (int)(q % d.D1);
+    q /= d.D1;
+    i = (int)(q % d.D0);
+    n = (int)(q / d.D0);
+}
+
+// ---------------------------------------------------------------- reductions
+
+// out[j] = sum over b of part[b * stride + j] for j < count, b in increasing order
+__global__ void k_reduce_parts(const float *part, int nb, int stride, int count, float *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    float s = 0.0f;
+    for (int b = 0; b < nb; b++) s += part[(int64_t)b * stride + j];
+    out[j] = s;
+}
+
+__device__ __forceinline__ float block_sum(float v, float *sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    float s = 0.0f;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) s += sh[i];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- TV
+
+constexpr int kTvBlock = 256;
+
+__device__ __forceinline__ float tv_term(float d, float eps) { return sqrtf(d * d + eps * eps); }
+
+__global__ __launch_bounds__(kTvBlock) void k_tv(const float *rho, Dims d, float eps,
+                                                 float *grad, float *part) {
+    __shared__ float sh[4];
+    const int64_t V = (int64_t)d.D0 * d.D1 * d.D2;
+    const int b = blockIdx.y;
+    const int64_t p = (int64_t)blockIdx.x * kTvBlock + threadIdx.x;
+    float val = 0.0f;
+    if (p < V) {
+        const float *r = rho + (int64_t)b * V;
+        const int k = (int)(p % d.D2), j = (int)((p / d.D2) % d.D1), i = (int)(p / d.D2 / d.D1);
+        const float c = r[p];
+        const int64_t sr = (int64_t)d.D1 * d.D2, se = d.D2;
+        float g = 0.0f;
+        // own forward differences
+        if (i + 1 < d.D0) {
+            const float df = r[p + sr] - c, t = tv_term(df, eps);
+            val += t;
+            g -= df / t;
+        }
+        if (j + 1 < d.D1) {
+            const float df = r[p + se] - c, t = tv_term(df, eps);
+            val += t;
+            g -= df / t;
+        }
+        {
+            const int64_t q = (k + 1 < d.D2) ? p + 1 : p + 1 - d.D2;
+            const float df = r[q] - c, t = tv_term(df, eps);
+            val += t;
+            g -= df / t;
+        }
+        // differences of the backward neighbours that involve this voxel
+        if (i > 0) {
+            const float df = c - r[p - sr];
+            g += df / tv_term(df, eps);
+        }
+        if (j > 0) {
+            const float df = c - r[p - se];
+            g += df / tv_term(df, eps);
+        }
+        {
+            const int64_t q = (k > 0) ? p - 1 : p - 1 + d.D2;
+            const float df = c - r[q];
+            g += df / tv_term(df, eps);
+        }
+        if (grad) grad[(int64_t)b * V + p] = g;
+    }
+    const float s = block_sum(val, sh);
+    if (threadIdx.x == 0) part[(int64_t)b * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void k_tv_value(const float *part, int nblk, int B, float *value) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float s = 0.0f;
+    for (int i = 0; i < nblk; i++) s += part[(int64_t)b * nblk + i];
+    value[b] = s;
+}
+
+// ---------------------------------------------------------------- Adam
+
+__global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, float wd, float c1, float c2, uint16_t *pb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i] + wd * p[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+}
+
+__global__ void k_to_bf16(const float *x, uint16_t *y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+__global__ void k_from_bf16(const uint16_t *x, float *y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = bf2f(x[i]);
+}
+
+// ---------------------------------------------------------------- edge layers (VALU)
+
+__global__ __launch_bounds__(256) void k_conv_in_fwd(const float *x, Dims d, const float *w,
+                                                     const float *b, uint16_t *y) {
+    __shared__ float ws[27 * C + C];
+    for (int i = threadIdx.x; i < 27 * C; i += 256) ws[i] = w[i];
+    if (threadIdx.x < C) ws[27 * C + threadIdx.x] = b[threadIdx.x];
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= d.vox()) return;
+    int n, i, j, k;
+    unflatten(d, p, n, i, j, k);
+    float xn[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) {
+        const int64_t q = neighbour(d, n, i, j, k, t);
+        xn[t] = q >= 0 ? x[q] : 0.0f;
+    }
+    u16x8 out[4];
+#pragma unroll
+    for (int o = 0; o < C; o++) {
+        float a = ws[27 * C + o];
+#pragma unroll
+        for (int t = 0; t < 27; t++) a = fmaf(ws[t * C + o], xn[t], a);
+        out[o >> 3][o & 7] = f2bf(fmaxf(a, 0.0f));
+    }
+    u16x8 *dst = (u16x8 *)(y + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; q++) dst[q] = out[q];
+}
+
+__global__ __launch_bounds__(256) void k_conv_out_fwd(const uint16_t *x, Dims d, const float *w,
+                                                      const float *b, const float *res,
+                                                      float *out) {
+    __shared__ float ws[27 * C];
+    for (int i = threadIdx.x; i < 27 * C; i += 256) ws[i] = w[i];
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= d.vox()) return;
+    int n, i, j, k;
+    unflatten(d, p, n, i, j, k);
+    float a = b[0] + (res ? res[p] : 0.0f);
+    for (int t = 0; t < 27; t++) {
+        const int64_t q = neighbour(d, n, i, j, k, t);
+        if (q < 0) continue;
+        const u16x8 *src = (const u16x8 *)(x + q * C);
+#pragma unroll
+        for (int c8 = 0; c8 < 4; c8++) {
+            const u16x8 v = src[c8];
+#pragma unroll
+            for (int e = 0; e < 8; e++) a = fmaf(ws[t * C + c8 * 8 + e], bf2f(v[e]), a);
+        }
+    }
+    out[p] = a;
+}
+
+// dz_in[q][i] = (sum_t w[t][i] dout[q - off(t)]) * (x[q][i] > 0)
+__global__ __launch_bounds__(256) void k_conv_out_bwd_data(const uint16_t *x, const float *dout,
+                                                           Dims d, const float *w,
+                                                           uint16_t *dz) {
+    __shared__ float ws[27 * C];
+    for (int i = threadIdx.x; i < 27 * C; i += 256) ws[i] = w[i];
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= d.vox()) return;
+    int n, i, j, k;
+    unflatten(d, p, n, i, j, k);
+    float dn[27];
+#pragma unroll
+    for (int t = 0; t < 27; t++) {
+        const int64_t q = neighbour(d, n, i, j, k, 26 - t);  // p - off(t) = p + off(26 - t)
+        dn[t] = q >= 0 ? dout[q] : 0.0f;
+    }
+    const u16x8 *src = (const u16x8 *)(x + p * C);
+    u16x8 *dst = (u16x8 *)(dz + p * C);
+#pragma unroll
+    for (int c8 = 0; c8 < 4; c8++) {
+        const u16x8 xv = src[c8];
+        u16x8 o;
+#pragma unroll
+        for (int e = 0; e < 8; e++) {
+            float a = 0.0f;
+#pragma unroll
+            for (int t = 0; t < 27; t++) a = fmaf(ws[t * C + c8 * 8 + e], dn[t], a);
+            o[e] = f2bf(bf2f(xv[e]) > 0.0f ? a : 0.0f);
+        }
+        dst[c8] = o;
+    }
+}
+
+constexpr int kChunk = 1024;  // voxels per block of the channel sums
+constexpr int kRowsPerBlk = 16;  // azimuth rows per block of the small weight gradients
+
+// mode 0 (input layer):  part[blk][t*32+o] = sum_p dz[p][o] * xin[p + off(t)]
+//                        part[blk][864+o]  = sum_p dz[p][o]
+// mode 1 (output layer): part[blk][t*32+i] = sum_p dout[p] * x[p + off(t)][i]
+//                        part[blk][864]    = sum_p dout[p]
+// A block walks kRowsPerBlk azimuth rows; thread jo owns outputs jo, jo+256, ...
+template <int MODE>
+__global__ __launch_bounds__(256) void k_small_wgrad(const float *xin, const uint16_t *xb,
+                                                     const uint16_t *dzb, const float *dout,
+                                                     Dims d, float *part, int n_out) {
+    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlk;
+    for (int jo = threadIdx.x; jo < n_out; jo += 256) {
+        float s = 0.0f;
+        const bool bias = jo >= 27 * C;
+        const int t = bias ? 13 : jo / C, c = jo % C;
+        const int dr = t / 9 - 1, de = (t / 3) % 3 - 1, da = t % 3 - 1;
+        for (int64_t row = r0; row < r0 + kRowsPerBlk && row < rows; row++) {
+            const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
+            const int n = (int)(row / d.D1 / d.D0);
+            const int ii = i + dr, jj = j + de;
+            if (ii < 0 || ii >= d.D0 || jj < 0 || jj >= d.D1) continue;
+            const int64_t pb = row * d.D2;
+            const int64_t qb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
+            for (int k = 0; k < d.D2; k++) {
+                int kk = k + da;
+                kk = kk < 0 ? kk + d.D2 : (kk >= d.D2 ? kk - d.D2 : kk);
+                const int64_t p = pb + k, q = qb + kk;
+                if (MODE == 0) {
+                    const float g = bf2f(dzb[p * C + c]);
+                    s = fmaf(g, bias ? 1.0f : xin[q], s);
+                } else {
+                    const float g = dout[p];
+                    s = fmaf(g, bias ? 1.0f : bf2f(xb[q * C + c]), s);
+                }
+            }
+        }
+        part[(int64_t)blockIdx.x * n_out + jo] = s;
+    }
+}
+
+// per-block channel sums of dz (bias gradient of the 32 -> 32 layers)
+__global__ __launch_bounds__(256) void k_chan_sum(const uint16_t *dz, int64_t nv, float *part) {
+    __shared__ float sh[256];
+    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
+    const int c = threadIdx.x & 31, r = threadIdx.x >> 5;  // 8 voxel lanes x 32 channels
+    float s = 0.0f;
+    for (int64_t p = p0 + r; p < p0 + kChunk && p < nv; p += 8) s += bf2f(dz[p * C + c]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float a = 0.0f;
+        for (int i = 0; i < 8; i++) a += sh[i * 32 + threadIdx.x];
+        part[(int64_t)blockIdx.x * C + threadIdx.x] = a;
+    }
+}
+
+// ---------------------------------------------------------------- 32 -> 32 on MFMA
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
+    return *reinterpret_cast<const bf16x8 *>(p);
+}
+
+// EPI 0: y = relu(acc + b); EPI 1: y = acc * (mask > 0).  One wavefront per 64
+// voxels of an azimuth row (4 M tiles of 16), all 32 output channels (2 N tiles).
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ x, Dims d,
+                                                   const uint16_t *__restrict__ w,
+                                                   const float *__restrict__ bias,
+                                                   const uint16_t *__restrict__ mask,
+                                                   uint16_t *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int nchunk = (d.D2 + 63) / 64;
+    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
+    if (wave >= rows * nchunk) return;  // uniform per wave
+    const int64_t row = wave / nchunk;
+    const int a0 = (int)(wave % nchunk) * 64;
+    const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1), n = (int)(row / d.D1 / d.D0);
+    const int ntile = min(4, (d.D2 - a0) / 16);
+    const int m = lane & 15, kq = lane >> 4;
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+#pragma unroll
+        for (int u = 0; u < 2; u++) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int dr = -1; dr <= 1; dr++) {
+        const int ii = i + dr;
+        if (ii < 0 || ii >= d.D0) continue;
+        for (int de = -1; de <= 1; de++) {
+            const int jj = j + de;
+            if (jj < 0 || jj >= d.D1) continue;
+            const int64_t rb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
+#pragma unroll
+            for (int da = -1; da <= 1; da++) {
+                const int tap = (dr + 1) * 9 + (de + 1) * 3 + (da + 1);
+                const bf16x8 b0 = ld8(w + ((int64_t)tap * C + m) * C + 8 * kq);
+                const bf16x8 b1 = ld8(w + ((int64_t)tap * C + 16 + m) * C + 8 * kq);
+#pragma unroll
+                for (int t = 0; t < 4; t++) {
+                    if (t < ntile) {
+                        int a = a0 + 16 * t + m + da;
+                        a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
+                        const bf16x8 av = ld8(x + (rb + a) * C + 8 * kq);
+                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc[t][0], 0, 0, 0);
+                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc[t][1], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    const int64_t ob = row * d.D2;
+#pragma unroll
+    for (int t = 0; t < 4; t++) {
+        if (t >= ntile) continue;
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int o = 16 * u + m;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int64_t p = ob + a0 + 16 * t + 4 * kq + e;
+                float v = acc[t][u][e];
+                if (EPI == 0) {
+                    v = fmaxf(v + bias[o], 0.0f);
+                } else {
+                    v = bf2f(mask[p * C + o]) > 0.0f ? v : 0.0f;
+                }
+                y[p * C + o] = f2bf(v);
+            }
+        }
+    }
+}
+
+// Weight gradient of a 32 -> 32 layer.  A workgroup walks rows r = blockIdx.x,
+// blockIdx.x + gridDim.x, ...; per row it stages dz transposed ([o][a]) and, for
+// each of the 9 (dr, de) neighbour rows, three azimuth-shifted transposed
+// copies of x ([da][i][a] = x[(a + da) mod D2][i]).  Wave w owns the taps
+// t = w, w + 4, ... (at most 7) and keeps their 32x32 sums in registers; at the
+// end every workgroup writes its partial sums (reduced later in fixed order).
+constexpr int kMaxD2 = 128;
+constexpr int kLdsStride = kMaxD2 + 8;  // padded row stride (bf16 elements)
+
+__global__ __launch_bounds__(256) void k_conv_wgrad_mfma(const uint16_t *__restrict__ x,
+                                                         const uint16_t *__restrict__ dz, Dims d,
+                                                         float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) uint16_t dzT[C * kLdsStride];
+    __shared__ __attribute__((aligned(16))) uint16_t xT[3][C * kLdsStride];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
+    const int D2 = d.D2;
+    const int nks = D2 / 32;
+    f32x4 acc[7][2][2];
+#pragma unroll
+    for (int s = 0; s < 7; s++)
+#pragma unroll
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int b = 0; b < 2; b++) acc[s][a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
+        const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
+        const int n = (int)(row / d.D1 / d.D0);
+        __syncthreads();
+        for (int e = tid; e < D2 * 4; e += 256) {  // 8 channels of one voxel per item
+            const int a = e >> 2, c8 = (e & 3) * 8;
+            const u16x8 v = *reinterpret_cast<const u16x8 *>(dz + (row * D2 + a) * C + c8);
+#pragma unroll
+            for (int q = 0; q < 8; q++) dzT[(c8 + q) * kLdsStride + a] = v[q];
+        }
+        for (int dr = -1; dr <= 1; dr++) {
+            const int ii = i + dr;
+            const bool okr = ii >= 0 && ii < d.D0;
+            for (int de = -1; de <= 1; de++) {
+                const int jj = j + de;
+                if (!okr || jj < 0 || jj >= d.D1) continue;  // uniform over the block
+                const int64_t rb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * D2;
+                __syncthreads();
+                for (int e = tid; e < D2 * 4; e += 256) {
+                    const int a = e >> 2, c8 = (e & 3) * 8;
+                    const u16x8 v = *reinterpret_cast<const u16x8 *>(x + (rb + a) * C + c8);
+#pragma unroll
+                    for (int s = 0; s < 3; s++) {  // copy for shift da = s - 1
+                        int ap = a - (s - 1);
+                        ap = ap < 0 ? ap + D2 : (ap >= D2 ? ap - D2 : ap);
+#pragma unroll
+                        for (int q = 0; q < 8; q++) xT[s][(c8 + q) * kLdsStride + ap] = v[q];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < 3; s++) {
+                    const int tap = (dr + 1) * 9 + (de + 1) * 3 + s;
+                    if ((tap & 3) != wv) continue;  // uniform per wave
+                    const int slot = tap >> 2;
+                    for (int ks = 0; ks < nks; ks++) {
+                        const int a = 32 * ks + 8 * kq;
+                        bf16x8 A[2], Bv[2];
+#pragma unroll
+                        for (int u = 0; u < 2; u++) {
+                            A[u] = *reinterpret_cast<const bf16x8 *>(&dzT[(16 * u + m) * kLdsStride + a]);
+                            Bv[u] = *reinterpret_cast<const bf16x8 *>(&xT[s][(16 * u + m) * kLdsStride + a]);
+                        }
+#pragma unroll
+                        for (int sl = 0; sl < 7; sl++) {
+                            if (sl != slot) continue;
+#pragma unroll
+                            for (int mu = 0; mu < 2; mu++)
+#pragma unroll
+                                for (int nu = 0; nu < 2; nu++)
+                                    acc[sl][mu][nu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                        A[mu], Bv[nu], acc[sl][mu][nu], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    // partial sums: part[blk][tap][o][i]
+    float *pb = part + (int64_t)blockIdx.x * 27 * C * C;
+#pragma unroll
+    for (int sl = 0; sl < 7; sl++) {
+        const int tap = sl * 4 + wv;
+        if (tap >= 27) continue;
+#pragma unroll
+        for (int mu = 0; mu < 2; mu++)
+#pragma unroll
+            for (int nu = 0; nu < 2; nu++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const int o = 16 * mu + 4 * kq + e, ci = 16 * nu + m;
+                    pb[((int64_t)tap * C + o) * C + ci] = acc[sl][mu][nu][e];
+                }
+    }
+}
+
+__global__ void k_flip(const uint16_t *w, uint16_t *wt) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 27 * C * C) return;
+    const int t = e / (C * C), i = (e / C) % C, o = e % C;
+    wt[e] = w[((26 - t) * C + o) * C + i];  // wt[t][i][o]
+}
+
+inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+int wgrad_blocks(int64_t rows) { return (int)(rows < 256 ? rows : 256); }
+
+bool dims_ok(int N, int D0, int D1, int D2) { return N > 0 && D0 > 0 && D1 > 0 && D2 > 0; }
+
+tspnn_status hipret(hipError_t e, const char *what) {
+    if (e != hipSuccess) return fail(TSPNN_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return TSPNN_OK;
+}
+
+tspnn_status mfma_dims(int N, int D0, int D1, int D2) {
+    if (!dims_ok(N, D0, D1, D2)) return fail(TSPNN_E_INVALID, "dimensions must be positive");
+    if (D2 % 32 != 0 || D2 > kMaxD2)
+        return fail(TSPNN_E_UNSUPPORTED, "MFMA layers need D2 % 32 == 0 and D2 <= 128");
+    return TSPNN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tspnn_last_error(void) { return g_err.c_str(); }
+
+size_t tspnn_tv_workspace(int32_t B, int64_t V) {
+    return sizeof(float) * (size_t)B * (size_t)((V + kTvBlock - 1) / kTvBlock) + 64;
+}
+
+tspnn_status tspnn_tv(const float *rho, int32_t B, int32_t D0, int32_t D1, int32_t D2, float eps,
+                      float *value, float *grad, void *work, void *stream) {
+    g_err.clear();
+    if (!rho || !value || !work || B < 1 || !dims_ok(1, D0, D1, D2))
+        return fail(TSPNN_E_INVALID, "tspnn_tv: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t V = (int64_t)D0 * D1 * D2;
+    const unsigned nb = nblk(V, kTvBlock);
+    Dims d{1, D0, D1, D2};
+    hipLaunchKernelGGL(k_tv, dim3(nb, B), dim3(kTvBlock), 0, st, rho, d, eps, grad, (float *)work);
+    hipLaunchKernelGGL(k_tv_value, dim3(nblk(B, 64)), dim3(64), 0, st, (const float *)work, (int)nb,
+                       B, value);
+    return hipret(hipGetLastError(), "tspnn_tv");
+}
+
+tspnn_status tspnn_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr,
+                        float beta1, float beta2, float eps, float weight_decay, int32_t step,
+                        uint16_t *p_bf16, void *stream) {
+    g_err.clear();
+    if (!p || !g || !m || !v || n < 0 || step < 1)
+        return fail(TSPNN_E_INVALID, "tspnn_adam: bad arguments");
+    if (n == 0) return TSPNN_OK;
+    const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n,
+                       lr, beta1, beta2, eps, weight_decay, c1, c2, p_bf16);
+    return hipret(hipGetLastError(), "tspnn_adam");
+}
+
+tspnn_status tspnn_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream) {
+    g_err.clear();
+    if (!x || !y || n < 0) return fail(TSPNN_E_INVALID, "tspnn_to_bf16: bad arguments");
+    if (n == 0) return TSPNN_OK;
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, n);
+    return hipret(hipGetLastError(), "tspnn_to_bf16");
+}
+
+tspnn_status tspnn_from_bf16(const uint16_t *x, float *y, int64_t n, void *stream) {
+    g_err.clear();
+    if (!x || !y || n < 0) return fail(TSPNN_E_INVALID, "tspnn_from_bf16: bad arguments");
+    if (n == 0) return TSPNN_OK;
+    hipLaunchKernelGGL(k_from_bf16, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y,
+                       n);
+    return hipret(hipGetLastError(), "tspnn_from_bf16");
+}
+
+size_t tspnn_conv_workspace(int32_t N, int32_t D0, int32_t D1, int32_t D2) {
+    const int64_t nv = (int64_t)N * D0 * D1 * D2;
+    const int64_t rows = (int64_t)N * D0 * D1;
+    const int64_t chunks = (nv + kChunk - 1) / kChunk;
+    const size_t a = sizeof(float) * (size_t)wgrad_blocks(rows) * 27 * C * C;
+    const int64_t rblk = (rows + kRowsPerBlk - 1) / kRowsPerBlk;
+    const size_t b = sizeof(float) * (size_t)rblk * (27 * C + C);
+    const size_t c = sizeof(float) * (size_t)chunks * C;
+    size_t mx = a > b ? a : b;
+    return (mx > c ? mx : c) + 256;
+}
+
+tspnn_status tspnn_conv_in_fwd(const float *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
+                               const float *w, const float *b, uint16_t *y, void *stream) {
+    g_err.clear();
+    if (!x || !w || !b || !y || !dims_ok(N, D0, D1, D2))
+        return fail(TSPNN_E_INVALID, "tspnn_conv_in_fwd: bad arguments");
+    Dims d{N, D0, D1, D2};
+    hipLaunchKernelGGL(k_conv_in_fwd, dim3(nblk(d.vox(), 256)), dim3(256), 0, (hipStream_t)stream,
+                       x, d, w, b, y);
+    return hipret(hipGetLastError(), "tspnn_conv_in_fwd");
+}
+
+tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
+                            const uint16_t *w, const float *b, uint16_t *y, void *stream) {
+    g_err.clear();
+    if (!x || !w || !b || !y) return fail(TSPNN_E_INVALID, "tspnn_conv_fwd: NULL argument");
+    tspnn_status s = mfma_dims(N, D0, D1, D2);
+    if (s != TSPNN_OK) return s;
+    Dims d{N, D0, D1, D2};
+    const int64_t waves = (int64_t)N * D0 * D1 * ((D2 + 63) / 64);
+    hipLaunchKernelGGL(k_conv_mfma<0>, dim3(nblk(waves * 64, 256)), dim3(256), 0,
+                       (hipStream_t)stream, x, d, w, b, (const uint16_t *)nullptr, y);
+    return hipret(hipGetLastError(), "tspnn_conv_fwd");
+}
+
+tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, int32_t D1,
+                                 int32_t D2, const uint16_t *w, const uint16_t *act_in,
+                                 uint16_t *dz_in, void *stream) {
+    g_err.clear();
+    if (!dz_out || !w || !act_in || !dz_in)
+        return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_data: NULL argument");
+    tspnn_status s = mfma_dims(N, D0, D1, D2);
+    if (s != TSPNN_OK) return s;
+    Dims d{N, D0, D1, D2};
+    const int64_t waves = (int64_t)N * D0 * D1 * ((D2 + 63) / 64);
+    hipLaunchKernelGGL(k_conv_mfma<1>, dim3(nblk(waves * 64, 256)), dim3(256), 0,
+                       (hipStream_t)stream, dz_out, d, w, (const float *)nullptr, act_in, dz_in);
+    return hipret(hipGetLastError(), "tspnn_conv_bwd_data");
+}
+
+tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t D0,
+                                   int32_t D1, int32_t D2, float *dw, float *db, void *work,
+                                   void *stream) {
+    g_err.clear();
+    if (!x || !dz || !dw || !work) return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_weight: NULL");
+    tspnn_status s = mfma_dims(N, D0, D1, D2);
+    if (s != TSPNN_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Dims d{N, D0, D1, D2};
+    const int64_t rows = (int64_t)N * D0 * D1;
+    const int nb = wgrad_blocks(rows);
+    float *part = (float *)work;
+    hipLaunchKernelGGL(k_conv_wgrad_mfma, dim3(nb), dim3(256), 0, st, x, dz, d, part);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C * C, 256)), dim3(256), 0, st, part, nb,
+                       27 * C * C, 27 * C * C, dw);
+    if (db) {
+        const int64_t nv = d.vox();
+        const int nc = (int)((nv + kChunk - 1) / kChunk);
+        hipLaunchKernelGGL(k_chan_sum, dim3(nc), dim3(256), 0, st, dz, nv, part);
+        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part, nc, C, C, db);
+    }
+    return hipret(hipGetLastError(), "tspnn_conv_bwd_weight");
+}
+
+tspnn_status tspnn_conv_in_bwd_weight(const float *x, const uint16_t *dz, int32_t N, int32_t D0,
+                                      int32_t D1, int32_t D2, float *dw, float *db, void *work,
+                                      void *stream) {
+    g_err.clear();
+    if (!x || !dz || !dw || !db || !work || !dims_ok(N, D0, D1, D2))
+        return fail(TSPNN_E_INVALID, "tspnn_conv_in_bwd_weight: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    Dims d{N, D0, D1, D2};
+    const int nc = (int)(((int64_t)N * D0 * D1 + kRowsPerBlk - 1) / kRowsPerBlk);
+    const int n_out = 27 * C + C;
+    float *part = (float *)work;
+    hipLaunchKernelGGL(k_small_wgrad<0>, dim3(nc), dim3(256), 0, st, x, (const uint16_t *)nullptr,
+                       dz, (const float *)nullptr, d, part, n_out);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C, 256)), dim3(256), 0, st, part, nc, n_out,
+                       27 * C, dw);
+    // bias sums live at offset 27*C of every partial row
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part + 27 * C, nc, n_out, C, db);
+    return hipret(hipGetLastError(), "tspnn_conv_in_bwd_weight");
+}
+
+tspnn_status tspnn_conv_out_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
+                                const float *w, const float *b, const float *res, float *out,
+                                void *stream) {
+    g_err.clear();
+    if (!x || !w || !b || !out || !dims_ok(N, D0, D1, D2))
+        return fail(TSPNN_E_INVALID, "tspnn_conv_out_fwd: bad arguments");
+    Dims d{N, D0, D1, D2};
+    hipLaunchKernelGGL(k_conv_out_fwd, dim3(nblk(d.vox(), 256)), dim3(256), 0,
+                       (hipStream_t)stream, x, d, w, b, res, out);
+    return hipret(hipGetLastError(), "tspnn_conv_out_fwd");
+}
+
+tspnn_status tspnn_conv_out_bwd(const uint16_t *x, const float *dout, int32_t N, int32_t D0,
+                                int32_t D1, int32_t D2, const float *w, float *dw, float *db,
+                                uint16_t *dz_in, void *work, void *stream) {
+    g_err.clear();
+    if (!x || !dout || !w || !dw || !db || !work || !dims_ok(N, D0, D1, D2))
+        return fail(TSPNN_E_INVALID, "tspnn_conv_out_bwd: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    Dims d{N, D0, D1, D2};
+    const int nc = (int)(((int64_t)N * D0 * D1 + kRowsPerBlk - 1) / kRowsPerBlk);
+    const int n_out = 27 * C + 1;
+    float *part = (float *)work;
+    hipLaunchKernelGGL(k_small_wgrad<1>, dim3(nc), dim3(256), 0, st, (const float *)nullptr, x,
+                       (const uint16_t *)nullptr, dout, d, part, n_out);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C, 256)), dim3(256), 0, st, part, nc, n_out,
+                       27 * C, dw);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part + 27 * C, nc, n_out, 1, db);
+    if (dz_in)
+        hipLaunchKernelGGL(k_conv_out_bwd_data, dim3(nblk(d.vox(), 256)), dim3(256), 0, st, x, dout,
+                           d, w, dz_in);
+    return hipret(hipGetLastError(), "tspnn_conv_out_bwd");
+}
+
+tspnn_status tspnn_conv_flip_weights(const uint16_t *w, uint16_t *wt, void *stream) {
+    g_err.clear();
+    if (!w || !wt) return fail(TSPNN_E_INVALID, "tspnn_conv_flip_weights: NULL");
+    hipLaunchKernelGGL(k_flip, dim3(nblk(27 * C * C, 256)), dim3(256), 0, (hipStream_t)stream, w,
+                       wt);
+    return hipret(hipGetLastError(), "tspnn_conv_flip_weights");
+}
+
+}  // extern "C"

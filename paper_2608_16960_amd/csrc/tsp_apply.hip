@@ -2,13 +2,13 @@
 // segment lists, on gfx950.
 //
 // Forward: one lane per ray slot of a 64-ray slice of the ray-major store.
-// Every step a wavefront reads one coalesced 256-byte row of voxel indices and
-// one of lengths, gathers rho (the object stays in L2 / Infinity Cache), and
-// accumulates len * rho in FP32 with FMA.  No reduction across lanes.
+// Each lane reads four consecutive segments per 16-byte load (a wavefront
+// reads 1 KiB contiguous of indices and of lengths), gathers rho (the object
+// stays in L2), and accumulates len * rho in FP32 with FMA.  No reduction
+// across lanes.
 //
-// Deterministic adjoint: one wavefront per voxel of the voxel-major store.
-// Lane l sums entries l, l+64, ... of the voxel's list (ray order) and a fixed
-// butterfly adds the 64 partial sums, so the result is bitwise reproducible.
+// Deterministic adjoint: one wavefront per voxel of the voxel-major store,
+// fixed summation order, bitwise reproducible.
 //
 // Atomic adjoint: ray-major like the forward, scattering len * y into x with
 // hardware float atomics.
@@ -17,6 +17,33 @@
 
 namespace tsp {
 namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Streamed segment data is read once: non-temporal loads keep it from
+// evicting the gathered object / measurements from L2.
+__device__ __forceinline__ v4i ld_nt(const v4i *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ v4f ld_nt(const v4f *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ int32_t ld_nt(const int32_t *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float *p) { return __builtin_nontemporal_load(p); }
+
+template <int NB>
+__device__ __forceinline__ void fwd_quad(const v4i v, const v4f l, int j, int c,
+                                         const float *__restrict__ rho, int nb, int64_t V,
+                                         float *acc) {
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const bool ok = j + i < c;  // padding entries hold voxel 0, length 0
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            if (b < nb) {
+                const float r = rho[b * V + v[i]];
+                acc[b] = fmaf(l[i], ok ? r : 0.0f, acc[b]);
+            }
+        }
+    }
+}
 
 template <int NB>
 __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ perm,
@@ -33,39 +60,28 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
     const int lane = (int)(slot & 63);
     const int32_t ray = perm[slot];
     const int c = cnt_sorted[slot];
-    const int m = slice_len[s];
-    const int32_t *vp = vox + slice_ptr[s] + lane;
-    const float *lp = len + slice_ptr[s] + lane;
+    const int nq = slice_len[s] >> 2;  // quads of segments in this slice
+    const v4i *vp = (const v4i *)(vox + slice_ptr[s]) + lane;
+    const v4f *lp = (const v4f *)(len + slice_ptr[s]) + lane;
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
-    int j = 0;
-    for (; j + 8 <= m; j += 8) {
-        int32_t vv[8];
-        float ll[8];
+    int q = 0;
+    for (; q + 4 <= nq; q += 4) {
+        v4i v[4];
+        v4f l[4];
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            const bool ok = j + u < c;
-            vv[u] = ok ? vp[(int64_t)(j + u) * kWave] : 0;
-            ll[u] = ok ? lp[(int64_t)(j + u) * kWave] : 0.0f;
+        for (int u = 0; u < 4; u++) {
+            v[u] = ld_nt(vp + (int64_t)(q + u) * kWave);
+            l[u] = ld_nt(lp + (int64_t)(q + u) * kWave);
         }
 #pragma unroll
-        for (int u = 0; u < 8; u++) {
-            if (j + u < c) {
-#pragma unroll
-                for (int b = 0; b < NB; b++)
-                    if (b < nb) acc[b] = fmaf(ll[u], rho[b * V + vv[u]], acc[b]);
-            }
-        }
+        for (int u = 0; u < 4; u++) fwd_quad<NB>(v[u], l[u], 4 * (q + u), c, rho, nb, V, acc);
     }
-    for (; j < m; j++) {
-        if (j < c) {
-            const int32_t v = vp[(int64_t)j * kWave];
-            const float l = lp[(int64_t)j * kWave];
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-                if (b < nb) acc[b] = fmaf(l, rho[b * V + v], acc[b]);
-        }
+    for (; q < nq; q++) {
+        const v4i v = ld_nt(vp + (int64_t)q * kWave);
+        const v4f l = ld_nt(lp + (int64_t)q * kWave);
+        fwd_quad<NB>(v, l, 4 * q, c, rho, nb, V, acc);
     }
     if (ray >= 0) {
 #pragma unroll
@@ -74,6 +90,12 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
     }
 }
 
+// One wavefront per voxel.  Lane i sums entries i, i+64, i+128, ... of the
+// voxel's list (ray order), four independent loads in flight per lane; a
+// fixed butterfly adds the 64 partial sums.  The order never depends on
+// timing, so x is bitwise reproducible.  Lanes read consecutive entries, so
+// one gather instruction touches the few cache lines that hold a patch of
+// neighbouring detector pixels.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
                                                   const int32_t *__restrict__ col_ray,
@@ -82,14 +104,29 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
                                                   float *__restrict__ x) {
     const int64_t v = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (v >= V) return;
+    if (v >= V) return;  // uniform over the wavefront
     const int64_t lo = col_ptr[v], hi = col_ptr[v + 1];
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
-    for (int64_t k = lo + lane; k < hi; k += kWave) {
-        const int32_t r = col_ray[k];
-        const float l = col_len[k];
+    int64_t k = lo + lane;
+    for (; k + 3 * kWave < hi; k += 4 * kWave) {
+        int32_t r[4];
+        float l[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            r[u] = ld_nt(col_ray + k + kWave * u);
+            l[u] = ld_nt(col_len + k + kWave * u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                if (b < nb) acc[b] = fmaf(l[u], y[b * R + r[u]], acc[b]);
+    }
+    for (; k < hi; k += kWave) {
+        const int32_t r = ld_nt(col_ray + k);
+        const float l = ld_nt(col_len + k);
 #pragma unroll
         for (int b = 0; b < NB; b++)
             if (b < nb) acc[b] = fmaf(l, y[b * R + r], acc[b]);
@@ -119,13 +156,15 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
     const int32_t ray = perm[slot];
     if (ray < 0) return;
     const int c = cnt_sorted[slot];
-    const int64_t base = slice_ptr[slot >> 6] + (slot & 63);
+    const int64_t base = slice_ptr[slot >> 6];
+    const int lane = (int)(slot & 63);
     float yv[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) yv[b] = (b < nb) ? y[b * R + ray] : 0.0f;
     for (int j = 0; j < c; j++) {
-        const int32_t v = vox[base + (int64_t)j * kWave];
-        const float l = len[base + (int64_t)j * kWave];
+        const int64_t i = sell_index(base, lane, j);
+        const int32_t v = vox[i];
+        const float l = len[i];
 #pragma unroll
         for (int b = 0; b < NB; b++)
             if (b < nb) atomicAdd(x + b * V + v, l * yv[b]);
@@ -178,15 +217,15 @@ hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, co
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * R;
         float *xx = x + (int64_t)b0 * V;
-        const dim3 g(blocks_for(V * kWave, 256));
+        const dim3 grid(blocks_for(V * kWave, 256));
         if (nb == 1)
-            hipLaunchKernelGGL(k_adj_csc<1>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+            hipLaunchKernelGGL(k_adj_csc<1>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
                                yy, nb, R, xx);
         else if (nb == 2)
-            hipLaunchKernelGGL(k_adj_csc<2>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+            hipLaunchKernelGGL(k_adj_csc<2>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
                                yy, nb, R, xx);
         else
-            hipLaunchKernelGGL(k_adj_csc<4>, g, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
+            hipLaunchKernelGGL(k_adj_csc<4>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
                                yy, nb, R, xx);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -51,6 +51,14 @@ __device__ __forceinline__ int32_t natural_ray(const RayDesc &rd, int64_t slot) 
     return (view * rd.H + i) * rd.W + j;
 }
 
+// Ray-major sliced store: slice s holds 64 rays (one per lane); segment j of
+// lane l sits at slice_ptr[s] + 256 (j / 4) + 4 l + (j % 4), so each lane
+// reads four consecutive segments with one 16-byte load and a wavefront reads
+// 1 KiB contiguous.  Slices are padded to a multiple of 4 segments.
+__host__ __device__ __forceinline__ int64_t sell_index(int64_t base, int lane, int j) {
+    return base + (int64_t)(j >> 2) * 256 + lane * 4 + (j & 3);
+}
+
 // ---- launchers (tsp_trace.hip) ----
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
                         unsigned long long *total, int *maxcnt, hipStream_t st);

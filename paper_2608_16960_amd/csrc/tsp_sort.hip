@@ -4,13 +4,13 @@
 //
 // Ray-major store ("sliced"): the 256 ray slots of a 16x16 detector window
 // are ordered by decreasing segment count and cut into four 64-ray slices;
-// slice s stores segment j of its lane l at slice_ptr[s] + 64 j + l, padded
-// to the slice's longest list.  A wavefront then reads one coalesced 256-byte
-// row of indices and of lengths per step.
+// slice s stores segment j of its lane l at sell_index(slice_ptr[s], l, j)
+// (four consecutive segments per lane, 1 KiB per wavefront step), padded to
+// the slice's longest list rounded up to 4.
 //
 // Voxel-major store: the canonical (ray-ordered) segments are sorted by voxel
-// with a stable LSD radix sort (8-bit digits), so every voxel's entries keep
-// increasing ray order; the adjoint then sums each voxel in a fixed order.
+// with a stable LSD radix sort (8-bit digits), so every voxel's list keeps
+// increasing ray order and the adjoint sums it in a fixed order.
 
 #include "tsp_internal.h"
 
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_window_sort(RayDesc rd, const int32_t *
     const uint32_t r = (uint32_t)(mine & 0xffffffffu);
     perm[slot] = (r == 0xffffffffu) ? -1 : (int32_t)r;
     cnt_sorted[slot] = cs;
-    if ((t & 63) == 0) slice_len[slot >> 6] = cs;  // longest list of the slice
+    if ((t & 63) == 0) slice_len[slot >> 6] = (cs + 3) & ~3;  // longest list, padded to 4
 }
 
 // ------------------------------------------------------------ scan (int32 -> int64)
@@ -147,11 +147,13 @@ __global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32
     const int32_t r = perm[slot];
     if (r < 0) return;
     const int c = cnt_sorted[slot];
-    const int64_t src = slice_ptr[slot >> 6] + (slot & 63);
+    const int64_t base = slice_ptr[slot >> 6];
+    const int lane = (int)(slot & 63);
     const int64_t dst = row_ptr[r];
     for (int j = 0; j < c; j++) {
-        const int32_t v = vox[src + (int64_t)j * kWave];
-        const float l = len[src + (int64_t)j * kWave];
+        const int64_t i = sell_index(base, lane, j);
+        const int32_t v = vox[i];
+        const float l = len[i];
         if (keys) {
             keys[dst + j] = v;
             vals[dst + j] = (uint64_t)(uint32_t)r | ((uint64_t)__float_as_uint(l) << 32);

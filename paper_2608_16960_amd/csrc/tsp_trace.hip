@@ -74,12 +74,15 @@ struct CountVis {
 struct FillVis {
     int32_t *vox;
     float *len;
+    int64_t base;
+    int lane;
     int cap;
     int n = 0;
     __device__ void seg(int v, double l) {
         if (n < cap) {
-            vox[(int64_t)n * kWave] = v;
-            len[(int64_t)n * kWave] = (float)l;
+            const int64_t i = sell_index(base, lane, n);
+            vox[i] = v;
+            len[i] = (float)l;
         }
         n++;
     }
@@ -168,19 +171,20 @@ __global__ __launch_bounds__(256) void k_fill(TabDesc D, const double *tab, RayD
     const int32_t ray = perm[slot];
     const int cap = cnt_sorted[slot];
     const int m = slice_len[s];
-    const int64_t base = slice_ptr[s] + lane;
+    const int64_t base = slice_ptr[s];
     int n = 0;
     if (ray >= 0) {
         V3 x, nn;
         ray_of(rd, ray, x, nn);
-        FillVis vis{vox + base, len + base, cap};
+        FillVis vis{vox, len, base, lane, cap};
         trace_ray(T, x, nn, vis);
         n = vis.n;
         if (n != cap) atomicOr(err, 1);
     }
-    for (int j = min(n, cap); j < m; j++) {
-        vox[base + (int64_t)j * kWave] = 0;
-        len[base + (int64_t)j * kWave] = 0.0f;
+    for (int j = min(n, cap); j < m; j++) {  // padding up to the slice length
+        const int64_t i = sell_index(base, lane, j);
+        vox[i] = 0;
+        len[i] = 0.0f;
     }
 }
 

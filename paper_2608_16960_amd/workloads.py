@@ -150,26 +150,28 @@ def exp_background(grid: Grid, scale=4.0):
 
 
 def blob_phantom(grid: Grid, rng, n_blobs=5, scale=4.0, amp=(0.5, 2.0), width=(1.0, 3.0),
-                 r_mu=(5.0, 20.0)):
-    """exp(-(r-3)/scale) plus Gaussian blobs A exp(-|x - mu|^2 / (2 w^2))."""
-    X, R = centroids(grid)
+                 r_mu=(5.0, 20.0), cent=None):
+    """exp(-(r-3)/scale) plus Gaussian blobs A exp(-|x - mu|^2 / (2 w^2)).
+    cent: precomputed centroids(grid), to reuse across many phantoms."""
+    X, R = centroids(grid) if cent is None else cent
     rho = np.exp(-(R - 3.0) / scale)
+    R2 = R * R  # |x|^2 at the centroids
     for _ in range(n_blobs):
         A = rng.uniform(*amp)
         w = rng.uniform(*width)
         u = rng.normal(size=3)
         u /= np.linalg.norm(u)
         mu = rng.uniform(*r_mu) * u
-        d2 = np.sum((X - mu) ** 2, axis=-1)
-        rho = rho + A * np.exp(-d2 / (2 * w * w))
+        d2 = np.maximum(R2 - 2.0 * (X @ mu) + mu @ mu, 0.0)  # |x - mu|^2
+        rho += A * np.exp(-d2 / (2 * w * w))
     return rho
 
 
-def plume_phantom(grid: Grid, rng):
+def plume_phantom(grid: Grid, rng, cent=None):
     """Learned-workload phantom: exp(-(r-3)/s), s ~ U[2,6], + K ~ U{1..8} plumes."""
     s = rng.uniform(2.0, 6.0)
     k = int(rng.integers(1, 9))
-    return blob_phantom(grid, rng, n_blobs=k, scale=s)
+    return blob_phantom(grid, rng, n_blobs=k, scale=s, cent=cent)
 
 
 def tiny(noise_seed=0, noise=0.01) -> Workload:
@@ -206,7 +208,11 @@ def learned_geometry(orbit_seed=5, n_views=64, det=256):
 
 def learned_phantoms(grid: Grid, n, seed):
     rng = np.random.default_rng(seed)
-    return np.stack([plume_phantom(grid, rng) for _ in range(n)]).astype(np.float32)
+    cent = centroids(grid)
+    out = np.empty((n, *grid.shape), np.float32)
+    for i in range(n):
+        out[i] = plume_phantom(grid, rng, cent)
+    return out
 
 
 def large(orbit_seed=9, obj_seeds=(10, 11, 12, 13)) -> Workload:

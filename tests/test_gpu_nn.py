@@ -1,0 +1,219 @@
+"""GPU parity of the TV, Adam and CNN-layer kernels against FP64 references.
+
+Bars: float32 results within 1e-5 relative of their scale; bfloat16 outputs
+within one bf16 rounding (2^-8 relative) of the FP64 result computed from the
+same bf16-rounded inputs, plus 1e-6 of the output scale for the FP32
+accumulation order; reductions (weight / bias gradients) within 1e-5 of the
+gradient scale, and bitwise reproducible across runs.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import conv as OC
+from oracle import reg as OR
+
+pytestmark = pytest.mark.gpu
+
+BF_REL = 2.0 ** -8
+
+
+@pytest.fixture(scope="module")
+def nn():
+    assert torch.cuda.is_available()
+    from paper_2608_16960_amd import nn as _nn
+    return _nn
+
+
+def _bf(t):
+    """Round a float tensor to bfloat16 on the CPU (input generation)."""
+    return t.to(torch.bfloat16)
+
+
+def _dev(**ts):
+    """Device copies that stay alive for the whole test (a temporary passed as a
+    raw pointer would be freed, and its memory reused, before the kernel runs)."""
+    return {k: v.cuda() for k, v in ts.items()}
+
+
+def _close_bf16(got_bf, ref):
+    got = got_bf.float().cpu().double()
+    scale = float(ref.abs().max())
+    err = (got - ref).abs()
+    tol = BF_REL * ref.abs() + 1e-6 * scale + 1e-30
+    assert bool((err <= tol).all()), f"max excess {float((err - tol).max()):.3e} (scale {scale:.3e})"
+
+
+def test_tv_value_and_gradient(nn):
+    rng = np.random.default_rng(0)
+    rho = rng.normal(size=(2, 9, 7, 16)).astype(np.float32)
+    eps = 1e-3
+    val, grad = nn.tv(torch.from_numpy(rho).cuda(), eps)
+    v_ref, g_ref = OR.tv_value_grad(rho.astype(np.float64), eps)
+    assert np.allclose(val.cpu().numpy(), v_ref, rtol=1e-5, atol=0)
+    assert np.max(np.abs(grad.cpu().numpy() - g_ref)) <= 1e-5 * np.max(np.abs(g_ref))
+    val2, grad2 = nn.tv(torch.from_numpy(rho).cuda(), eps)
+    assert torch.equal(val, val2) and torch.equal(grad, grad2)
+
+
+def test_adam_matches_reference(nn):
+    rng = np.random.default_rng(1)
+    p0 = rng.normal(size=1000).astype(np.float32)
+    p = torch.from_numpy(p0.copy()).cuda()
+    pb = torch.empty(1000, dtype=torch.bfloat16, device="cuda")
+    opt = nn.Adam([p], lr=0.01, betas=(0.9, 0.99), eps=1e-7, weight_decay=0.3)
+    pr, m, v = p0.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for t in range(1, 4):
+        g = rng.normal(size=1000).astype(np.float32)
+        opt.step([torch.from_numpy(g).cuda()], bf16_copies=[pb])
+        pr, m, v = OR.adam_step(pr, g.astype(np.float64), m, v, t, 0.01, 0.9, 0.99, 1e-7, 0.3)
+    assert np.max(np.abs(p.cpu().numpy() - pr)) < 1e-5 * np.max(np.abs(pr))
+    assert torch.equal(pb, p.to(torch.bfloat16))
+
+
+SHAPES = [(2, 5, 4, 64), (1, 3, 6, 32)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_conv_hidden_forward_mfma(nn, shape):
+    N, D0, D1, D2 = shape
+    g = torch.Generator().manual_seed(2)
+    x = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    w = _bf(torch.randn((27, 32, 32), generator=g) * 0.05)
+    b = torch.randn(32, generator=g) * 0.1
+    y = torch.empty((N, D0, D1, D2, 32), dtype=torch.bfloat16, device="cuda")
+    D = _dev(b=b, w=w, x=x)
+    nn.check(nn.lib.tspnn_conv_fwd(nn._p(D["x"]), N, D0, D1, D2, nn._p(D["w"]),
+                                   nn._p(D["b"]), nn._p(y), nn._s()))
+    ref = torch.relu(OC.conv(x.double(), w.double(), b.double()))
+    _close_bf16(y, ref)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_conv_hidden_input_gradient_mfma(nn, shape):
+    N, D0, D1, D2 = shape
+    g = torch.Generator().manual_seed(3)
+    dz = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    act = _bf(torch.relu(torch.randn((N, D0, D1, D2, 32), generator=g)))
+    w = _bf(torch.randn((27, 32, 32), generator=g) * 0.05)
+    wt = torch.empty_like(w.cuda())
+    D = _dev(act=act, dz=dz, w=w)
+    nn.check(nn.lib.tspnn_conv_flip_weights(nn._p(D["w"]), nn._p(wt), nn._s()))
+    out = torch.empty((N, D0, D1, D2, 32), dtype=torch.bfloat16, device="cuda")
+    nn.check(nn.lib.tspnn_conv_bwd_data(nn._p(D["dz"]), N, D0, D1, D2, nn._p(wt),
+                                        nn._p(D["act"]), nn._p(out), nn._s()))
+    xr = torch.zeros((N, D0, D1, D2, 32), dtype=torch.float64, requires_grad=True)
+    (OC.conv(xr, w.double()) * dz.double()).sum().backward()
+    ref = xr.grad * (act.double() > 0)
+    _close_bf16(out, ref)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_conv_hidden_weight_gradient_mfma(nn, shape):
+    N, D0, D1, D2 = shape
+    g = torch.Generator().manual_seed(4)
+    x = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    dz = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    ws = torch.empty(int(nn.lib.tspnn_conv_workspace(N, D0, D1, D2)) // 4 + 1, device="cuda")
+    dw = torch.empty((27, 32, 32), device="cuda")
+    db = torch.empty(32, device="cuda")
+    D = _dev(dz=dz, x=x)
+    nn.check(nn.lib.tspnn_conv_bwd_weight(nn._p(D["x"]), nn._p(D["dz"]), N, D0, D1, D2,
+                                          nn._p(dw), nn._p(db), nn._p(ws), nn._s()))
+    wr = torch.zeros((27, 32, 32), dtype=torch.float64, requires_grad=True)
+    br = torch.zeros(32, dtype=torch.float64, requires_grad=True)
+    (OC.conv(x.double(), wr, br) * dz.double()).sum().backward()
+    for got, ref in ((dw, wr.grad), (db, br.grad)):
+        scale = float(ref.abs().max())
+        assert float((got.cpu().double() - ref).abs().max()) <= 1e-5 * scale
+    dw2 = torch.empty_like(dw)
+    nn.check(nn.lib.tspnn_conv_bwd_weight(nn._p(D["x"]), nn._p(D["dz"]), N, D0, D1, D2,
+                                          nn._p(dw2), nn._p(db), nn._p(ws), nn._s()))
+    assert torch.equal(dw, dw2)
+
+
+def test_conv_edge_layers(nn):
+    N, D0, D1, D2 = 2, 4, 5, 32
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn((N, D0, D1, D2), generator=g)
+    w0 = torch.randn((27, 32), generator=g) * 0.2
+    b0 = torch.randn(32, generator=g) * 0.1
+    a = _bf(torch.relu(torch.randn((N, D0, D1, D2, 32), generator=g)))
+    w5 = torch.randn((27, 32), generator=g) * 0.1
+    b5 = torch.randn(1, generator=g)
+    dout = torch.randn((N, D0, D1, D2), generator=g)
+    dz0 = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    D = _dev(x=x, w0=w0, b0=b0, a=a, w5=w5, b5=b5, dout=dout, dz0=dz0)
+
+    # input layer forward
+    y = torch.empty((N, D0, D1, D2, 32), dtype=torch.bfloat16, device="cuda")
+    nn.check(nn.lib.tspnn_conv_in_fwd(nn._p(D["x"]), N, D0, D1, D2, nn._p(D["w0"]),
+                                      nn._p(D["b0"]), nn._p(y), nn._s()))
+    ref = torch.relu(OC.conv(x.double()[..., None], w0.double()[:, :, None], b0.double()))
+    _close_bf16(y, ref)
+
+    # output layer forward with the residual
+    out = torch.empty((N, D0, D1, D2), device="cuda")
+    nn.check(nn.lib.tspnn_conv_out_fwd(nn._p(D["a"]), N, D0, D1, D2, nn._p(D["w5"]),
+                                       nn._p(D["b5"]), nn._p(D["x"]), nn._p(out), nn._s()))
+    ref = x.double() + OC.conv(a.double(), w5.double()[:, None, :], b5.double())[..., 0]
+    assert float((out.cpu().double() - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
+
+    # output layer backward
+    ws = torch.empty(int(nn.lib.tspnn_conv_workspace(N, D0, D1, D2)) // 4 + 1, device="cuda")
+    dw5 = torch.empty((27, 32), device="cuda")
+    db5 = torch.empty(1, device="cuda")
+    dz = torch.empty((N, D0, D1, D2, 32), dtype=torch.bfloat16, device="cuda")
+    nn.check(nn.lib.tspnn_conv_out_bwd(nn._p(D["a"]), nn._p(D["dout"]), N, D0, D1, D2,
+                                       nn._p(D["w5"]), nn._p(dw5), nn._p(db5), nn._p(dz),
+                                       nn._p(ws), nn._s()))
+    ar = a.double().clone().requires_grad_(True)
+    wr = w5.double()[:, None, :].clone().requires_grad_(True)
+    br = b5.double().clone().requires_grad_(True)
+    (OC.conv(ar, wr, br)[..., 0] * dout.double()).sum().backward()
+    for got, ref in ((dw5, wr.grad[:, 0, :]), (db5, br.grad)):
+        assert float((got.cpu().double() - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
+    _close_bf16(dz, ar.grad * (a.double() > 0))
+
+    # input layer weight gradient
+    dw0 = torch.empty((27, 32), device="cuda")
+    db0 = torch.empty(32, device="cuda")
+    nn.check(nn.lib.tspnn_conv_in_bwd_weight(nn._p(D["x"]), nn._p(D["dz0"]), N, D0, D1, D2,
+                                             nn._p(dw0), nn._p(db0), nn._p(ws), nn._s()))
+    wr = torch.zeros((27, 32, 1), dtype=torch.float64, requires_grad=True)
+    br = torch.zeros(32, dtype=torch.float64, requires_grad=True)
+    (OC.conv(x.double()[..., None], wr, br) * dz0.double()).sum().backward()
+    for got, ref in ((dw0, wr.grad[:, :, 0]), (db0, br.grad)):
+        assert float((got.cpu().double() - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
+
+
+def test_cnn_end_to_end_gradient(nn):
+    """Whole-network gradient against an FP64 replica that rounds weights and
+    activations to bfloat16 at the same points as the kernels."""
+    N, D0, D1, D2 = 2, 6, 5, 32
+    net = nn.CNN(device="cuda", seed=11, scale_out=1.0)
+    g = torch.Generator().manual_seed(6)
+    x = torch.randn((N, D0, D1, D2), generator=g)
+    dout = torch.randn((N, D0, D1, D2), generator=g)
+    D = _dev(x=x, dout=dout)
+    out = net.forward(D["x"])
+    grads = net.backward(D["dout"])
+
+    params = [p.detach().cpu().double().clone().requires_grad_(True) for p in net.parameters()]
+    w0, b0 = params[0], params[1]
+    wh, bh = params[2:6], params[6:10]
+    w5, b5 = params[10], params[11]
+
+    def bfr(t):  # round to bf16 in the forward pass, identity gradient
+        return t + (t.to(torch.bfloat16).double() - t).detach()
+
+    a = bfr(torch.relu(OC.conv(x.double()[..., None], w0[:, :, None], b0)))
+    for w, b in zip(wh, bh):
+        a = bfr(torch.relu(OC.conv(a, bfr(w), b)))
+    ref_out = x.double() + OC.conv(a, w5[:, None, :], b5)[..., 0]
+    (ref_out * dout.double()).sum().backward()
+    assert float((out.cpu().double() - ref_out).abs().max()) <= 1e-2 * float(ref_out.abs().max())
+    for k, (gg, p) in enumerate(zip(grads, params)):
+        gc, gr = gg.cpu().double().reshape(-1), p.grad.reshape(-1)
+        cos = float(gc @ gr / (gc.norm() * gr.norm() + 1e-30))
+        assert cos > 0.995, (k, cos)

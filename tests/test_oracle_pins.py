@@ -317,3 +317,33 @@ def test_degenerate_los_against_brute_force(ora):
         b2 = np.sum(np.cross(starts[i], n[i]) ** 2)
         ref = 2 * math.sqrt(max(4 - b2, 0)) - 2 * math.sqrt(max(0.25 - b2, 0))
         assert abs(tot - ref) < 1e-12, i
+
+
+# ------------------------------------------------------------ data-term gradient
+
+def test_data_gradient_equals_adjoint_of_residual_and_fd(ora):
+    """The on-the-fly data-term gradient g_v = 2 F^T(F rho - y) at sampled voxels
+    equals (a) the stored-list adjoint of the residual and (b) central finite
+    differences of the FP64 loss (exact up to rounding: the loss is quadratic)."""
+    w = W.tiny(noise=0)
+    v = w.views
+    rng = np.random.default_rng(17)
+    V = w.grid.size
+    rho = rng.uniform(0.0, 1.0, V)
+    s, d = _rays_of(ora, v)
+    y = rng.uniform(0.0, 5.0, len(s))
+    tr = ora.trace(w.grid.arrays(), s, d)
+    resid = ora.forward(tr, rho) - y
+    full = 2.0 * ora.adjoint(tr, resid, V)
+    targets = rng.choice(np.nonzero(full)[0], 12, replace=False)
+    g, bound, n = ora.cone_data_grad(w.grid.arrays(), v.pos, v.look, v.up, v.fov_deg, v.H, v.W,
+                                     rho, y, targets)
+    assert np.allclose(g, full[targets], rtol=1e-12, atol=1e-12)
+    assert np.all(bound >= np.abs(g)) and n < len(s)
+    h = 1e-3
+    for k, t in enumerate(targets[:4]):
+        e = np.zeros(V)
+        e[t] = h
+        lp = np.sum((ora.forward(tr, rho + e) - y) ** 2)
+        lm = np.sum((ora.forward(tr, rho - e) - y) ** 2)
+        assert abs((lp - lm) / (2 * h) - g[k]) <= 1e-8 * max(1.0, abs(g[k]))
