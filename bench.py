@@ -13,7 +13,10 @@ time is reported separately.
 
 Prints ONE JSON line: rays/s of forward+adjoint as `value`, segments/s and
 per-kernel roofline fractions alongside, the CPU FP64 oracle timed on the host
-cores on a bounded sample, and the trace time.
+cores, and the trace time.  Unless --quick, it also measures (as extra fields)
+the on-the-fly mode on the Large workload (batch 4, no segment storage), the
+stored-list path on the Differentiation workload, and the learned warm start
+(projector calls to reach the plain solver's residual, 200 held-out phantoms).
 """
 import argparse
 import json
@@ -36,6 +39,8 @@ def _args():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--workload", default="medium", choices=["medium", "tiny", "learned", "diff"])
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--quick", action="store_true",
+                   help="only the Medium forward+adjoint line (for profiler runs)")
     p.add_argument("--calib-copy", action="store_true",
                    help="after timing, run a plain 1 GiB device copy (counter calibration)")
     p.add_argument("--cpu-views", type=int, default=30,
@@ -73,6 +78,119 @@ def cpu_baseline(w, n_views):
         "trace_s": t1 - t0, "forward_s": t2 - t1, "adjoint_s": t3 - t2,
         "host": platform.processor() or platform.machine(),
     }
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _time_ms(fn, reps, warm=1):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def extra_large_onthefly():
+    """Large workload on the fly, batch 4: count pass (steps 1-3 without
+    storage), forward and adjoint per launch."""
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.projector import Projector
+    w = W.large()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Projector(w.grid, views=w.views, mode="onthefly")
+    torch.cuda.synchronize()
+    count_s = time.perf_counter() - t0
+    inf = P.info()
+    R, V, S, B = inf["n_rays"], inf["n_voxels"], inf["n_segments"], 4
+    rho = torch.from_numpy(w.rho).cuda()
+    y = P.forward(rho)
+    x = torch.empty_like(rho)
+    f_ms = _time_ms(lambda: P.forward(rho, out=y), 3)
+    a_ms = _time_ms(lambda: P.backproject(y, "atomic", out=x), 2)
+    alg = 4 * B * V + 4 * B * R
+    P.close()
+    return {"workload": f"large: grid {P.shape}, {w.views.n_views} cone views "
+                        f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch {B}",
+            "count_s": count_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
+            "forward_rays_per_s": B * R / f_ms * 1e3, "forward_segments_per_s": B * S / f_ms * 1e3,
+            "adjoint_rays_per_s": B * R / a_ms * 1e3, "adjoint_segments_per_s": B * S / a_ms * 1e3,
+            "forward_hbm_frac": alg / f_ms / 1e6 / HBM_PEAK_GBS,
+            "note": "FP64 tracing per launch; the HBM roof does not bind (4BV + 4BR bytes)"}
+
+
+def extra_diff_csr():
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.projector import Projector
+    w = W.diff()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Projector(w.grid, views=w.views)
+    torch.cuda.synchronize()
+    trace_s = time.perf_counter() - t0
+    inf = P.info()
+    R, V, S = inf["n_rays"], inf["n_voxels"], inf["n_segments"]
+    rho = torch.from_numpy(w.rho).cuda()
+    y = P.forward(rho)
+    x = torch.empty_like(rho)
+    f_ms = _time_ms(lambda: P.forward(rho, out=y), 10)
+    a_ms = _time_ms(lambda: P.backproject(y, "deterministic", out=x), 10)
+    fb, ab = 8 * S + 8 * R + 4 * R + 4 * V, 8 * S + 8 * V + 4 * V + 4 * R
+    P.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"diff: grid {P.shape}, {w.views.n_views} cone views "
+                        f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch 1",
+            "trace_s": trace_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
+            "rays_per_s": R / (f_ms + a_ms) * 1e3, "segments_per_s": S / (f_ms + a_ms) * 1e3,
+            "forward_hbm_frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
+            "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS}
+
+
+def extra_learned(epochs=6):
+    import numpy as np
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.learned import WarmStart
+    from paper_2608_16960_amd.projector import Projector
+    g, v = W.learned_geometry()
+    P = Projector(g, views=v)
+    ws = WarmStart(P, k0=2, K=60)
+    train = torch.from_numpy(W.learned_phantoms(g, 2000, seed=6)).cuda()
+    xs = []
+    for b0 in range(0, train.shape[0], 8):
+        xs.append(ws.inputs(ws.measure(train[b0:b0 + 8]))[0])
+    x_in = torch.cat(xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = ws.fit(x_in, train, epochs=epochs, batch=8, lr=2e-3)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del x_in, train
+    res = ws.evaluate(torch.from_numpy(W.learned_phantoms(g, 200, seed=7)).cuda())
+    warm = np.array(res["warm_calls"])
+    plain = np.array(res["plain_calls"])
+    P.close()
+    return {"workload": "learned: grid (64, 32, 64), 64 cone views 256x256; 2000 training and "
+                        "200 held-out phantoms",
+            "plain_calls_median": float(np.median(plain)),
+            "warm_calls_median": float(np.median(warm)),
+            "warm_calls_p90": float(np.percentile(warm, 90)), "warm_calls_max": int(warm.max()),
+            "fallback_rate": float(np.mean(res["fallback"])),
+            "reduction": float(np.median(plain) / np.median(warm)),
+            "train_epochs": epochs, "train_s": train_s, "train_mse_last": hist[-1]}
 
 
 def main():
@@ -139,6 +257,8 @@ def main():
     }
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
+    from paper_2608_16960_amd.profiling import read_traffic
+    traffic = read_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_medium.txt"), d["kernel"])
     line = {
         "metric": "rays/s & segments/s fwd+adjoint (%HBM roofline); projector calls to residual",
         "value": R / (ms_step / 1e3),
@@ -151,7 +271,7 @@ def main():
                    "mode": "csr + voxel-major deterministic adjoint"},
         "segments_per_s": S / (ms_step / 1e3),
         "roofline": {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": None, "kernel": d["kernel"]},
+                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": d["kernel"]},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kern.items()},
         "trace_s": trace_s,
@@ -164,7 +284,17 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         line["calib_copy_bytes_each_way"] = src.numel() * 4
+    if not a.quick:
+        del P
+        torch.cuda.empty_cache()
+        _log("large on-the-fly")
+        line["onthefly_large"] = extra_large_onthefly()
+        _log("differentiation workload")
+        line["diff_csr"] = extra_diff_csr()
+        _log("learned warm start")
+        line["learned_warm_start"] = extra_learned()
     if not a.no_cpu_baseline:
+        _log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_views)
     print(json.dumps(line))
 

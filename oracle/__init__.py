@@ -14,4 +14,4 @@ Contents
     conv3d in float64 as the library step).
 """
 from .projector import (cone_rays, trace, forward, adjoint, project, num_threads,  # noqa: F401
-                        load_library, cone_data_grad, voxel_bounding_spheres)
+                        load_library, cone_data_grad, voxel_bounding_spheres, cone_ray_ids)

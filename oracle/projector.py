@@ -49,6 +49,9 @@ def load_library():
     lib.ora_project.restype = ctypes.c_int
     lib.ora_project.argtypes = grid_args + [_dp, _dp, ctypes.c_int64, _dp, ctypes.c_int, _dp,
                                             _i64p]
+    lib.ora_cone_ray_ids.restype = None
+    lib.ora_cone_ray_ids.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                     _i64p, ctypes.c_int64, _dp, _dp]
     lib.ora_cone_data_grad.restype = ctypes.c_int
     lib.ora_cone_data_grad.argtypes = grid_args + [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int,
                                                    ctypes.c_int, _dp, _dp, ctypes.c_int, _i64p,
@@ -79,6 +82,18 @@ def cone_rays(pos, look, up, fov_deg, H, W):
     dirs = np.empty((R, 3), np.float64)
     lib.ora_cone_rays(nv, _p(pos, _dp), _p(look, _dp), _p(up, _dp), _p(fov, _dp), int(H), int(W),
                       _p(starts, _dp), _p(dirs, _dp))
+    return starts, dirs
+
+
+def cone_ray_ids(pos, look, up, fov_deg, H, W, ids):
+    """Rays with the given ids of a stack of cone views (as cone_rays)."""
+    lib = load_library()
+    pos, look, up, fov = _f64(pos), _f64(look), _f64(up), _f64(fov_deg)
+    ids = np.ascontiguousarray(ids, np.int64)
+    starts = np.empty((len(ids), 3))
+    dirs = np.empty((len(ids), 3))
+    lib.ora_cone_ray_ids(pos.shape[0], _p(pos, _dp), _p(look, _dp), _p(up, _dp), _p(fov, _dp),
+                         int(H), int(W), _p(ids, _i64p), len(ids), _p(starts, _dp), _p(dirs, _dp))
     return starts, dirs
 
 

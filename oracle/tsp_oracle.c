@@ -395,6 +395,25 @@ void ora_cone_rays(int nv, const double *pos, const double *look, const double *
     }
 }
 
+/* The rays with the given ids only (same convention as ora_cone_rays). */
+void ora_cone_ray_ids(int nv, const double *pos, const double *look, const double *up,
+                      const double *fov_deg, int H, int W, const int64_t *ids, int64_t n,
+                      double *starts, double *dirs) {
+    for (int64_t q = 0; q < n; q++) {
+        int64_t id = ids[q];
+        int v = (int)(id / ((int64_t)H * W));
+        int rem = (int)(id % ((int64_t)H * W));
+        double w[3], u[3], vv[3], d[3];
+        cone_frame(pos + 3 * v, look + 3 * v, up + 3 * v, w, u, vv);
+        cone_dir(w, u, vv, tan(fov_deg[2 * v] * M_PI / 360.0),
+                 tan(fov_deg[2 * v + 1] * M_PI / 360.0), rem / W, rem % W, H, W, d);
+        for (int k = 0; k < 3; k++) {
+            starts[3 * q + k] = pos[3 * v + k];
+            dirs[3 * q + k] = d[k];
+        }
+    }
+}
+
 /* Per-ray canonical segment counts and tie flags. */
 int ora_count(const double *rb, int nr, const double *eb, int ne, const double *ab, int na,
               const double *starts, const double *dirs, int64_t nrays, int32_t *counts,

@@ -317,10 +317,17 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
         rd.W = W;
         rd.tiles_h = (H + kTile - 1) / kTile;
         rd.tiles_w = (W + kTile - 1) / kTile;
+        rd.st = 1;
+        for (int c : {8, 4, 2})
+            if (rd.tiles_h % c == 0 && rd.tiles_w % c == 0) {
+                rd.st = c;
+                break;
+            }
         rd.n_slots = (int64_t)n_views * rd.tiles_h * rd.tiles_w * kWindow;
         rd.explicit_rays = 0;
     } else {
         rd.explicit_rays = 1;
+        rd.st = 1;
         rd.n_slots = (R + kWindow - 1) / kWindow * kWindow;
     }
 
@@ -576,8 +583,9 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
         e = launch_zero_f32(x, (int64_t)batch * g->V, st);
         if (e == hipSuccess) {
             if (g->mode == TSP_MODE_CSR)
-                e = launch_adjoint_atomic(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox,
-                                          g->d_len, g->rd.n_slots, y, batch, g->V, g->R, x, st);
+                e = launch_adjoint_atomic(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                          g->d_slice_len, g->d_vox, g->d_len, g->rd.n_slots, y,
+                                          batch, g->V, g->R, x, st);
             else
                 e = launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
         }

@@ -11,7 +11,7 @@
 // fixed summation order, bitwise reproducible.
 //
 // Atomic adjoint: ray-major like the forward, scattering len * y into x with
-// hardware float atomics.
+// hardware float atomics, merged across the wavefront per voxel first.
 
 #include "tsp_internal.h"
 
@@ -143,31 +143,54 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
     }
 }
 
+// Atomic adjoint from the ray-major store.  The 64 rays of a slice (one 16x16
+// detector window) cross similar voxels; each step the wavefront takes the
+// j-th segment of every lane, adds up the contributions that land in the same
+// voxel, and one lane per distinct voxel issues the atomic add.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ perm,
                                                      const int32_t *__restrict__ cnt_sorted,
                                                      const int64_t *__restrict__ slice_ptr,
+                                                     const int32_t *__restrict__ slice_len,
                                                      const int32_t *__restrict__ vox,
                                                      const float *__restrict__ len,
                                                      int64_t n_slots, const float *__restrict__ y,
                                                      int nb, int64_t V, int64_t R, float *x) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (slot >= n_slots) return;
-    const int32_t ray = perm[slot];
-    if (ray < 0) return;
-    const int c = cnt_sorted[slot];
-    const int64_t base = slice_ptr[slot >> 6];
+    if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
     const int lane = (int)(slot & 63);
+    const int32_t ray = perm[slot];
+    const int c = (ray >= 0) ? cnt_sorted[slot] : 0;
+    const int m = slice_len[slot >> 6];
+    const int64_t base = slice_ptr[slot >> 6];
     float yv[NB];
 #pragma unroll
-    for (int b = 0; b < NB; b++) yv[b] = (b < nb) ? y[b * R + ray] : 0.0f;
-    for (int j = 0; j < c; j++) {
-        const int64_t i = sell_index(base, lane, j);
-        const int32_t v = vox[i];
-        const float l = len[i];
+    for (int b = 0; b < NB; b++) yv[b] = (ray >= 0 && b < nb) ? y[b * R + ray] : 0.0f;
+    for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
+        int v = -1;
+        float l = 0.0f;
+        if (j < c) {
+            const int64_t i = sell_index(base, lane, j);
+            v = vox[i];
+            l = len[i];
+        }
+        float cb[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b++)
-            if (b < nb) atomicAdd(x + b * V + v, l * yv[b]);
+        for (int b = 0; b < NB; b++) cb[b] = (v >= 0) ? l * yv[b] : 0.0f;
+        uint64_t pend = __ballot(v >= 0);
+        while (pend) {
+            const int leader = __ffsll((unsigned long long)pend) - 1;
+            const int v0 = __shfl(v, leader, kWave);
+            const bool mine = (v == v0);
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                float sb = mine ? cb[b] : 0.0f;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) sb += __shfl_xor(sb, o, kWave);
+                if (lane == leader && b < nb) atomicAdd(x + b * V + v0, sb);
+            }
+            pend &= ~__ballot(mine);
+        }
     }
 }
 
@@ -234,9 +257,10 @@ hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, co
 }
 
 hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
-                                 const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                                 int64_t n_slots, const float *y, int B, int64_t V, int64_t R,
-                                 float *x, hipStream_t st) {
+                                 const int64_t *slice_ptr, const int32_t *slice_len,
+                                 const int32_t *vox, const float *len, int64_t n_slots,
+                                 const float *y, int B, int64_t V, int64_t R, float *x,
+                                 hipStream_t st) {
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * R;
@@ -244,13 +268,13 @@ hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
         const dim3 g(blocks_for(n_slots, 256));
         if (nb == 1)
             hipLaunchKernelGGL(k_adj_atomic<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
         else if (nb == 2)
             hipLaunchKernelGGL(k_adj_atomic<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
         else
             hipLaunchKernelGGL(k_adj_atomic<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

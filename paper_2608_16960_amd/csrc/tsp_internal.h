@@ -25,6 +25,7 @@ struct TabDesc {
 // Where rays come from: cone views (frames) or explicit arrays.
 struct RayDesc {
     int n_views, H, W, tiles_h, tiles_w;
+    int st;                // supertile side in tiles (divides tiles_h and tiles_w)
     const double *frames;  // per view 16 doubles: pos(3) w(3) u(3) v(3) tan_h tan_w 0 0
     const double *starts;  // explicit: [R][3]
     const double *dirs;    // explicit: [R][3], unit
@@ -34,8 +35,10 @@ struct RayDesc {
 };
 
 // Slot -> ray id in the natural order: windows of 16x16 pixels of one view,
-// split into four 8x8 wavefront blocks; -1 for slots past the detector edge.
-// Explicit rays: slot i is ray i.
+// enumerated supertile by supertile (st x st windows, row-major inside), so
+// that consecutive windows cover a compact patch of the detector; each window
+// is split into four 8x8 wavefront blocks; -1 for slots past the detector
+// edge.  Explicit rays: slot i is ray i.
 __device__ __forceinline__ int32_t natural_ray(const RayDesc &rd, int64_t slot) {
     if (rd.explicit_rays) return (slot < rd.R) ? (int32_t)slot : -1;
     const int64_t wdw = slot / kWindow;
@@ -43,7 +46,10 @@ __device__ __forceinline__ int32_t natural_ray(const RayDesc &rd, int64_t slot) 
     const int per_view = rd.tiles_h * rd.tiles_w;
     const int view = (int)(wdw / per_view);
     const int t = (int)(wdw % per_view);
-    const int ti = t / rd.tiles_w, tj = t % rd.tiles_w;
+    const int st2 = rd.st * rd.st, sw = rd.tiles_w / rd.st;
+    const int sidx = t / st2, inner = t % st2;
+    const int ti = (sidx / sw) * rd.st + inner / rd.st;
+    const int tj = (sidx % sw) * rd.st + inner % rd.st;
     const int w = lane >> 6, l = lane & 63;
     const int i = ti * kTile + (w >> 1) * 8 + (l >> 3);
     const int j = tj * kTile + (w & 1) * 8 + (l & 7);
@@ -105,9 +111,10 @@ hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, co
                               int64_t V, const float *y, int B, int64_t R, float *x,
                               hipStream_t st);
 hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
-                                 const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                                 int64_t n_slots, const float *y, int B, int64_t V, int64_t R,
-                                 float *x, hipStream_t st);
+                                 const int64_t *slice_ptr, const int32_t *slice_len,
+                                 const int32_t *vox, const float *len, int64_t n_slots,
+                                 const float *y, int B, int64_t V, int64_t R, float *x,
+                                 hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
 

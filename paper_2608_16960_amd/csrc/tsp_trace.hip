@@ -88,33 +88,33 @@ struct FillVis {
     }
 };
 
+// NB == 1: rho is [V]; NB == 4: rho is voxel-major [V][4] (one 16-byte gather
+// per segment serves the whole batch).
 template <int NB>
 struct FwdVis {
     const float *rho;
-    int64_t V;
-    int nb;
     float acc[NB];
     __device__ void seg(int v, double l) {
         const float lf = (float)l;
-#pragma unroll
-        for (int b = 0; b < NB; b++)
-            if (b < nb) acc[b] = fmaf(lf, rho[b * V + v], acc[b]);
+        if (NB == 1) {
+            acc[0] = fmaf(lf, rho[v], acc[0]);
+        } else {
+            const float4 r = reinterpret_cast<const float4 *>(rho)[v];
+            acc[0] = fmaf(lf, r.x, acc[0]);
+            acc[1] = fmaf(lf, r.y, acc[1]);
+            acc[2] = fmaf(lf, r.z, acc[2]);
+            acc[3] = fmaf(lf, r.w, acc[3]);
+        }
     }
 };
 
-template <int NB>
-struct AdjVis {
-    float *x;
-    int64_t V;
-    int nb;
-    float yv[NB];
-    __device__ void seg(int v, double l) {
-        const float lf = (float)l;
-#pragma unroll
-        for (int b = 0; b < NB; b++)
-            if (b < nb) atomicAdd(x + b * V + v, lf * yv[b]);
-    }
-};
+// Workgroups are dispatched to the 8 XCDs round-robin; this remaps block b so
+// that each XCD walks a contiguous run of windows (consecutive windows cover
+// a compact detector patch, whose rays share voxels in that XCD's L2).
+__device__ __forceinline__ int64_t xcd_window(int64_t nwin) {
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
 
 // ---------------------------------------------------------------- kernels
 
@@ -195,16 +195,15 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
     extern __shared__ double lds[];
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
-    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (slot >= rd.n_slots) return;
+    const int64_t win = xcd_window(rd.n_slots / kWindow);
+    if (win >= rd.n_slots / kWindow) return;  // padding blocks of the remapped grid
+    const int64_t slot = win * kWindow + threadIdx.x;
     const int32_t ray = natural_ray(rd, slot);
     if (ray < 0) return;
     V3 x, n;
     ray_of(rd, ray, x, n);
     FwdVis<NB> vis;
     vis.rho = rho;
-    vis.V = V;
-    vis.nb = nb;
 #pragma unroll
     for (int b = 0; b < NB; b++) vis.acc[b] = 0.0f;
     trace_ray(T, x, n, vis);
@@ -213,6 +212,18 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
         if (b < nb) y[b * rd.R + ray] = vis.acc[b];
 }
 
+__device__ __forceinline__ float wave_sum_f(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// On-the-fly adjoint with wavefront-merged atomics into x ([V] for one object,
+// voxel-major [V][4] for a batch).  Rays of one wavefront
+// (an 8x8 pixel block) cross nearly the same voxels in the same order, so the
+// wavefront advances all its rays one canonical segment per step (a uniform
+// loop) and, per step, adds up the contributions of lanes that hit the same
+// voxel before a single lane issues the atomic add.
 template <int NB>
 __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
                                                       const float *y, int nb, int64_t V,
@@ -220,24 +231,48 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
     extern __shared__ double lds[];
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
-    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (slot >= rd.n_slots) return;
+    const int64_t win = xcd_window(rd.n_slots / kWindow);
+    if (win >= rd.n_slots / kWindow) return;  // whole padding blocks of the remapped grid
+    const int64_t slot = win * kWindow + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const int32_t ray = natural_ray(rd, slot);
-    if (ray < 0) return;
-    AdjVis<NB> vis;
-    vis.x = x_out;
-    vis.V = V;
-    vis.nb = nb;
+    float yv[NB];
     bool any = false;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        vis.yv[b] = (b < nb) ? y[b * rd.R + ray] : 0.0f;
-        any |= (vis.yv[b] != 0.0f);
+        yv[b] = (ray >= 0 && b < nb) ? y[b * rd.R + ray] : 0.0f;
+        any |= (yv[b] != 0.0f);
     }
-    if (!any) return;  // a zero measurement contributes nothing
-    V3 x, n;
-    ray_of(rd, ray, x, n);
-    trace_ray(T, x, n, vis);
+    Walker w;
+    bool alive = false;
+    if (ray >= 0 && any) {  // a zero measurement contributes nothing
+        V3 x, n;
+        ray_of(rd, ray, x, n);
+        alive = w.init(T, x, n);
+    }
+    while (__any(alive)) {  // uniform over the wavefront
+        int v = -1;
+        double l = 0.0;
+        if (alive) {
+            alive = w.next(T, v, l);
+            if (!alive) v = -1;
+        }
+        float c[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) c[b] = (v >= 0) ? (float)l * yv[b] : 0.0f;
+        uint64_t pend = __ballot(v >= 0);
+        while (pend) {
+            const int leader = __ffsll((unsigned long long)pend) - 1;
+            const int v0 = __shfl(v, leader, kWave);
+            const bool mine = (v == v0);
+#pragma unroll
+            for (int b = 0; b < NB; b++) {  // x_out: [V] (NB 1) or voxel-major [V][4]
+                const float sb = wave_sum_f(mine ? c[b] : 0.0f);
+                if (lane == leader && b < nb) atomicAdd(x_out + (int64_t)v0 * NB + b, sb);
+            }
+            pend &= ~__ballot(mine);
+        }
+    }
 }
 
 __global__ void k_rays(RayDesc rd, double *starts, double *dirs) {
@@ -277,48 +312,84 @@ hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
     return hipGetLastError();
 }
 
+// [B][V] <-> voxel-major [V][4] for batch chunks of up to 4 objects
+__global__ void k_to_vmajor(const float *src, int nb, int64_t V, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * 4) return;
+    const int b = (int)(i & 3);
+    dst[i] = (b < nb) ? src[(int64_t)b * V + (i >> 2)] : 0.0f;
+}
+
+__global__ void k_from_vmajor(const float *src, int nb, int64_t V, float *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * nb) return;
+    const int64_t v = i % V;
+    const int b = (int)(i / V);
+    dst[i] = src[v * 4 + b];
+}
+
+__global__ void k_zero4(float *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+inline unsigned remapped_grid(int64_t n_slots) {  // windows, padded to a multiple of 8
+    const int64_t nw = n_slots / kWindow;
+    return (unsigned)((nw + 7) / 8 * 8);
+}
+
 hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *rho, int B, int64_t V, float *y, hipStream_t st) {
     const size_t sh = T.n_tab * sizeof(double);
+    const dim3 grid(remapped_grid(rd.n_slots));
+    float *vm = nullptr;
+    if (B > 1) {
+        hipError_t e = hipMallocAsync((void **)&vm, (size_t)V * 4 * sizeof(float), st);
+        if (e != hipSuccess) return e;
+    }
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *r = rho + (int64_t)b0 * V;
         float *yy = y + (int64_t)b0 * rd.R;
-        if (nb == 1)
-            hipLaunchKernelGGL(k_otf_forward<1>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, r, nb, V, yy);
-        else if (nb == 2)
-            hipLaunchKernelGGL(k_otf_forward<2>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, r, nb, V, yy);
-        else
-            hipLaunchKernelGGL(k_otf_forward<4>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, r, nb, V, yy);
+        if (B == 1) {
+            hipLaunchKernelGGL(k_otf_forward<1>, grid, dim3(256), sh, st, T, tab, rd, r, nb, V, yy);
+        } else {
+            hipLaunchKernelGGL(k_to_vmajor, dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st,
+                               r, nb, V, vm);
+            hipLaunchKernelGGL(k_otf_forward<4>, grid, dim3(256), sh, st, T, tab, rd, vm, nb, V,
+                               yy);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return vm ? hipFreeAsync(vm, st) : hipSuccess;
 }
 
+// x must be zero on entry for B == 1 (the caller clears it).
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *y, int B, int64_t V, float *x, hipStream_t st) {
     const size_t sh = T.n_tab * sizeof(double);
+    const dim3 grid(remapped_grid(rd.n_slots));
+    if (B == 1) {
+        hipLaunchKernelGGL(k_otf_adjoint<1>, grid, dim3(256), sh, st, T, tab, rd, y, 1, V, x);
+        return hipGetLastError();
+    }
+    float *vm = nullptr;
+    hipError_t e = hipMallocAsync((void **)&vm, (size_t)V * 4 * sizeof(float), st);
+    if (e != hipSuccess) return e;
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
         float *xx = x + (int64_t)b0 * V;
-        if (nb == 1)
-            hipLaunchKernelGGL(k_otf_adjoint<1>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, yy, nb, V, xx);
-        else if (nb == 2)
-            hipLaunchKernelGGL(k_otf_adjoint<2>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, yy, nb, V, xx);
-        else
-            hipLaunchKernelGGL(k_otf_adjoint<4>, dim3(grid_of(rd.n_slots)), dim3(256), sh, st, T,
-                               tab, rd, yy, nb, V, xx);
-        hipError_t e = hipGetLastError();
+        hipLaunchKernelGGL(k_zero4, dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st, vm,
+                           4 * V);
+        hipLaunchKernelGGL(k_otf_adjoint<4>, grid, dim3(256), sh, st, T, tab, rd, yy, nb, V, vm);
+        hipLaunchKernelGGL(k_from_vmajor, dim3((unsigned)((nb * V + 255) / 256)), dim3(256), 0, st,
+                           vm, nb, V, xx);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    return hipFreeAsync(vm, st);
 }
 
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st) {

@@ -146,78 +146,33 @@ TSP_HD double plane_t(const Tab &T, int k, const V3 &x, const V3 &n,
     return (nm != 0.0) ? -xm / nm : lo;
 }
 
-// Walk one ray; calls vis.seg(voxel, length) once per canonical segment in
-// increasing distance.
-template <class Vis>
-TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
-    const int nr = T.nr, ne = T.ne, na = T.na, np = T.np;
-    const double xx = x.x * x.x + x.y * x.y + x.z * x.z;
-    const double xn = x.x * n.x + x.y * n.y + x.z * n.z;
-    const double cx = x.y * n.z - x.z * n.y;
-    const double cy = x.z * n.x - x.x * n.z;
-    const double cz = x.x * n.y - x.y * n.x;  // (x cross n)_z, constant along the ray
-    const double b2 = cx * cx + cy * cy + cz * cz;
-    const double Ro = T.rb[nr];
-    const double tc = -xn;
-    if (!(tc > 0.0) || !(b2 < Ro * Ro)) return;  // moving away, or misses the grid
-    const double b = sqrt(b2);
-    const double hch = sqrt((Ro - b) * (Ro + b));
-    const double tin = tc - hch, tout = tc + hch;
-
-    // ---------------- radial stream (Eq. 11)
-    const int kb = count_le(T.rb, nr + 1, b);  // shells kb..nr-1 are crossed twice
-    int ir = nr - 1;
-    int rk = nr - 1;
-    int rstage;  // 0 inbound, 1 outbound, 2 next event is the exit at tout
+// Resumable walk along one ray.  init() sets up the three crossing streams;
+// each next() call advances the merge until the next canonical segment is
+// complete and returns it (false once the ray has left the grid).  Keeping
+// the walk resumable lets a wavefront advance all its rays one segment at a
+// time (see the on-the-fly adjoint).
+struct Walker {
+    // ray
+    V3 x, n;
+    double xx, xn, b, tc, tin, tout, ts;
+    // radial stream (Eq. 11)
+    int kb, ir, rk, rstage;  // rstage: 0 inbound, 1 outbound, 2 next event is the exit
     double t_r;
-    if (kb <= nr - 1) {
-        rstage = 0;
-        t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
-    } else {
-        rstage = 2;
-        t_r = tout;
-    }
+    // elevation stream (Eq. 12): estage 0 first run, 1 second run,
+    // 3 jump pending at tc (ray through the origin), 2 done
+    int ie, ie_out, estage, etgt;
+    double elo, ehi, t_e, elast;
+    bool two;
+    // azimuth stream (Eq. 13)
+    int ia, ia_out, aleft, adir;
+    bool ajump;
+    double t_a, alast;
+    // merge state
+    double tcur, plen;
+    int pv;
+    bool gap, finished;
 
-    // ---------------- classification at entry and exit of the outer sphere
-    const V3 pin = {x.x + n.x * tin, x.y + n.y * tin, x.z + n.z * tin};
-    const V3 pout = {x.x + n.x * tout, x.y + n.y * tout, x.z + n.z * tout};
-    const double rin = sqrt(pin.x * pin.x + pin.y * pin.y + pin.z * pin.z);
-    const double rout = sqrt(pout.x * pout.x + pout.y * pout.y + pout.z * pout.z);
-    int ie = class_e(T, pin.z / rin);
-    const int ie_out = class_e(T, pout.z / rout);
-    double phi_in, phi_out;
-    int ia = class_a(T, pin.x, pin.y, &phi_in);
-    const int ia_out = class_a(T, pout.x, pout.y, &phi_out);
-
-    // ---------------- elevation stream (Eq. 12)
-    // estage: 0 first run, 1 second run, 3 jump pending at tc (ray through the
-    // origin: the colatitude jumps from theta to pi - theta), 2 done.
-    int estage = 0, etgt;
-    double elo = tin, ehi = tout, ts = 0.0;
-    bool two = false;
-    if (b2 == 0.0) {
-        etgt = ie;
-        estage = (ie_out != ie) ? 3 : 2;
-    } else {
-        const double den = n.z * xn - x.z;
-        const double num = x.z * xn - n.z * xx;
-        if (den != 0.0) {
-            ts = num / den;
-            two = (ts > tin) && (ts < tout);
-        }
-        if (two) {
-            const V3 ps = {x.x + n.x * ts, x.y + n.y * ts, x.z + n.z * ts};
-            const double rs = sqrt(ps.x * ps.x + ps.y * ps.y + ps.z * ps.z);
-            etgt = class_e(T, ps.z / rs);
-            ehi = ts;
-        } else {
-            etgt = ie_out;
-        }
-    }
-    double t_e = INFINITY;
-    double elast = tin;
-    // compute the next elevation event (or INFINITY)
-    auto next_e = [&]() {
+    TSP_HD void next_e(const Tab &T) {
         for (;;) {
             if (estage == 0 || estage == 1) {
                 if (ie != etgt) {
@@ -244,59 +199,148 @@ TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
             t_e = INFINITY;
             return;
         }
-    };
-    next_e();
-
-    // ---------------- azimuth stream (Eq. 13)
-    int aleft = 0, adir = 0;
-    bool ajump = false;
-    double t_a = INFINITY;
-    double alast = tin;
-    if (cz != 0.0) {
-        adir = (cz > 0.0) ? 1 : -1;
-        int cnt = (adir > 0) ? (ia_out - ia + np) % np : (ia - ia_out + np) % np;
-        double dph = (adir > 0) ? phi_out - phi_in : phi_in - phi_out;
-        dph = fmod(dph, kTwoPi);
-        if (dph < 0) dph += kTwoPi;
-        if (dph > kPi) {
-            cnt = 0;  // the sweep is tiny and rounding reversed it
-        } else if (cnt == 0 && dph > 0.0) {
-            // Same region at both ends.  A region wider than pi can be left
-            // and re-entered the other way round: then every plane is crossed.
-            double rel = fmod(phi_in - T.ab0, kTwoPi);
-            if (rel < 0) rel += kTwoPi;
-            const double edge = (adir > 0) ? ((ia + 1 <= na) ? T.ab[ia + 1] : kTwoPi) : T.ab[ia];
-            const double dist = (adir > 0) ? edge - rel : rel - edge;
-            if (dph > dist) cnt = np;
-        }
-        aleft = cnt;
-    } else {
-        const double nxy2 = n.x * n.x + n.y * n.y;
-        if (nxy2 > 0.0) {  // the xy-projection passes through the axis: azimuth jumps by pi
-            const double tax = -(x.x * n.x + x.y * n.y) / nxy2;
-            if (tax > tin && tax < tout && ia_out != ia) {
-                ajump = true;
-                t_a = tax;
-            }
-        }
     }
-    auto next_a = [&]() {
+
+    TSP_HD void next_a(const Tab &T) {
         if (aleft > 0) {
-            const int k = (adir > 0) ? ((ia + 1) % np) : ia;
+            const int k = (adir > 0) ? ((ia + 1) % T.np) : ia;
             const double lo = fmax(alast, tin);
             t_a = fmin(fmax(plane_t(T, k, x, n, lo), lo), tout);
         } else if (!ajump) {
             t_a = INFINITY;
         }
-    };
-    next_a();
+    }
 
-    // ---------------- merge
-    double tcur = tin;
-    int pv = -1;
-    double plen = 0.0;
-    bool gap = false;
-    for (;;) {
+    // Returns false when the ray misses the grid (nothing to walk).
+    TSP_HD bool init(const Tab &T, const V3 &x_, const V3 &n_) {
+        x = x_;
+        n = n_;
+        finished = true;
+        pv = -1;
+        plen = 0.0;
+        gap = false;
+        const int nr = T.nr, np = T.np;
+        xx = x.x * x.x + x.y * x.y + x.z * x.z;
+        xn = x.x * n.x + x.y * n.y + x.z * n.z;
+        const double cx = x.y * n.z - x.z * n.y;
+        const double cy = x.z * n.x - x.x * n.z;
+        const double cz = x.x * n.y - x.y * n.x;  // (x cross n)_z, constant along the ray
+        const double b2 = cx * cx + cy * cy + cz * cz;
+        const double Ro = T.rb[nr];
+        tc = -xn;
+        if (!(tc > 0.0) || !(b2 < Ro * Ro)) return false;  // moving away, or misses
+        b = sqrt(b2);
+        const double hch = sqrt((Ro - b) * (Ro + b));
+        tin = tc - hch;
+        tout = tc + hch;
+
+        // radial stream
+        kb = count_le(T.rb, nr + 1, b);  // shells kb..nr-1 are crossed twice
+        ir = nr - 1;
+        rk = nr - 1;
+        if (kb <= nr - 1) {
+            rstage = 0;
+            t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+        } else {
+            rstage = 2;
+            t_r = tout;
+        }
+
+        // classification at entry and exit of the outer sphere
+        const V3 pin = {x.x + n.x * tin, x.y + n.y * tin, x.z + n.z * tin};
+        const V3 pout = {x.x + n.x * tout, x.y + n.y * tout, x.z + n.z * tout};
+        const double rin = sqrt(pin.x * pin.x + pin.y * pin.y + pin.z * pin.z);
+        const double rout = sqrt(pout.x * pout.x + pout.y * pout.y + pout.z * pout.z);
+        ie = class_e(T, pin.z / rin);
+        ie_out = class_e(T, pout.z / rout);
+        double phi_in, phi_out;
+        ia = class_a(T, pin.x, pin.y, &phi_in);
+        ia_out = class_a(T, pout.x, pout.y, &phi_out);
+
+        // elevation stream
+        estage = 0;
+        elo = tin;
+        ehi = tout;
+        ts = 0.0;
+        two = false;
+        if (b2 == 0.0) {
+            etgt = ie;
+            estage = (ie_out != ie) ? 3 : 2;
+        } else {
+            const double den = n.z * xn - x.z;
+            const double num = x.z * xn - n.z * xx;
+            if (den != 0.0) {
+                ts = num / den;
+                two = (ts > tin) && (ts < tout);
+            }
+            if (two) {
+                const V3 ps = {x.x + n.x * ts, x.y + n.y * ts, x.z + n.z * ts};
+                const double rs = sqrt(ps.x * ps.x + ps.y * ps.y + ps.z * ps.z);
+                etgt = class_e(T, ps.z / rs);
+                ehi = ts;
+            } else {
+                etgt = ie_out;
+            }
+        }
+        t_e = INFINITY;
+        elast = tin;
+        next_e(T);
+
+        // azimuth stream
+        aleft = 0;
+        adir = 0;
+        ajump = false;
+        t_a = INFINITY;
+        alast = tin;
+        if (cz != 0.0) {
+            adir = (cz > 0.0) ? 1 : -1;
+            int cnt = (adir > 0) ? (ia_out - ia + np) % np : (ia - ia_out + np) % np;
+            double dph = (adir > 0) ? phi_out - phi_in : phi_in - phi_out;
+            dph = fmod(dph, kTwoPi);
+            if (dph < 0) dph += kTwoPi;
+            if (dph > kPi) {
+                cnt = 0;  // the sweep is tiny and rounding reversed it
+            } else if (cnt == 0 && dph > 0.0) {
+                // Same region at both ends.  A region wider than pi can be left
+                // and re-entered the other way round: then every plane is crossed.
+                double rel = fmod(phi_in - T.ab0, kTwoPi);
+                if (rel < 0) rel += kTwoPi;
+                const double edge =
+                    (adir > 0) ? ((ia + 1 <= T.na) ? T.ab[ia + 1] : kTwoPi) : T.ab[ia];
+                const double dist = (adir > 0) ? edge - rel : rel - edge;
+                if (dph > dist) cnt = np;
+            }
+            aleft = cnt;
+        } else {
+            const double nxy2 = n.x * n.x + n.y * n.y;
+            if (nxy2 > 0.0) {  // the xy-projection passes through the axis: azimuth jumps by pi
+                const double tax = -(x.x * n.x + x.y * n.y) / nxy2;
+                if (tax > tin && tax < tout && ia_out != ia) {
+                    ajump = true;
+                    t_a = tax;
+                }
+            }
+        }
+        next_a(T);
+        tcur = tin;
+        finished = false;
+        return true;
+    }
+
+    // Process one crossing event (or, once the ray has left the grid, flush
+    // the pending segment).  Returns true when a canonical segment completed
+    // (voxel, length in vout / lout).  done() tells when nothing is left.
+    TSP_HD bool step(const Tab &T, int &vout, double &lout) {
+        if (finished) {
+            if (pv >= 0) {  // the last pending segment
+                vout = pv;
+                lout = plen;
+                pv = -1;
+                return true;
+            }
+            return false;
+        }
+        const int nr = T.nr, ne = T.ne, na = T.na, np = T.np;
         double tm = t_r;
         int fam = 0;
         if (t_e < tm) {
@@ -307,15 +351,20 @@ TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
             tm = t_a;
             fam = 2;
         }
+        bool emitted = false;
         if (tm > tcur) {
-            const bool valid = (ir >= 0) && (ir < nr) && (ie >= 0) && (ie < ne) && (ia >= 0) &&
-                               (ia < na);
+            const bool valid =
+                (ir >= 0) && (ir < nr) && (ie >= 0) && (ie < ne) && (ia >= 0) && (ia < na);
             if (valid) {
                 const int v = (ir * ne + ie) * na + ia;
                 if (v == pv && !gap) {
                     plen += tm - tcur;
                 } else {
-                    if (pv >= 0) vis.seg(pv, plen);
+                    if (pv >= 0) {
+                        vout = pv;
+                        lout = plen;
+                        emitted = true;
+                    }
                     pv = v;
                     plen = tm - tcur;
                 }
@@ -326,8 +375,9 @@ TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
             tcur = tm;
         }
         if (fam == 0) {
-            if (rstage == 2) break;
-            if (rstage == 0) {
+            if (rstage == 2) {
+                finished = true;
+            } else if (rstage == 0) {
                 ir = rk - 1;
                 if (rk > kb) {
                     rk--;
@@ -354,7 +404,7 @@ TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
                 ie = (etgt < ie) ? ie - 1 : ie + 1;
             }
             elast = t_e;
-            next_e();
+            next_e(T);
         } else {
             if (ajump) {
                 ia = ia_out;
@@ -364,15 +414,33 @@ TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
                 ia = (adir > 0) ? (ia + 1) % np : (ia - 1 + np) % np;
                 aleft--;
                 alast = t_a;
-                next_a();
+                next_a(T);
             }
         }
+        return emitted;
     }
-    if (pv >= 0) vis.seg(pv, plen);
+
+    TSP_HD bool done() const { return finished && pv < 0; }
+
+    // Next canonical segment (events until one completes); false at the end.
+    TSP_HD bool next(const Tab &T, int &vout, double &lout) {
+        while (!done())
+            if (step(T, vout, lout)) return true;
+        return false;
+    }
+};
+
+// Walk one ray; calls vis.seg(voxel, length) once per canonical segment in
+// increasing distance.
+template <class Vis>
+TSP_HD void trace_ray(const Tab &T, const V3 &x, const V3 &n, Vis &vis) {
+    Walker w;
+    if (!w.init(T, x, n)) return;
+    int v;
+    double l;
+    while (!w.done())  // one crossing event per iteration, segments as they complete
+        if (w.step(T, v, l)) vis.seg(v, l);
 }
-
-// ---------------------------------------------------------------- rays
-
 
 }  // namespace core
 }  // namespace tsp

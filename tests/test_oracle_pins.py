@@ -347,3 +347,12 @@ def test_data_gradient_equals_adjoint_of_residual_and_fd(ora):
         lp = np.sum((ora.forward(tr, rho + e) - y) ** 2)
         lm = np.sum((ora.forward(tr, rho - e) - y) ** 2)
         assert abs((lp - lm) / (2 * h) - g[k]) <= 1e-8 * max(1.0, abs(g[k]))
+
+
+def test_cone_ray_ids_equal_full_generation(ora):
+    w = W.tiny()
+    v = w.views
+    s, d = _rays_of(ora, v)
+    ids = np.array([0, 5, 1023, 1024, 4095, 2222])
+    s2, d2 = ora.cone_ray_ids(v.pos, v.look, v.up, v.fov_deg, v.H, v.W, ids)
+    assert np.array_equal(s2, s[ids]) and np.array_equal(d2, d[ids])
