@@ -502,7 +502,8 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
         }
         int in_second = 0;
         e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len, ns,
-                          g->d_row_ptr, k1, v1, nullptr, nullptr, st);
+                          g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, k1, v1, nullptr, nullptr,
+                          st);
         if (e == hipSuccess)
             e = launch_radix_sort(k1, v1, k2, v2, S, bits_for(g->V), ws, &in_second, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -577,8 +578,8 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
         if (g->mode != TSP_MODE_CSR || !g->d_col_ptr)
             return fail(TSP_E_UNSUPPORTED,
                         "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
-        e = launch_adjoint_csc(g->d_col_ptr, g->d_col_ray, g->d_col_len, g->V, y, batch, g->R, x,
-                               st);
+        e = launch_adjoint_csc(g->d_col_ptr, g->d_col_ray, g->d_col_len, g->T.nr, g->T.ne,
+                               g->T.na, y, batch, g->R, x, st);
     } else {
         e = launch_zero_f32(x, (int64_t)batch * g->V, st);
         if (e == hipSuccess) {
@@ -605,7 +606,8 @@ tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, f
     if (row_ptr) e = launch_copy_i64(g->d_row_ptr, row_ptr, g->R + 1, st);
     if (e == hipSuccess && (vox || len))
         e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
-                          g->rd.n_slots, g->d_row_ptr, nullptr, nullptr, vox, len, st);
+                          g->rd.n_slots, g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, nullptr,
+                          nullptr, vox, len, st);
     if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
     return TSP_OK;
 }

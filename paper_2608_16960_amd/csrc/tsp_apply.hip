@@ -99,13 +99,15 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
                                                   const int32_t *__restrict__ col_ray,
-                                                  const float *__restrict__ col_len, int64_t V,
-                                                  const float *__restrict__ y, int nb, int64_t R,
-                                                  float *__restrict__ x) {
-    const int64_t v = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+                                                  const float *__restrict__ col_len, int nr,
+                                                  int ne, int na, const float *__restrict__ y,
+                                                  int nb, int64_t R, float *__restrict__ x) {
+    const int64_t V = (int64_t)nr * ne * na;
+    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (v >= V) return;  // uniform over the wavefront
-    const int64_t lo = col_ptr[v], hi = col_ptr[v + 1];
+    if (key >= V) return;  // uniform over the wavefront
+    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+    const int32_t v = from_angular_major(key, nr, ne, na);
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
@@ -234,22 +236,23 @@ hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
 }
 
 hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
-                              int64_t V, const float *y, int B, int64_t R, float *x,
+                              int nr, int ne, int na, const float *y, int B, int64_t R, float *x,
                               hipStream_t st) {
+    const int64_t V = (int64_t)nr * ne * na;
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * R;
         float *xx = x + (int64_t)b0 * V;
         const dim3 grid(blocks_for(V * kWave, 256));
         if (nb == 1)
-            hipLaunchKernelGGL(k_adj_csc<1>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
-                               yy, nb, R, xx);
+            hipLaunchKernelGGL(k_adj_csc<1>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
+                               ne, na, yy, nb, R, xx);
         else if (nb == 2)
-            hipLaunchKernelGGL(k_adj_csc<2>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
-                               yy, nb, R, xx);
+            hipLaunchKernelGGL(k_adj_csc<2>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
+                               ne, na, yy, nb, R, xx);
         else
-            hipLaunchKernelGGL(k_adj_csc<4>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, V,
-                               yy, nb, R, xx);
+            hipLaunchKernelGGL(k_adj_csc<4>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
+                               ne, na, yy, nb, R, xx);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

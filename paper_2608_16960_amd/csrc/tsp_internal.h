@@ -65,6 +65,20 @@ __host__ __device__ __forceinline__ int64_t sell_index(int64_t base, int lane, i
     return base + (int64_t)(j >> 2) * 256 + lane * 4 + (j & 3);
 }
 
+// Voxel (ir, ie, ia) <-> angular-major key (ie * na + ia) * nr + ir, the order
+// of the voxel-major store.
+__host__ __device__ __forceinline__ int32_t angular_major(int32_t v, int nr, int ne, int na) {
+    const int ir = v / (ne * na), ie = (v / na) % ne, ia = v % na;
+    return (ie * na + ia) * nr + ir;
+}
+__host__ __device__ __forceinline__ int32_t from_angular_major(int64_t k, int nr, int ne,
+                                                               int na) {
+    const int ir = (int)(k % nr);
+    const int64_t q = k / nr;
+    const int ia = (int)(q % na), ie = (int)(q / na);
+    return (ir * ne + ie) * na + ia;
+}
+
 // ---- launchers (tsp_trace.hip) ----
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
                         unsigned long long *total, int *maxcnt, hipStream_t st);
@@ -89,8 +103,8 @@ hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
                                  int32_t *cnt_ray, hipStream_t st);
 hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
                          const int32_t *vox, const float *len, int64_t n_slots,
-                         const int64_t *row_ptr, int32_t *keys, uint64_t *vals,
-                         int32_t *out_vox, float *out_len, hipStream_t st);
+                         const int64_t *row_ptr, int nr, int ne, int na, int32_t *keys,
+                         uint64_t *vals, int32_t *out_vox, float *out_len, hipStream_t st);
 // stable LSD radix sort of (key, val) by key (key < 2^key_bits); result lands in
 // (keys, vals) or (keys2, vals2): returns through *in_second whether it is the second.
 hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
@@ -107,8 +121,9 @@ hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
                                const int32_t *vox, const float *len, int64_t n_slots,
                                const float *rho, int B, int64_t V, int64_t R, float *y,
                                hipStream_t st);
+// col_ptr is indexed by the angular-major key; x is written in (r, e, a) order.
 hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
-                              int64_t V, const float *y, int B, int64_t R, float *x,
+                              int nr, int ne, int na, const float *y, int B, int64_t R, float *x,
                               hipStream_t st);
 hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
                                  const int64_t *slice_ptr, const int32_t *slice_len,

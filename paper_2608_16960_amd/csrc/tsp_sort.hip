@@ -10,7 +10,11 @@
 //
 // Voxel-major store: the canonical (ray-ordered) segments are sorted by voxel
 // with a stable LSD radix sort (8-bit digits), so every voxel's list keeps
-// increasing ray order and the adjoint sums it in a fixed order.
+// increasing ray order and the adjoint sums it in a fixed order.  Voxels are
+// keyed angular-major (all shells of one (e, a) cell, then the next cell): the
+// rays through consecutive lists are then a thin fan per view, so the
+// measurements they gather stay in L2 (in (r, e, a) order every shell needs
+// nearly every ray).
 
 #include "tsp_internal.h"
 
@@ -139,9 +143,9 @@ __global__ void k_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
 __global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32_t *cnt_sorted,
                                                  const int64_t *slice_ptr, const int32_t *vox,
                                                  const float *len, int64_t n_slots,
-                                                 const int64_t *row_ptr, int32_t *keys,
-                                                 uint64_t *vals, int32_t *out_vox,
-                                                 float *out_len) {
+                                                 const int64_t *row_ptr, int nr, int ne,
+                                                 int na, int32_t *keys, uint64_t *vals,
+                                                 int32_t *out_vox, float *out_len) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int32_t r = perm[slot];
@@ -155,7 +159,7 @@ __global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32
         const int32_t v = vox[i];
         const float l = len[i];
         if (keys) {
-            keys[dst + j] = v;
+            keys[dst + j] = angular_major(v, nr, ne, na);
             vals[dst + j] = (uint64_t)(uint32_t)r | ((uint64_t)__float_as_uint(l) << 32);
         }
         if (out_vox) out_vox[dst + j] = v;
@@ -295,11 +299,11 @@ hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
 
 hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
                          const int32_t *vox, const float *len, int64_t n_slots,
-                         const int64_t *row_ptr, int32_t *keys, uint64_t *vals,
-                         int32_t *out_vox, float *out_len, hipStream_t st) {
+                         const int64_t *row_ptr, int nr, int ne, int na, int32_t *keys,
+                         uint64_t *vals, int32_t *out_vox, float *out_len, hipStream_t st) {
     hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, perm,
-                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, keys, vals, out_vox,
-                       out_len);
+                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, nr, ne, na, keys, vals,
+                       out_vox, out_len);
     return hipGetLastError();
 }
 

@@ -1,0 +1,81 @@
+"""Error paths of the C ABI that need a device: state errors, the device-memory
+cap (TSP_MAX_DEVICE_BYTES) with the on-the-fly fallback, unsupported
+combinations.  Every case returns an error code; no kernel is made to fail."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2608_16960_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _geometry(N, w):
+    g = w.grid
+    arrs = [np.ascontiguousarray(a, np.float64) for a in g.arrays()]
+    gd = N.tsp_grid_desc(*g.shape, *[a.ctypes.data_as(N._dp) for a in arrs])
+    v = w.views
+    views = (N.tsp_cone_view * v.n_views)()
+    for i in range(v.n_views):
+        views[i].pos[:] = list(v.pos[i])
+        views[i].look[:] = list(v.look[i])
+        views[i].up[:] = list(v.up[i])
+        views[i].fov_deg[:] = list(v.fov_deg[i])
+        views[i].shape[:] = [v.H, v.W]
+    h = ctypes.c_void_p()
+    assert N.lib.tsp_geometry_create(ctypes.byref(gd), views, v.n_views, None, None, 0,
+                                     ctypes.byref(h)) == N.TSP_OK
+    return h, arrs
+
+
+def test_state_and_capacity_errors():
+    assert torch.cuda.is_available()
+    from paper_2608_16960_amd import native as N
+    w = W.tiny()
+    h, keep = _geometry(N, w)
+    rho = torch.from_numpy(w.rho).cuda()
+    y = torch.empty(w.views.n_rays, device="cuda")
+    x = torch.empty(w.grid.size, device="cuda")
+    s = N.stream_handle()
+    try:
+        assert N.lib.tsp_forward(h, N.ptr(rho), 1, N.ptr(y), s) == N.TSP_E_STATE
+        assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_ATOMIC, s) == \
+            N.TSP_E_STATE
+        assert N.lib.tsp_forward(h, N.ptr(rho), 0, N.ptr(y), s) == N.TSP_E_INVALID
+        os.environ["TSP_MAX_DEVICE_BYTES"] = str(200_000)  # below the segment store
+        try:
+            assert N.lib.tsp_trace(h, N.TSP_MODE_CSR, s) == N.TSP_E_NOMEM
+            assert b"TSP_MAX_DEVICE_BYTES" in N.lib.tsp_last_error()
+            assert N.lib.tsp_trace(h, N.TSP_MODE_ONTHEFLY, s) == N.TSP_OK
+        finally:
+            del os.environ["TSP_MAX_DEVICE_BYTES"]
+        assert N.lib.tsp_forward(h, N.ptr(rho), 1, N.ptr(y), s) == N.TSP_OK
+        assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_DETERMINISTIC, s) == \
+            N.TSP_E_UNSUPPORTED
+        assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_ATOMIC, s) == N.TSP_OK
+        rp = torch.empty(w.views.n_rays + 1, dtype=torch.int64, device="cuda")
+        assert N.lib.tsp_segments(h, N.ptr(rp), None, None, s) == N.TSP_E_STATE
+        assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), 7, s) == N.TSP_E_INVALID
+        info = N.tsp_info()
+        assert N.lib.tsp_query(h, ctypes.byref(info)) == N.TSP_OK
+        assert info.mode == N.TSP_MODE_ONTHEFLY and info.n_segments > 0 and info.has_csc == 0
+        # switch back to stored lists without the transposed store
+        assert N.lib.tsp_trace(h, N.TSP_MODE_CSR | N.TSP_TRACE_NO_CSC, s) == N.TSP_OK
+        assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_DETERMINISTIC, s) == \
+            N.TSP_E_UNSUPPORTED
+        torch.cuda.synchronize()
+    finally:
+        N.lib.tsp_geometry_destroy(h)
+
+
+def test_projector_falls_back_to_onthefly_adjoint():
+    """The Python layer uses the atomic adjoint in on-the-fly mode."""
+    from paper_2608_16960_amd.projector import Projector
+    w = W.tiny()
+    P = Projector(w.grid, views=w.views, mode="onthefly")
+    y = P.forward(torch.from_numpy(w.rho).cuda())
+    x = P.backproject(y)  # no error: switches to the atomic adjoint
+    assert torch.isfinite(x).all() and float(x.abs().sum()) > 0
