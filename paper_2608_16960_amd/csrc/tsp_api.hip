@@ -72,8 +72,7 @@ struct tsp_geometry {
     int64_t *d_row_ptr = nullptr;
     // voxel-major store
     int64_t *d_col_ptr = nullptr;
-    int32_t *d_col_ray = nullptr;
-    float *d_col_len = nullptr;
+    uint64_t *d_col_ent = nullptr;  // (ray, length bits) per entry
     int64_t bytes = 0;
     std::vector<std::pair<void *, int64_t>> allocs;
 };
@@ -139,8 +138,7 @@ void release_stores(tsp_geometry *g) {
     dfree_p(g, g->d_len);
     dfree_p(g, g->d_row_ptr);
     dfree_p(g, g->d_col_ptr);
-    dfree_p(g, g->d_col_ray);
-    dfree_p(g, g->d_col_len);
+    dfree_p(g, g->d_col_ent);
     g->mode = 0;
     g->S = g->max_per_ray = g->n_stored = 0;
 }
@@ -330,6 +328,10 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
         rd.st = 1;
         rd.n_slots = (R + kWindow - 1) / kWindow * kWindow;
     }
+    if (rd.n_slots >= ((int64_t)1 << 31)) {
+        tsp_geometry_destroy(g);
+        return fail(TSP_E_INVALID, "too many rays once padded to 16x16 windows (>= 2^31 slots)");
+    }
 
     auto cleanup = [&](tsp_status st) {
         tsp_geometry_destroy(g);
@@ -501,7 +503,7 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
             return s;
         }
         int in_second = 0;
-        e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len, ns,
+        e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len, ns,
                           g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, k1, v1, nullptr, nullptr,
                           st);
         if (e == hipSuccess)
@@ -514,7 +516,7 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
         }
         int32_t *ks = in_second ? k2 : k1;
         uint64_t *vs = in_second ? v2 : v1;
-        // release what the result does not live in before allocating the store
+        // the sorted values are the store: keep them, release the rest
         if (in_second) {
             dfree_p(g, k1);
             dfree_p(g, v1);
@@ -523,16 +525,21 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
             dfree_p(g, v2);
         }
         dfree_p(g, ws);
-        if ((s = dalloc_n(g, &g->d_col_ptr, g->V + 1, "column offsets")) != TSP_OK ||
-            (s = dalloc_n(g, &g->d_col_ray, S, "column rays")) != TSP_OK ||
-            (s = dalloc_n(g, &g->d_col_len, S, "column lengths")) != TSP_OK) {
+        if ((s = dalloc_n(g, &g->d_col_ptr, g->V + 1, "column offsets")) != TSP_OK) {
             free_sort();
             release_stores(g);
             return s;
         }
         e = launch_col_ptr(ks, S, g->V, g->d_col_ptr, st);
-        if (e == hipSuccess) e = launch_split_vals(vs, S, g->d_col_ray, g->d_col_len, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (in_second) {
+            v2 = nullptr;
+            dfree_p(g, k2);
+        } else {
+            v1 = nullptr;
+            dfree_p(g, k1);
+        }
+        g->d_col_ent = vs;
         free_sort();
         if (e != hipSuccess) {
             release_stores(g);
@@ -578,8 +585,8 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
         if (g->mode != TSP_MODE_CSR || !g->d_col_ptr)
             return fail(TSP_E_UNSUPPORTED,
                         "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
-        e = launch_adjoint_csc(g->d_col_ptr, g->d_col_ray, g->d_col_len, g->T.nr, g->T.ne,
-                               g->T.na, y, batch, g->R, x, st);
+        e = launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_ent, g->T.nr, g->T.ne, g->T.na, y,
+                               batch, x, st);
     } else {
         e = launch_zero_f32(x, (int64_t)batch * g->V, st);
         if (e == hipSuccess) {
@@ -605,7 +612,7 @@ tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, f
     hipError_t e = hipSuccess;
     if (row_ptr) e = launch_copy_i64(g->d_row_ptr, row_ptr, g->R + 1, st);
     if (e == hipSuccess && (vox || len))
-        e = launch_expand(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
+        e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
                           g->rd.n_slots, g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, nullptr,
                           nullptr, vox, len, st);
     if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));

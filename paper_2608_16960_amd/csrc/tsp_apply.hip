@@ -96,12 +96,52 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
 // timing, so x is bitwise reproducible.  Lanes read consecutive entries, so
 // one gather instruction touches the few cache lines that hold a patch of
 // neighbouring detector pixels.
+// Batch lane group of the slot-ordered copy of y: NB = 1, 2 or 4 values per
+// slot, loaded with one 4-, 8- or 16-byte access.
+template <int NB> struct YVec;
+template <> struct YVec<1> {
+    using T = float;
+    __device__ static float get(const T &v, int) { return v; }
+    __device__ static void set(T &v, int, float f) { v = f; }
+};
+template <> struct YVec<2> {
+    using T = float2;
+    __device__ static float get(const T &v, int b) { return b ? v.y : v.x; }
+    __device__ static void set(T &v, int b, float f) { (b ? v.y : v.x) = f; }
+};
+template <> struct YVec<4> {
+    using T = float4;
+    __device__ static float get(const T &v, int b) {
+        return b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w;
+    }
+    __device__ static void set(T &v, int b, float f) {
+        (b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w) = f;
+    }
+};
+
+// yt[s] = (y[b][natural_ray(s)] for b < nb), zero for padding slots and for
+// the unused lanes of the last group.
+template <int NB>
+__global__ __launch_bounds__(256) void k_tile_y(const RayDesc rd, const float *__restrict__ y,
+                                                 int nb, typename YVec<NB>::T *__restrict__ yt) {
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= rd.n_slots) return;
+    const int32_t r = natural_ray(rd, s);
+    typename YVec<NB>::T v;
+#pragma unroll
+    for (int b = 0; b < NB; b++) YVec<NB>::set(v, b, (r >= 0 && b < nb) ? y[b * rd.R + r] : 0.0f);
+    yt[s] = v;
+}
+
+// Deterministic adjoint: one wavefront per voxel of the voxel-major store,
+// lanes stride its entries (eight per lane in flight), fixed butterfly sum.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
-                                                  const int32_t *__restrict__ col_ray,
-                                                  const float *__restrict__ col_len, int nr,
-                                                  int ne, int na, const float *__restrict__ y,
-                                                  int nb, int64_t R, float *__restrict__ x) {
+                                                  const uint64_t *__restrict__ col_ent, int nr,
+                                                  int ne, int na,
+                                                  const typename YVec<NB>::T *__restrict__ yt,
+                                                  int nb, float *__restrict__ x) {
+    constexpr int UNR = 8;
     const int64_t V = (int64_t)nr * ne * na;
     const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
@@ -112,26 +152,24 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
     int64_t k = lo + lane;
-    for (; k + 3 * kWave < hi; k += 4 * kWave) {
-        int32_t r[4];
-        float l[4];
+    for (; k + (UNR - 1) * kWave < hi; k += UNR * kWave) {
+        uint64_t e[UNR];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            r[u] = ld_nt(col_ray + k + kWave * u);
-            l[u] = ld_nt(col_len + k + kWave * u);
+        for (int u = 0; u < UNR; u++) e[u] = __builtin_nontemporal_load(col_ent + k + kWave * u);
+#pragma unroll
+        for (int u = 0; u < UNR; u++) {
+            const typename YVec<NB>::T yv = yt[(uint32_t)e[u]];
+            const float l = __uint_as_float((uint32_t)(e[u] >> 32));
+#pragma unroll
+            for (int b = 0; b < NB; b++) acc[b] = fmaf(l, YVec<NB>::get(yv, b), acc[b]);
         }
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-#pragma unroll
-            for (int b = 0; b < NB; b++)
-                if (b < nb) acc[b] = fmaf(l[u], y[b * R + r[u]], acc[b]);
     }
     for (; k < hi; k += kWave) {
-        const int32_t r = ld_nt(col_ray + k);
-        const float l = ld_nt(col_len + k);
+        const uint64_t e = __builtin_nontemporal_load(col_ent + k);
+        const typename YVec<NB>::T yv = yt[(uint32_t)e];
+        const float l = __uint_as_float((uint32_t)(e >> 32));
 #pragma unroll
-        for (int b = 0; b < NB; b++)
-            if (b < nb) acc[b] = fmaf(l, y[b * R + r], acc[b]);
+        for (int b = 0; b < NB; b++) acc[b] = fmaf(l, YVec<NB>::get(yv, b), acc[b]);
     }
 #pragma unroll
     for (int b = 0; b < NB; b++) {
@@ -235,28 +273,40 @@ hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
     return hipSuccess;
 }
 
-hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
-                              int nr, int ne, int na, const float *y, int B, int64_t R, float *x,
+template <int NB>
+static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_ptr,
+                                const uint64_t *col_ent, int nr, int ne, int na, const float *y,
+                                int nb, float *x, void *yt, hipStream_t st) {
+    using T = typename YVec<NB>::T;
+    const int64_t V = (int64_t)nr * ne * na;
+    hipLaunchKernelGGL(k_tile_y<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, y,
+                       nb, (T *)yt);
+    hipLaunchKernelGGL(k_adj_csc<NB>, dim3(blocks_for(V * kWave, 256)), dim3(256), 0, st,
+                       col_ptr, col_ent, nr, ne, na, (const T *)yt, nb, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
+                              int nr, int ne, int na, const float *y, int B, float *x,
                               hipStream_t st) {
     const int64_t V = (int64_t)nr * ne * na;
-    for (int b0 = 0; b0 < B; b0 += 4) {
+    const int width = B >= 3 ? 4 : B;
+    void *yt = nullptr;
+    hipError_t e = hipMallocAsync(&yt, (size_t)rd.n_slots * width * sizeof(float), st);
+    if (e != hipSuccess) return e;
+    for (int b0 = 0; b0 < B && e == hipSuccess; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
-        const float *yy = y + (int64_t)b0 * R;
+        const float *yy = y + (int64_t)b0 * rd.R;
         float *xx = x + (int64_t)b0 * V;
-        const dim3 grid(blocks_for(V * kWave, 256));
         if (nb == 1)
-            hipLaunchKernelGGL(k_adj_csc<1>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
-                               ne, na, yy, nb, R, xx);
+            e = adj_csc_chunk<1>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
         else if (nb == 2)
-            hipLaunchKernelGGL(k_adj_csc<2>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
-                               ne, na, yy, nb, R, xx);
+            e = adj_csc_chunk<2>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
         else
-            hipLaunchKernelGGL(k_adj_csc<4>, grid, dim3(256), 0, st, col_ptr, col_ray, col_len, nr,
-                               ne, na, yy, nb, R, xx);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+            e = adj_csc_chunk<4>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
     }
-    return hipSuccess;
+    const hipError_t f = hipFreeAsync(yt, st);
+    return e != hipSuccess ? e : f;
 }
 
 hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,

@@ -57,6 +57,21 @@ __device__ __forceinline__ int32_t natural_ray(const RayDesc &rd, int64_t slot) 
     return (view * rd.H + i) * rd.W + j;
 }
 
+// Inverse of natural_ray inside one window: the natural slot of ray r, given
+// any slot `in_window` of the window that holds it.  The voxel-major store
+// keeps this slot rather than r, so that the adjoint gathers from a copy of y
+// in slot order, where a 128-byte line holds a 4 x 8 pixel patch instead of
+// 32 pixels of one detector row.
+__host__ __device__ __forceinline__ int64_t natural_slot(const RayDesc &rd, int64_t in_window,
+                                                         int32_t r) {
+    if (rd.explicit_rays) return r;
+    const int64_t hw = (int64_t)rd.H * rd.W;
+    const int pix = (int)(r % hw);
+    const int i = (pix / rd.W) & (kTile - 1), j = (pix % rd.W) & (kTile - 1);
+    const int lane = (((i >> 3) << 1) | (j >> 3)) * 64 + (i & 7) * 8 + (j & 7);
+    return (in_window & ~(int64_t)(kWindow - 1)) | lane;
+}
+
 // Ray-major sliced store: slice s holds 64 rays (one per lane); segment j of
 // lane l sits at slice_ptr[s] + 256 (j / 4) + 4 l + (j % 4), so each lane
 // reads four consecutive segments with one 16-byte load and a wavefront reads
@@ -101,10 +116,11 @@ hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *o
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
                                  int32_t *cnt_ray, hipStream_t st);
-hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                         const int32_t *vox, const float *len, int64_t n_slots,
-                         const int64_t *row_ptr, int nr, int ne, int na, int32_t *keys,
-                         uint64_t *vals, int32_t *out_vox, float *out_len, hipStream_t st);
+hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                         const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                         int64_t n_slots, const int64_t *row_ptr, int nr, int ne, int na,
+                         int32_t *keys, uint64_t *vals, int32_t *out_vox, float *out_len,
+                         hipStream_t st);
 // stable LSD radix sort of (key, val) by key (key < 2^key_bits); result lands in
 // (keys, vals) or (keys2, vals2): returns through *in_second whether it is the second.
 hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
@@ -112,8 +128,6 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
 size_t radix_ws_bytes(int64_t n);
 hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int64_t *col_ptr,
                           hipStream_t st);
-hipError_t launch_split_vals(const uint64_t *vals, int64_t n, int32_t *ray, float *len,
-                             hipStream_t st);
 
 // ---- launchers (tsp_apply.hip) ----
 hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
@@ -121,9 +135,12 @@ hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
                                const int32_t *vox, const float *len, int64_t n_slots,
                                const float *rho, int B, int64_t V, int64_t R, float *y,
                                hipStream_t st);
-// col_ptr is indexed by the angular-major key; x is written in (r, e, a) order.
-hipError_t launch_adjoint_csc(const int64_t *col_ptr, const int32_t *col_ray, const float *col_len,
-                              int nr, int ne, int na, const float *y, int B, int64_t R, float *x,
+// col_ptr is indexed by the angular-major key; each entry packs (natural slot
+// of the ray, length bits) as low / high 32 bits; x is written in (r, e, a)
+// order.  y is first copied into slot order (batch interleaved) in a
+// stream-ordered temporary.
+hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
+                              int nr, int ne, int na, const float *y, int B, float *x,
                               hipStream_t st);
 hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
                                  const int64_t *slice_ptr, const int32_t *slice_len,

@@ -140,7 +140,8 @@ __global__ void k_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
     if (r >= 0) cnt_ray[r] = cnt_sorted[slot];
 }
 
-__global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32_t *cnt_sorted,
+__global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t *perm,
+                                                 const int32_t *cnt_sorted,
                                                  const int64_t *slice_ptr, const int32_t *vox,
                                                  const float *len, int64_t n_slots,
                                                  const int64_t *row_ptr, int nr, int ne,
@@ -154,13 +155,14 @@ __global__ __launch_bounds__(256) void k_expand(const int32_t *perm, const int32
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
     const int64_t dst = row_ptr[r];
+    const int64_t ns = natural_slot(rd, slot, r);
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
         const int32_t v = vox[i];
         const float l = len[i];
         if (keys) {
             keys[dst + j] = angular_major(v, nr, ne, na);
-            vals[dst + j] = (uint64_t)(uint32_t)r | ((uint64_t)__float_as_uint(l) << 32);
+            vals[dst + j] = (uint64_t)(uint32_t)ns | ((uint64_t)__float_as_uint(l) << 32);
         }
         if (out_vox) out_vox[dst + j] = v;
         if (out_len) out_len[dst + j] = l;
@@ -255,14 +257,6 @@ __global__ void k_col_ptr(const int32_t *keys, int64_t n, int64_t V, int64_t *co
     col_ptr[v] = lo;
 }
 
-__global__ void k_split(const uint64_t *vals, int64_t n, int32_t *ray, float *len) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint64_t v = vals[i];
-    ray[i] = (int32_t)(uint32_t)(v & 0xffffffffull);
-    len[i] = __uint_as_float((uint32_t)(v >> 32));
-}
-
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -297,11 +291,12 @@ hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
     return hipGetLastError();
 }
 
-hipError_t launch_expand(const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                         const int32_t *vox, const float *len, int64_t n_slots,
-                         const int64_t *row_ptr, int nr, int ne, int na, int32_t *keys,
-                         uint64_t *vals, int32_t *out_vox, float *out_len, hipStream_t st) {
-    hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, perm,
+hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                         const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                         int64_t n_slots, const int64_t *row_ptr, int nr, int ne, int na,
+                         int32_t *keys, uint64_t *vals, int32_t *out_vox, float *out_len,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, rd, perm,
                        cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, nr, ne, na, keys, vals,
                        out_vox, out_len);
     return hipGetLastError();
@@ -357,13 +352,6 @@ hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int6
                           hipStream_t st) {
     hipLaunchKernelGGL(k_col_ptr, dim3(blocks_for(V + 1, 256)), dim3(256), 0, st, sorted_keys, n,
                        V, col_ptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_split_vals(const uint64_t *vals, int64_t n, int32_t *ray, float *len,
-                             hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_split, dim3(blocks_for(n, 256)), dim3(256), 0, st, vals, n, ray, len);
     return hipGetLastError();
 }
 

@@ -153,6 +153,38 @@ def test_ragged_wedge_grid(ora, dev, mode):
     _check_all(ora, g, P, s, d, rho)
 
 
+@pytest.mark.parametrize("explicit", [False, True])
+def test_batched_adjoint_chunks(ora, dev, explicit):
+    """Batches of 3, 5 and 6 (processed in groups of at most 4 objects): the
+    deterministic adjoint of each object equals, bit for bit, the adjoint of
+    that object alone, and the oracle's within the adjoint bar; ragged 16x16
+    windows, or explicit rays."""
+    g = W.Grid(np.array([2.0, 2.7, 3.1, 4.4, 6.0, 9.5]), np.array([0.3, 0.8, 1.2, 1.5708, 2.0, 2.9]),
+               np.array([-0.4, 0.3, 1.0, 1.9, 2.2, 3.0, 4.1]))
+    if explicit:
+        s, d = W.random_rays(1500, np.random.default_rng(31), r_start=(12.0, 20.0), aim=5.0)
+        P = _P()(g, rays=(s, d))
+    else:
+        pos = np.array([[20.0, 3.0, 5.0], [-4.0, 18.0, -7.0]])
+        v = W.views_at(pos, (45.0, 38.0), 37, 29, look=[0.5, -0.2, 0.1])
+        s, d = _oracle_rays(ora, v)
+        P = _P()(g, views=v)
+    tr = ora.trace(g.arrays(), s, d)
+    R, V = len(tr["counts"]), g.size
+    rng = np.random.default_rng(12)
+    for B in (3, 5, 6):
+        yy = rng.normal(size=(B, R)).astype(np.float32)
+        y_t = torch.from_numpy(yy).to(dev).reshape(B, *P.out_shape)
+        x = P.backproject(y_t, "deterministic")
+        for b in range(B):
+            assert torch.equal(x[b:b + 1], P.backproject(y_t[b:b + 1], "deterministic")), (B, b)
+        xo = ora.adjoint(tr, yy.astype(np.float64), V)
+        xg = x.reshape(B, V).cpu().numpy().astype(np.float64)
+        for b in range(B):
+            tol = FWD_RTOL * _abs_adjoint(tr, yy[b].astype(np.float64), V) + 1e-7
+            assert np.all(np.abs(xg[b] - xo[b]) <= tol), (B, b)
+
+
 def test_explicit_rays_with_degenerate_lines(ora, dev):
     """Explicit (Listing 4 style, un-normalised) rays plus hand-picked degenerate
     lines: in the equatorial plane, in an azimuth half-plane, along the polar
