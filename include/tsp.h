@@ -122,7 +122,10 @@ typedef struct tsp_geometry tsp_geometry;
  * Validates the grid (finite, strictly increasing, ranges above), the views
  * (finite, pos outside the outer sphere, fov in (0, 180), equal shapes, pos
  * != look) and the rays (finite, non-zero direction, start outside the outer
- * sphere: TSP_E_INVALID otherwise).  Uploads boundary tables and per-view
+ * sphere: TSP_E_INVALID otherwise).  Limits (TSP_E_INVALID beyond them):
+ * fewer than 2^31 voxels and 2^31 rays (after padding cone views to 16x16
+ * pixel windows), and nr + ne + 3 na <= 5627 (the boundary tables are staged
+ * in workgroup-shared memory).  Uploads boundary tables and per-view
  * frames to the current HIP device.  *out receives the new geometry, owned
  * by the caller and released with tsp_geometry_destroy.
  */

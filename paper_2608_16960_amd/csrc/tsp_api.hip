@@ -194,6 +194,9 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
     if (span > kTwoPi + 1e-12) return fail(TSP_E_INVALID, "a_b spans more than 2 pi");
     const int64_t V = (int64_t)nr * ne * na;
     if (V >= ((int64_t)1 << 31)) return fail(TSP_E_INVALID, "too many voxels (>= 2^31)");
+    if ((int64_t)nr + ne + 3 * (int64_t)na + 5 > kMaxTabDoubles)
+        return fail(TSP_E_INVALID, "grid too fine for the shared-memory boundary tables "
+                                   "(nr + ne + 3 na > 5627)");
     const double Rout = grid->r_b[nr];
 
     const bool use_views = views != nullptr;

@@ -10,6 +10,10 @@ namespace tsp {
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kWindow = 256;  // ray slots per window: one 16x16 detector tile
 constexpr int kTile = 16;
+// Boundary tables (doubles) are staged in LDS next to at most kOtfHashBytes
+// of the on-the-fly adjoint's hash table, within 64 KiB per workgroup.
+constexpr int kOtfHashBytes = 20480;
+constexpr int kMaxTabDoubles = (65536 - kOtfHashBytes) / 8;
 
 // Packed FP64 boundary tables, staged into LDS by every trace kernel.
 //   rb[nr+1]    radii

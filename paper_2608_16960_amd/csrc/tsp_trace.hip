@@ -212,29 +212,45 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
         if (b < nb) y[b * rd.R + ray] = vis.acc[b];
 }
 
-__device__ __forceinline__ float wave_sum_f(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
+// On-the-fly adjoint into x ([V] for one object, voxel-major [V][4] for a
+// batch).  The 256 rays of a window cross largely the same voxels, so the
+// workgroup first adds its contributions in a hash table in LDS (open
+// addressing on the voxel index, native LDS float adds, values stored object
+// by object so that the lanes of one add spread over the banks) and only a
+// flush issues global atomics, one per distinct voxel and object.  The rays
+// advance kOtfEvents boundary events between workgroup barriers; at a barrier
+// the table is flushed once it is more than half full, and after the last ray
+// ends.  An insertion that finds no slot within kOtfProbes probes goes
+// straight to a global atomic, so a crowded table costs speed, never
+// correctness.
+constexpr int kOtfEvents = 16;
+constexpr int kOtfProbes = 8;
+template <int NB> struct OtfHash {
+    static constexpr int kSize = NB == 1 ? 2048 : 1024;  // power of two
+    static constexpr size_t kBytes = (size_t)kSize * (1 + NB) * 4;
+    static_assert(kBytes <= kOtfHashBytes, "hash table exceeds its LDS reserve");
+};
 
-// On-the-fly adjoint with wavefront-merged atomics into x ([V] for one object,
-// voxel-major [V][4] for a batch).  Rays of one wavefront
-// (an 8x8 pixel block) cross nearly the same voxels in the same order, so the
-// wavefront advances all its rays one canonical segment per step (a uniform
-// loop) and, per step, adds up the contributions of lanes that hit the same
-// voxel before a single lane issues the atomic add.
 template <int NB>
 __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
                                                       const float *y, int nb, int64_t V,
                                                       float *x_out) {
-    extern __shared__ double lds[];
+    constexpr int HS = OtfHash<NB>::kSize;
+    extern __shared__ double lds[];  // grid tables, then the hash keys and values
+    __shared__ int fill;
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
+    int *hkey = reinterpret_cast<int *>(lds + D.n_tab);
+    float *hval = reinterpret_cast<float *>(hkey + HS);  // [NB][HS]
     const int64_t win = xcd_window(rd.n_slots / kWindow);
     if (win >= rd.n_slots / kWindow) return;  // whole padding blocks of the remapped grid
+    for (int i = threadIdx.x; i < HS; i += 256) {
+        hkey[i] = -1;
+#pragma unroll
+        for (int b = 0; b < NB; b++) hval[b * HS + i] = 0.0f;
+    }
+    if (threadIdx.x == 0) fill = 0;
     const int64_t slot = win * kWindow + threadIdx.x;
-    const int lane = threadIdx.x & 63;
     const int32_t ray = natural_ray(rd, slot);
     float yv[NB];
     bool any = false;
@@ -250,28 +266,52 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
         ray_of(rd, ray, x, n);
         alive = w.init(T, x, n);
     }
-    while (__any(alive)) {  // uniform over the wavefront
-        int v = -1;
-        double l = 0.0;
-        if (alive) {
-            alive = w.next(T, v, l);
-            if (!alive) v = -1;
-        }
-        float c[NB];
+    __syncthreads();
+    for (;;) {
+        for (int k = 0; k < kOtfEvents && alive; k++) {
+            int v;
+            double l;
+            const bool seg = w.step(T, v, l);
+            alive = !w.done();
+            if (!seg) continue;
+            const float lf = (float)l;
+            unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
+            bool done = false;
+            for (int p = 0; p < kOtfProbes; p++) {
+                const int key = atomicCAS(hkey + h, -1, v);
+                if (key == -1) atomicAdd(&fill, 1);
+                if (key == -1 || key == v) {
 #pragma unroll
-        for (int b = 0; b < NB; b++) c[b] = (v >= 0) ? (float)l * yv[b] : 0.0f;
-        uint64_t pend = __ballot(v >= 0);
-        while (pend) {
-            const int leader = __ffsll((unsigned long long)pend) - 1;
-            const int v0 = __shfl(v, leader, kWave);
-            const bool mine = (v == v0);
-#pragma unroll
-            for (int b = 0; b < NB; b++) {  // x_out: [V] (NB 1) or voxel-major [V][4]
-                const float sb = wave_sum_f(mine ? c[b] : 0.0f);
-                if (lane == leader && b < nb) atomicAdd(x_out + (int64_t)v0 * NB + b, sb);
+                    for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, lf * yv[b]);
+                    done = true;
+                    break;
+                }
+                h = (h + 1) & (HS - 1);
             }
-            pend &= ~__ballot(mine);
+            if (!done) {
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, lf * yv[b]);
+            }
         }
+        __syncthreads();  // every insertion of this round has landed
+        const int f = fill;
+        const bool more = __syncthreads_or(alive);  // also: every thread has read fill
+        if (f > HS / 2 || !more) {
+            for (int i = threadIdx.x; i < HS; i += 256) {
+                const int key = hkey[i];
+                if (key < 0) continue;
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    if (b < nb) atomicAdd(x_out + (int64_t)key * NB + b, hval[b * HS + i]);
+                    hval[b * HS + i] = 0.0f;
+                }
+                hkey[i] = -1;
+            }
+            if (threadIdx.x == 0) fill = 0;
+            __syncthreads();
+        }
+        if (!more) break;
     }
 }
 
@@ -368,7 +408,7 @@ hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc
 // x must be zero on entry for B == 1 (the caller clears it).
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *y, int B, int64_t V, float *x, hipStream_t st) {
-    const size_t sh = T.n_tab * sizeof(double);
+    const size_t sh = T.n_tab * sizeof(double) + (B == 1 ? OtfHash<1>::kBytes : OtfHash<4>::kBytes);
     const dim3 grid(remapped_grid(rd.n_slots));
     if (B == 1) {
         hipLaunchKernelGGL(k_otf_adjoint<1>, grid, dim3(256), sh, st, T, tab, rd, y, 1, V, x);
