@@ -56,7 +56,8 @@ def _view(pos=(10.0, 0.0, 0.0), fov=(30.0, 30.0), shape=(4, 4)):
 
 @pytest.mark.parametrize("case", ["null_grid", "rb_not_increasing", "eb_out_of_range",
                                   "ab_span", "detector_inside", "fov", "both_sources",
-                                  "ray_inside", "zero_dir", "shape_mismatch"])
+                                  "ray_inside", "zero_dir", "shape_mismatch",
+                                  "tables_exceed_lds"])
 def test_create_validation(case):
     from paper_2608_16960_amd import native as N
     out = ctypes.c_void_p()
@@ -83,6 +84,8 @@ def test_create_validation(case):
         nv = 1
     elif case == "shape_mismatch":
         views = (N.tsp_cone_view * 2)(_view(), _view(shape=(4, 5)))
+    elif case == "tables_exceed_lds":  # nr + ne + 3 na = 5630 > 5627
+        gd, keep = _grid(ab=np.linspace(0.0, 2 * np.pi, 1876 + 1))
     elif case in ("both_sources", "ray_inside", "zero_dir"):
         s = np.array([[10.0, 0, 0]] if case != "ray_inside" else [[0.5, 0, 0]])
         d = np.array([[-1.0, 0, 0]] if case != "zero_dir" else [[0.0, 0, 0]])
@@ -95,6 +98,19 @@ def test_create_validation(case):
     assert st == N.TSP_E_INVALID, N.lib.tsp_last_error()
     assert not out.value
     assert len(N.lib.tsp_last_error()) > 0
+
+
+def test_table_limit_is_inclusive():
+    """nr + ne + 3 na = 5627 passes validation (without a GPU the call then
+    fails in the HIP runtime, not in argument checking)."""
+    from paper_2608_16960_amd import native as N
+    out = ctypes.c_void_p()
+    gd, keep = _grid(ab=np.linspace(0.0, 2 * np.pi, 1875 + 1))
+    views = (N.tsp_cone_view * 1)(_view())
+    st = N.lib.tsp_geometry_create(ctypes.byref(gd), views, 1, None, None, 0, ctypes.byref(out))
+    assert st != N.TSP_E_INVALID, N.lib.tsp_last_error()
+    if out.value:
+        N.lib.tsp_geometry_destroy(out)
 
 
 def test_null_geometry_calls():
