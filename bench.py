@@ -43,41 +43,101 @@ def _args():
                    help="only the Medium forward+adjoint line (for profiler runs)")
     p.add_argument("--calib-copy", action="store_true",
                    help="after timing, run a plain 1 GiB device copy (counter calibration)")
+    p.add_argument("--large-only", action="store_true",
+                   help="only the Large on-the-fly forward and adjoint (for counter runs)")
     p.add_argument("--cpu-views", type=int, default=30,
                    help="views of the workload the CPU oracle traces (bounded sample)")
     return p.parse_args()
 
 
-def cpu_baseline(w, n_views):
-    """The FP64 oracle as it stands, on the host cores, on a subset of views:
-    trace (steps 1-3) and apply (forward + adjoint from its own lists) timed
-    separately; `value` is the apply rate in rays/s, like the GPU's."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(w, n_views, large_views=6):
+    """The FP64 oracle as it stands, on the host cores: trace (steps 1-3) and
+    apply (forward + adjoint from its own lists) timed separately, with all
+    threads and with one; `value` is the all-thread apply rate in rays/s over
+    `n_views` views of the workload, like the GPU's.  Also the trace and apply
+    rates on a fixed subset of the Large workload (every 30th view)."""
     import numpy as np
 
     import oracle
+    from paper_2608_16960_amd import workloads as W
+
+    def run(wl, sel):
+        v = wl.views
+        s, d = oracle.cone_rays(v.pos[sel], v.look[sel], v.up[sel], v.fov_deg[sel], v.H, v.W)
+        t0 = time.perf_counter()
+        tr = oracle.trace(wl.grid.arrays(), s, d)
+        t1 = time.perf_counter()
+        rho = wl.rho[0].reshape(-1).astype(np.float64)
+        y = oracle.forward(tr, rho)
+        t2 = time.perf_counter()
+        oracle.adjoint(tr, y, wl.grid.size)
+        t3 = time.perf_counter()
+        return tr, rho, len(s), int(tr["counts"].sum()), (t1 - t0, t2 - t1, t3 - t2)
+
+    nt = oracle.num_threads()
     v = w.views
     sel = np.linspace(0, v.n_views - 1, n_views).round().astype(int)
-    s, d = oracle.cone_rays(v.pos[sel], v.look[sel], v.up[sel], v.fov_deg[sel], v.H, v.W)
-    t0 = time.perf_counter()
-    tr = oracle.trace(w.grid.arrays(), s, d)
-    t1 = time.perf_counter()
-    rho = w.rho[0].astype(np.float64)
-    y = oracle.forward(tr, rho)
-    t2 = time.perf_counter()
-    oracle.adjoint(tr, y, w.grid.size)
-    t3 = time.perf_counter()
-    R = len(s)
-    S = int(tr["counts"].sum())
-    return {
-        "value": R / (t3 - t1), "unit": "rays/s", "cores": oracle.num_threads(), "kind": "oracle",
+    tr, rho, R, S, (ts, fs, as_) = run(w, sel)
+    out = {
+        "value": R / (fs + as_), "unit": "rays/s", "cores": nt, "kind": "oracle",
         "sample": f"{len(sel)} of {v.n_views} views ({R} rays, {S} segments) of the "
                   f"{w.name} workload; forward (OpenMP) + adjoint (serial) from the oracle's "
                   f"own segment lists, FP64",
-        "segments_per_s": S / (t3 - t1),
-        "trace_rays_per_s": R / (t1 - t0),
-        "trace_s": t1 - t0, "forward_s": t2 - t1, "adjoint_s": t3 - t2,
-        "host": platform.processor() or platform.machine(),
+        "segments_per_s": S / (fs + as_),
+        "trace_rays_per_s": R / ts,
+        "trace_s": ts, "forward_s": fs, "adjoint_s": as_,
+        "host": _cpu_model(),
     }
+    # one thread: apply on the same lists; trace on the first view only
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.forward(tr, rho)
+        f1 = time.perf_counter() - t0
+        del tr
+        _, _, R1, _, (t1s, _, _) = run(w, sel[:1])
+    finally:
+        oracle.set_num_threads(nt)
+    out["one_thread"] = {"apply_rays_per_s": R / (f1 + as_), "forward_s": f1,
+                         "trace_rays_per_s": R1 / t1s, "trace_sample": f"1 view ({R1} rays)"}
+    # Large subset, all threads
+    L = W.large()
+    lsel = np.arange(0, L.views.n_views, L.views.n_views // large_views)[:large_views]
+    trL, _, RL, SL, (tl, fl, al) = run(L, lsel)
+    del trL
+    out["large_subset"] = {"views": lsel.tolist(), "rays": RL, "segments": SL,
+                           "trace_rays_per_s": RL / tl, "apply_rays_per_s": RL / (fl + al),
+                           "apply_segments_per_s": SL / (fl + al), "object": "first of 4"}
+    return out
+
+
+def measured_copy_gbps(dev, nbytes=1 << 30, reps=10):
+    """Bytes read + written per second by a plain device-to-device copy of
+    `nbytes` (torch's copy kernel), the practical streaming ceiling."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2.0 * nbytes / ms / 1e6
 
 
 def _log(msg):
@@ -120,13 +180,22 @@ def extra_large_onthefly():
     a_ms = _time_ms(lambda: P.backproject(y, "atomic", out=x), 2)
     alg = 4 * B * V + 4 * B * R
     P.close()
+    from paper_2608_16960_amd.profiling import read_valu
+    fp64 = {}
+    for k, kern in (("forward", "k_otf_forward<4>"), ("adjoint", "k_otf_adjoint<4>")):
+        r = read_valu(os.path.join(ROOT, "profiles", "otf_large_fp64.txt"), kern)
+        fp64[k] = None if r is None else {
+            "flops_per_launch": r[0], "frac_of_fp64_peak": r[1],
+            "tflops_live": r[0] / ((f_ms if k == "forward" else a_ms) * 1e9)}
     return {"workload": f"large: grid {P.shape}, {w.views.n_views} cone views "
                         f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch {B}",
             "count_s": count_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
             "forward_rays_per_s": B * R / f_ms * 1e3, "forward_segments_per_s": B * S / f_ms * 1e3,
             "adjoint_rays_per_s": B * R / a_ms * 1e3, "adjoint_segments_per_s": B * S / a_ms * 1e3,
             "forward_hbm_frac": alg / f_ms / 1e6 / HBM_PEAK_GBS,
-            "note": "FP64 tracing per launch; the HBM roof does not bind (4BV + 4BR bytes)"}
+            "fp64_valu": fp64,
+            "note": "FP64 tracing per launch; the HBM roof does not bind (4BV + 4BR bytes); "
+                    "fp64_valu from rocprofv3 FP64 instruction counters (profiles)"}
 
 
 def extra_diff_csr():
@@ -208,6 +277,9 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if a.large_only:
+        print(json.dumps({"onthefly_large": extra_large_onthefly()}))
+        return
     w = getattr(W, a.workload)()
     rho = torch.from_numpy(w.rho[:1]).to(dev)
 
@@ -241,8 +313,9 @@ def main():
         e2.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    fwd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
-    adj_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+    fwd_t = sorted(e[0].elapsed_time(e[1]) for e in ev)
+    adj_t = sorted(e[1].elapsed_time(e[2]) for e in ev)
+    fwd_ms, adj_ms = sum(fwd_t) / K, sum(adj_t) / K
     ms_step = wall / K * 1e3
 
     # algorithmic bytes per launch (4-byte index + 4-byte length per segment,
@@ -250,11 +323,14 @@ def main():
     fwd_bytes = 8 * S + 8 * R + 4 * B * R + 4 * B * V
     adj_bytes = 8 * S + 8 * V + 4 * B * V + 4 * B * R
     kern = {
-        "forward": {"kernel": "k_fwd_sell<1>", "ms": fwd_ms, "bytes": fwd_bytes,
+        "forward": {"kernel": "k_fwd_sell<1>", "ms": fwd_ms, "min_ms": fwd_t[0],
+                    "median_ms": fwd_t[K // 2], "bytes": fwd_bytes,
                     "GBps": fwd_bytes / fwd_ms / 1e6},
-        "adjoint": {"kernel": "k_adj_csc<1>", "ms": adj_ms, "bytes": adj_bytes,
+        "adjoint": {"kernel": "k_adj_csc<1>", "ms": adj_ms, "min_ms": adj_t[0],
+                    "median_ms": adj_t[K // 2], "bytes": adj_bytes,
                     "GBps": adj_bytes / adj_ms / 1e6},
     }
+    copy_gbps = measured_copy_gbps(dev)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
     from paper_2608_16960_amd.profiling import read_traffic
@@ -271,7 +347,8 @@ def main():
                    "mode": "csr + voxel-major deterministic adjoint"},
         "segments_per_s": S / (ms_step / 1e3),
         "roofline": {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": d["kernel"]},
+                     "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": d["kernel"],
+                     "copy_GBps": copy_gbps, "frac_of_copy": d["GBps"] / copy_gbps},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kern.items()},
         "trace_s": trace_s,

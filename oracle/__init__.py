@@ -14,4 +14,5 @@ Contents
     conv3d in float64 as the library step).
 """
 from .projector import (cone_rays, trace, forward, adjoint, project, num_threads,  # noqa: F401
+                        set_num_threads,
                         load_library, cone_data_grad, voxel_bounding_spheres, cone_ray_ids)

@@ -32,6 +32,8 @@ def load_library():
         _b.build()
     lib = ctypes.CDLL(path)
     lib.ora_num_threads.restype = ctypes.c_int
+    lib.ora_set_num_threads.restype = None
+    lib.ora_set_num_threads.argtypes = [ctypes.c_int]
     lib.ora_cone_rays.restype = None
     lib.ora_cone_rays.argtypes = [ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int,
                                   _dp, _dp]
@@ -70,6 +72,10 @@ def _f64(a):
 
 def num_threads() -> int:
     return int(load_library().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    load_library().ora_set_num_threads(int(n))
 
 
 def cone_rays(pos, look, up, fov_deg, H, W):

@@ -323,6 +323,15 @@ int ora_num_threads(void) {
 #endif
 }
 
+/* Threads for the parallel loops that follow (timing runs use 1 and all). */
+void ora_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /*
  * Cone-beam rays (Sec. 4.2, detector at the cone vertex, Sec. 4.6), pinhole
  * reading: w = unit(look - pos); u = unit(w x up) (up = +X when w is

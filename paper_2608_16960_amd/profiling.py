@@ -1,6 +1,7 @@
-"""HBM-traffic figures from rocprofv3 counter runs, for the benchmark line.
+"""HBM-traffic and FP64 figures from rocprofv3 counter runs, for the benchmark line.
 
     python -m paper_2608_16960_amd.profiling FETCH_DIR WRITE_DIR BYTES_JSON OUT_TXT
+    python -m paper_2608_16960_amd.profiling valu PMC_DIR STATS_DIR OUT_TXT
 
 FETCH_DIR / WRITE_DIR hold the counter_collection CSV of a `rocprofv3 --pmc
 FETCH_SIZE` and a `--pmc WRITE_SIZE` run of `bench.py --calib-copy`; each
@@ -15,17 +16,81 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = {"k_fwd_sell<1>": "csrc/tsp_apply.hip", "k_adj_csc<1>": "csrc/tsp_apply.hip"}
+KERNEL_SOURCES = {"k_fwd_sell<1>": "csrc/tsp_apply.hip", "k_adj_csc<1>": "csrc/tsp_apply.hip",
+                  "k_otf_forward<4>": "csrc/tsp_trace.hip", "k_otf_adjoint<4>": "csrc/tsp_trace.hip"}
+FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64, published
 COPY_KIB = 1 << 20  # the calibration copy moves 1 GiB each way
 
 
 def source_sha(kernel):
-    path = os.path.join(PKG, KERNEL_SOURCES[kernel])
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+    """SHA-1 of the kernel's source file (and, for the tracing kernels, of the
+    shared tracer header)."""
+    h = hashlib.sha1()
+    paths = [KERNEL_SOURCES[kernel]]
+    if "otf" in kernel:
+        paths.append("csrc/tsp_trace_core.h")
+    for p in paths:
+        with open(os.path.join(PKG, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:12]
+
+
+def _match(name, kernel):
+    """rocprofv3 kernel name -> does it denote `kernel` ("k_x<4>")?"""
+    base, _, targ = kernel.partition("<")
+    return re.search(r"\b" + base + r"<" + targ.rstrip(">") + r"\b", name) is not None
+
+
+def _per_dispatch(dirname, kernel):
+    """Mean per dispatch of every counter of `kernel` in a counter_collection CSV."""
+    path = glob.glob(os.path.join(dirname, "*counter_collection.csv"))[0]
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        if _match(r["Kernel_Name"], kernel):
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def _mean_ns(stats_dir, kernel):
+    path = glob.glob(os.path.join(stats_dir, "*kernel_stats.csv"))[0]
+    for r in csv.DictReader(open(path)):
+        if _match(r["Name"], kernel):
+            return float(r["AverageNs"])
+    return None
+
+
+def summarise_valu(pmc_dir, stats_dir, kernels=("k_otf_forward<4>", "k_otf_adjoint<4>")):
+    """FP64 work per dispatch from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 (wave
+    instructions; x64 lanes, FMA counts 2 flops) and the kernel's mean duration
+    from a --kernel-trace --stats run of the same command."""
+    out = {}
+    for k in kernels:
+        c = _per_dispatch(pmc_dir, k)
+        ns = _mean_ns(stats_dir, k)
+        if not c or ns is None:
+            continue
+        flops = 64.0 * (c.get("SQ_INSTS_VALU_ADD_F64", 0) + c.get("SQ_INSTS_VALU_MUL_F64", 0)
+                        + 2.0 * c.get("SQ_INSTS_VALU_FMA_F64", 0)
+                        + c.get("SQ_INSTS_VALU_TRANS_F64", 0))
+        out[k] = {"fp64_flops": flops, "ns": ns, "counters": c, "sha1": source_sha(k),
+                  "tflops": flops / ns / 1e3, "frac": flops / ns / 1e3 / FP64_PEAK_TFLOPS}
+    return out
+
+
+def read_valu(txt_path, kernel):
+    """(FP64 flops per dispatch, fraction of the FP64 peak) of `kernel` from a
+    summary file, or None when absent or taken on a different source."""
+    if not os.path.exists(txt_path):
+        return None
+    for line in open(txt_path):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == "valu" and parts[1] == kernel:
+            return (float(parts[2]), float(parts[3])) if parts[4] == source_sha(kernel) else None
+    return None
 
 
 def _counter(dirname):
@@ -68,7 +133,21 @@ def read_traffic(txt_path, kernel):
     return None
 
 
+def main_valu(argv):
+    pmc_dir, stats_dir, out_txt = argv
+    s = summarise_valu(pmc_dir, stats_dir)
+    with open(out_txt, "a") as f:
+        f.write("\n# machine-readable: valu <kernel> <FP64 flops per dispatch> <fraction of "
+                f"{FP64_PEAK_TFLOPS} TFLOP/s> <source sha1>\n")
+        for k, v in s.items():
+            f.write(f"valu {k} {v['fp64_flops']:.0f} {v['frac']:.4f} {v['sha1']}\n")
+            cs = ", ".join(f"{n} {x:.4g}" for n, x in sorted(v["counters"].items()))
+            f.write(f"# {k}: {v['ns'] / 1e6:.2f} ms, {v['tflops']:.2f} TFLOP/s FP64; {cs}\n")
+
+
 def main(argv):
+    if argv and argv[0] == "valu":
+        return main_valu(argv[1:])
     fetch_dir, write_dir, bench_json, out_txt = argv
     s = summarise(fetch_dir, write_dir)
     algo = {}
