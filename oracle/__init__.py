@@ -9,6 +9,8 @@ Contents
   - projector (C, ``tsp_oracle.c``): cone-beam rays, canonical segment lists by
     the plain definition of the line integral (TomoSphero Sec. 2.1 Eqs. 3-5,
     Sec. 3), forward and adjoint;
+  - ``dynamic``: forward and adjoint for dynamic (4-D) objects, one object
+    frame per view (Sec. 4.4, 4.6), on the oracle's segment lists;
   - ``reg``: anisotropic smoothed total variation and the Adam update;
   - ``conv``: 3x3x3 convolution with circular azimuth padding (PyTorch CPU
     conv3d in float64 as the library step).
