@@ -110,6 +110,8 @@ typedef struct tsp_info {
     int64_t device_bytes; /* device memory currently owned by the geometry */
     int32_t mode;         /* 0 before tsp_trace, else TSP_MODE_CSR or TSP_MODE_ONTHEFLY */
     int32_t has_csc;      /* voxel-major store present */
+    int32_t n_obj_frames; /* F: object frames (1 for a static object) */
+    int32_t reserved;
 } tsp_info;
 
 typedef struct tsp_geometry tsp_geometry;
@@ -134,6 +136,24 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
                                int64_t n_rays, tsp_geometry **out);
 
 /*
+ * Dynamic objects (Sec. 4.4: the operator applies to a 3-D or a 4-D object;
+ * Sec. 4.6: the grid stays the same for every frame).  Assigns object frame
+ * frame_of_view[v] to cone view v.  Afterwards tsp_forward reads rho as
+ * [batch][n_frames][V]; every ray of view v integrates frame
+ * frame_of_view[v].  tsp_backproject writes x in the same layout, and frame f
+ * receives only the rays of the views assigned to it (zero if none).
+ * frame_of_view: host int32 [n_views], each in [0, n_frames), read during
+ * the call.  Must precede tsp_trace, because the voxel-major store is keyed
+ * by frame; calling it again replaces the assignment.  Without this call a
+ * geometry has one frame.
+ * Errors: TSP_E_INVALID (NULL, n_frames < 1, a frame index out of range,
+ * n_frames * V >= 2^31), TSP_E_STATE after tsp_trace, TSP_E_UNSUPPORTED for
+ * a geometry of explicit rays.
+ */
+tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
+                                 int32_t n_frames);
+
+/*
  * Precompute steps 1-3 (Sec. 3.1-3.3) for every ray.
  *   TSP_MODE_CSR: counts segments per ray, then stores the canonical segment
  *     lists (voxel index int32 + length float32 per segment) in a ray-major
@@ -151,16 +171,19 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
 tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream);
 
 /*
- * y[b][i] = sum over ray i's segments of len * rho[b][vox]   (Eq. 5)
- * rho: device float32 [batch][V]; y: device float32 [batch][R], overwritten.
+ * y[b][i] = sum over ray i's segments of len * rho[b][f][vox]   (Eq. 5)
+ * where f is the object frame of ray i's view (0 for a static object).
+ * rho: device float32 [batch][F][V] (F = n_obj_frames, usually 1);
+ * y: device float32 [batch][R], overwritten.
  * batch >= 1.  TSP_E_STATE before tsp_trace.
  */
 tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, float *y,
                        void *stream);
 
 /*
- * Adjoint: x[b][v] = sum over all segments in voxel v of len * y[b][ray].
- * y: device float32 [batch][R]; x: device float32 [batch][V], overwritten.
+ * Adjoint: x[b][f][v] = sum over all segments in voxel v of rays of views in
+ * object frame f of len * y[b][ray].
+ * y: device float32 [batch][R]; x: device float32 [batch][F][V], overwritten.
  * method TSP_ADJ_DETERMINISTIC (CSR mode with the transposed store:
  * bitwise reproducible) or TSP_ADJ_ATOMIC (CSR or on-the-fly mode).
  * TSP_E_UNSUPPORTED for a deterministic adjoint without a transposed store.

@@ -72,7 +72,10 @@ struct tsp_geometry {
     int64_t *d_row_ptr = nullptr;
     // voxel-major store
     int64_t *d_col_ptr = nullptr;
-    uint64_t *d_col_ent = nullptr;  // (ray, length bits) per entry
+    uint64_t *d_col_ent = nullptr;  // (ray slot, length bits) per entry
+    // dynamic objects: object frame per cone view (null for a static object)
+    int32_t *d_obj_frame = nullptr;
+    int64_t FV() const { return V * rd.n_obj_frames; }
     int64_t bytes = 0;
     std::vector<std::pair<void *, int64_t>> allocs;
 };
@@ -326,8 +329,12 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
             }
         rd.n_slots = (int64_t)n_views * rd.tiles_h * rd.tiles_w * kWindow;
         rd.explicit_rays = 0;
+        rd.obj_frame = nullptr;
+        rd.n_obj_frames = 1;
     } else {
         rd.explicit_rays = 1;
+        rd.obj_frame = nullptr;
+        rd.n_obj_frames = 1;
         rd.st = 1;
         rd.n_slots = (R + kWindow - 1) / kWindow * kWindow;
     }
@@ -374,6 +381,42 @@ void tsp_geometry_destroy(tsp_geometry *g) {
     for (auto &a : g->allocs) (void)hipFree(a.first);
     g->allocs.clear();
     delete g;
+}
+
+tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
+                                 int32_t n_frames) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (g->mode != 0) return fail(TSP_E_STATE, "object frames must be set before tsp_trace");
+    if (g->rd.explicit_rays)
+        return fail(TSP_E_UNSUPPORTED, "object frames need cone views (explicit rays given)");
+    if (!frame_of_view) return fail(TSP_E_INVALID, "frame_of_view is NULL");
+    if (n_frames < 1) return fail(TSP_E_INVALID, "n_frames < 1");
+    if (g->V * (int64_t)n_frames >= ((int64_t)1 << 31))
+        return fail(TSP_E_INVALID, "n_frames * voxels >= 2^31");
+    const int nv = g->rd.n_views;
+    for (int v = 0; v < nv; v++)
+        if (frame_of_view[v] < 0 || frame_of_view[v] >= n_frames) {
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "frame_of_view[%d] = %d outside [0, %d)", v,
+                          (int)frame_of_view[v], (int)n_frames);
+            return fail(TSP_E_INVALID, buf);
+        }
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
+    if (g->d_obj_frame) dfree_p(g, g->d_obj_frame);
+    g->rd.obj_frame = nullptr;
+    g->rd.n_obj_frames = 1;
+    tsp_status s;
+    if ((s = dalloc_n(g, &g->d_obj_frame, nv, "object frames")) != TSP_OK) return s;
+    if (hipMemcpy(g->d_obj_frame, frame_of_view, sizeof(int32_t) * nv, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        dfree_p(g, g->d_obj_frame);
+        return fail(TSP_E_HIP, "hipMemcpy of object frames failed");
+    }
+    g->rd.obj_frame = g->d_obj_frame;
+    g->rd.n_obj_frames = n_frames;
+    return TSP_OK;
 }
 
 tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
@@ -510,7 +553,7 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
                           g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, k1, v1, nullptr, nullptr,
                           st);
         if (e == hipSuccess)
-            e = launch_radix_sort(k1, v1, k2, v2, S, bits_for(g->V), ws, &in_second, st);
+            e = launch_radix_sort(k1, v1, k2, v2, S, bits_for(g->FV()), ws, &in_second, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) {
             free_sort();
@@ -528,12 +571,12 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
             dfree_p(g, v2);
         }
         dfree_p(g, ws);
-        if ((s = dalloc_n(g, &g->d_col_ptr, g->V + 1, "column offsets")) != TSP_OK) {
+        if ((s = dalloc_n(g, &g->d_col_ptr, g->FV() + 1, "column offsets")) != TSP_OK) {
             free_sort();
             release_stores(g);
             return s;
         }
-        e = launch_col_ptr(ks, S, g->V, g->d_col_ptr, st);
+        e = launch_col_ptr(ks, S, g->FV(), g->d_col_ptr, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (in_second) {
             v2 = nullptr;
@@ -564,8 +607,8 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (g->mode == TSP_MODE_CSR)
-        e = launch_forward_sell(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
-                                g->d_vox, g->d_len, g->rd.n_slots, rho, batch, g->V, g->R, y, st);
+        e = launch_forward_sell(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                g->d_slice_len, g->d_vox, g->d_len, rho, batch, g->V, y, st);
     else
         e = launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("forward: ") + hipGetErrorString(e));
@@ -591,12 +634,12 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
         e = launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_ent, g->T.nr, g->T.ne, g->T.na, y,
                                batch, x, st);
     } else {
-        e = launch_zero_f32(x, (int64_t)batch * g->V, st);
+        e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
         if (e == hipSuccess) {
             if (g->mode == TSP_MODE_CSR)
-                e = launch_adjoint_atomic(g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                          g->d_slice_len, g->d_vox, g->d_len, g->rd.n_slots, y,
-                                          batch, g->V, g->R, x, st);
+                e = launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                          g->d_slice_len, g->d_vox, g->d_len, y, batch, g->V, x,
+                                          st);
             else
                 e = launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
         }
@@ -642,6 +685,7 @@ tsp_status tsp_query(const tsp_geometry *g, tsp_info *info) {
     info->device_bytes = g->bytes;
     info->mode = g->mode;
     info->has_csc = g->d_col_ptr != nullptr;
+    info->n_obj_frames = g->rd.n_obj_frames;
     return TSP_OK;
 }
 

@@ -53,12 +53,16 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
                                                    const int32_t *__restrict__ vox,
                                                    const float *__restrict__ len, int64_t n_slots,
                                                    const float *__restrict__ rho, int nb,
-                                                   int64_t V, int64_t R, float *__restrict__ y) {
+                                                   int64_t V, int64_t R, float *__restrict__ y,
+                                                   const int32_t *__restrict__ obj_frame,
+                                                   int64_t hw, int64_t vf) {
+    // V: batch stride of rho (voxels of all object frames); vf: one frame
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int64_t s = slot >> 6;
     const int lane = (int)(slot & 63);
     const int32_t ray = perm[slot];
+    rho += (ray >= 0) ? frame_base(obj_frame, hw, ray, vf) : 0;
     const int c = cnt_sorted[slot];
     const int nq = slice_len[s] >> 2;  // quads of segments in this slice
     const v4i *vp = (const v4i *)(vox + slice_ptr[s]) + lane;
@@ -90,12 +94,6 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
     }
 }
 
-// One wavefront per voxel.  Lane i sums entries i, i+64, i+128, ... of the
-// voxel's list (ray order), four independent loads in flight per lane; a
-// fixed butterfly adds the 64 partial sums.  The order never depends on
-// timing, so x is bitwise reproducible.  Lanes read consecutive entries, so
-// one gather instruction touches the few cache lines that hold a patch of
-// neighbouring detector pixels.
 // Batch lane group of the slot-ordered copy of y: NB = 1, 2 or 4 values per
 // slot, loaded with one 4-, 8- or 16-byte access.
 template <int NB> struct YVec;
@@ -135,19 +133,23 @@ __global__ __launch_bounds__(256) void k_tile_y(const RayDesc rd, const float *_
 
 // Deterministic adjoint: one wavefront per voxel of the voxel-major store,
 // lanes stride its entries (eight per lane in flight), fixed butterfly sum.
+// Keys run over object frames, then voxels in angular-major order; x is
+// [nf][V] per object (nf = 1 for a static object).
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
                                                   const uint64_t *__restrict__ col_ent, int nr,
-                                                  int ne, int na,
+                                                  int ne, int na, int nf,
                                                   const typename YVec<NB>::T *__restrict__ yt,
                                                   int nb, float *__restrict__ x) {
     constexpr int UNR = 8;
     const int64_t V = (int64_t)nr * ne * na;
+    const int64_t FV = V * nf;
     const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (key >= V) return;  // uniform over the wavefront
+    if (key >= FV) return;  // uniform over the wavefront
     const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
-    const int32_t v = from_angular_major(key, nr, ne, na);
+    const int64_t f = key / V;
+    const int64_t v = f * V + from_angular_major(key - f * V, nr, ne, na);
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
@@ -179,7 +181,7 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
     if (lane == 0) {
 #pragma unroll
         for (int b = 0; b < NB; b++)
-            if (b < nb) x[b * V + v] = acc[b];
+            if (b < nb) x[b * FV + v] = acc[b];
     }
 }
 
@@ -195,11 +197,15 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
                                                      const int32_t *__restrict__ vox,
                                                      const float *__restrict__ len,
                                                      int64_t n_slots, const float *__restrict__ y,
-                                                     int nb, int64_t V, int64_t R, float *x) {
+                                                     int nb, int64_t V, int64_t R, float *x,
+                                                     const int32_t *__restrict__ obj_frame,
+                                                     int64_t hw, int64_t vf) {
+    // V: batch stride of x (voxels of all object frames); vf: one frame
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
     const int lane = (int)(slot & 63);
     const int32_t ray = perm[slot];
+    const int32_t fb = (ray >= 0) ? (int32_t)frame_base(obj_frame, hw, ray, vf) : 0;
     const int c = (ray >= 0) ? cnt_sorted[slot] : 0;
     const int m = slice_len[slot >> 6];
     const int64_t base = slice_ptr[slot >> 6];
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
         float l = 0.0f;
         if (j < c) {
             const int64_t i = sell_index(base, lane, j);
-            v = vox[i];
+            v = fb + vox[i];
             l = len[i];
         }
         float cb[NB];
@@ -248,25 +254,29 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
-hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
+hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
-                               const int32_t *vox, const float *len, int64_t n_slots,
-                               const float *rho, int B, int64_t V, int64_t R, float *y,
-                               hipStream_t st) {
+                               const int32_t *vox, const float *len, const float *rho, int B,
+                               int64_t vf, float *y, hipStream_t st) {
+    const int64_t FV = vf * rd.n_obj_frames, R = rd.R, hw = (int64_t)rd.H * rd.W;
+    const int64_t n_slots = rd.n_slots;
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
-        const float *r = rho + (int64_t)b0 * V;
+        const float *r = rho + (int64_t)b0 * FV;
         float *yy = y + (int64_t)b0 * R;
         const dim3 g(blocks_for(n_slots, 256));
         if (nb == 1)
             hipLaunchKernelGGL(k_fwd_sell<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
+                               vf);
         else if (nb == 2)
             hipLaunchKernelGGL(k_fwd_sell<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
+                               vf);
         else
             hipLaunchKernelGGL(k_fwd_sell<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, V, R, yy);
+                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
+                               vf);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -278,18 +288,18 @@ static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_ptr,
                                 const uint64_t *col_ent, int nr, int ne, int na, const float *y,
                                 int nb, float *x, void *yt, hipStream_t st) {
     using T = typename YVec<NB>::T;
-    const int64_t V = (int64_t)nr * ne * na;
+    const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     hipLaunchKernelGGL(k_tile_y<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, y,
                        nb, (T *)yt);
-    hipLaunchKernelGGL(k_adj_csc<NB>, dim3(blocks_for(V * kWave, 256)), dim3(256), 0, st,
-                       col_ptr, col_ent, nr, ne, na, (const T *)yt, nb, x);
+    hipLaunchKernelGGL(k_adj_csc<NB>, dim3(blocks_for(FV * kWave, 256)), dim3(256), 0, st,
+                       col_ptr, col_ent, nr, ne, na, rd.n_obj_frames, (const T *)yt, nb, x);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
                               int nr, int ne, int na, const float *y, int B, float *x,
                               hipStream_t st) {
-    const int64_t V = (int64_t)nr * ne * na;
+    const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     const int width = B >= 3 ? 4 : B;
     void *yt = nullptr;
     hipError_t e = hipMallocAsync(&yt, (size_t)rd.n_slots * width * sizeof(float), st);
@@ -297,7 +307,7 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const u
     for (int b0 = 0; b0 < B && e == hipSuccess; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
-        float *xx = x + (int64_t)b0 * V;
+        float *xx = x + (int64_t)b0 * FV;
         if (nb == 1)
             e = adj_csc_chunk<1>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
         else if (nb == 2)
@@ -309,25 +319,29 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const u
     return e != hipSuccess ? e : f;
 }
 
-hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
-                                 const int64_t *slice_ptr, const int32_t *slice_len,
-                                 const int32_t *vox, const float *len, int64_t n_slots,
-                                 const float *y, int B, int64_t V, int64_t R, float *x,
-                                 hipStream_t st) {
+hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
+                                 const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                                 const int32_t *slice_len, const int32_t *vox, const float *len,
+                                 const float *y, int B, int64_t vf, float *x, hipStream_t st) {
+    const int64_t FV = vf * rd.n_obj_frames, R = rd.R, hw = (int64_t)rd.H * rd.W;
+    const int64_t n_slots = rd.n_slots;
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * R;
-        float *xx = x + (int64_t)b0 * V;
+        float *xx = x + (int64_t)b0 * FV;
         const dim3 g(blocks_for(n_slots, 256));
         if (nb == 1)
             hipLaunchKernelGGL(k_adj_atomic<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf);
         else if (nb == 2)
             hipLaunchKernelGGL(k_adj_atomic<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf);
         else
             hipLaunchKernelGGL(k_adj_atomic<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, V, R, xx);
+                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

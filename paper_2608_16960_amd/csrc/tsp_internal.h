@@ -36,7 +36,18 @@ struct RayDesc {
     int explicit_rays;
     int64_t R;
     int64_t n_slots;       // multiple of kWindow
+    // dynamic objects: object frame of each cone view (device, [n_views]),
+    // nullptr for a static object
+    const int32_t *obj_frame;
+    int n_obj_frames;      // 1 for a static object
 };
+
+// Offset, in voxels, of the object frame that ray r reads and writes: the
+// frame of its view times the voxels of one frame (0 for a static object).
+__host__ __device__ __forceinline__ int64_t frame_base(const int32_t *obj_frame, int64_t hw,
+                                                       int32_t r, int64_t vf) {
+    return obj_frame ? (int64_t)obj_frame[r / hw] * vf : 0;
+}
 
 // Slot -> ray id in the natural order: windows of 16x16 pixels of one view,
 // enumerated supertile by supertile (st x st windows, row-major inside), so
@@ -105,10 +116,11 @@ hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
                        const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
                        const int32_t *slice_len, int32_t *vox, float *len, int *err,
                        hipStream_t st);
+// vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.
 hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
-                              const float *rho, int B, int64_t V, float *y, hipStream_t st);
+                              const float *rho, int B, int64_t vf, float *y, hipStream_t st);
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
-                              const float *y, int B, int64_t V, float *x, hipStream_t st);
+                              const float *y, int B, int64_t vf, float *x, hipStream_t st);
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st);
 
 // ---- launchers (tsp_sort.hip) ----
@@ -134,23 +146,22 @@ hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int6
                           hipStream_t st);
 
 // ---- launchers (tsp_apply.hip) ----
-hipError_t launch_forward_sell(const int32_t *perm, const int32_t *cnt_sorted,
+// vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.
+hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
-                               const int32_t *vox, const float *len, int64_t n_slots,
-                               const float *rho, int B, int64_t V, int64_t R, float *y,
-                               hipStream_t st);
-// col_ptr is indexed by the angular-major key; each entry packs (natural slot
-// of the ray, length bits) as low / high 32 bits; x is written in (r, e, a)
-// order.  y is first copied into slot order (batch interleaved) in a
-// stream-ordered temporary.
+                               const int32_t *vox, const float *len, const float *rho, int B,
+                               int64_t vf, float *y, hipStream_t st);
+// col_ptr is indexed by object frame, then the angular-major key; each entry
+// packs (natural slot of the ray, length bits) as low / high 32 bits; x is
+// written in (frame, r, e, a) order.  y is first copied into slot order
+// (batch interleaved) in a stream-ordered temporary.
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
                               int nr, int ne, int na, const float *y, int B, float *x,
                               hipStream_t st);
-hipError_t launch_adjoint_atomic(const int32_t *perm, const int32_t *cnt_sorted,
-                                 const int64_t *slice_ptr, const int32_t *slice_len,
-                                 const int32_t *vox, const float *len, int64_t n_slots,
-                                 const float *y, int B, int64_t V, int64_t R, float *x,
-                                 hipStream_t st);
+hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
+                                 const int32_t *cnt_sorted, const int64_t *slice_ptr,
+                                 const int32_t *slice_len, const int32_t *vox, const float *len,
+                                 const float *y, int B, int64_t vf, float *x, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
 

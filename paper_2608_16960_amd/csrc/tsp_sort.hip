@@ -156,12 +156,15 @@ __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t 
     const int lane = (int)(slot & 63);
     const int64_t dst = row_ptr[r];
     const int64_t ns = natural_slot(rd, slot, r);
+    // key: object frame of the ray's view, then the voxel in angular-major order
+    const int32_t fbase =
+        (int32_t)frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, r, (int64_t)nr * ne * na);
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
         const int32_t v = vox[i];
         const float l = len[i];
         if (keys) {
-            keys[dst + j] = angular_major(v, nr, ne, na);
+            keys[dst + j] = fbase + angular_major(v, nr, ne, na);
             vals[dst + j] = (uint64_t)(uint32_t)ns | ((uint64_t)__float_as_uint(l) << 32);
         }
         if (out_vox) out_vox[dst + j] = v;

@@ -203,7 +203,8 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
     V3 x, n;
     ray_of(rd, ray, x, n);
     FwdVis<NB> vis;
-    vis.rho = rho;
+    vis.rho = rho + NB * frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, ray,
+                                    (int64_t)D.nr * D.ne * D.na);
 #pragma unroll
     for (int b = 0; b < NB; b++) vis.acc[b] = 0.0f;
     trace_ray(T, x, n, vis);
@@ -261,10 +262,13 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
     }
     Walker w;
     bool alive = false;
+    int32_t fb = 0;  // object frame of this ray, in voxels
     if (ray >= 0 && any) {  // a zero measurement contributes nothing
         V3 x, n;
         ray_of(rd, ray, x, n);
         alive = w.init(T, x, n);
+        fb = (int32_t)frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, ray,
+                                 (int64_t)D.nr * D.ne * D.na);
     }
     __syncthreads();
     for (;;) {
@@ -274,6 +278,7 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
             const bool seg = w.step(T, v, l);
             alive = !w.done();
             if (!seg) continue;
+            v += fb;
             const float lf = (float)l;
             unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
             bool done = false;
@@ -379,7 +384,8 @@ inline unsigned remapped_grid(int64_t n_slots) {  // windows, padded to a multip
 }
 
 hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
-                              const float *rho, int B, int64_t V, float *y, hipStream_t st) {
+                              const float *rho, int B, int64_t vf, float *y, hipStream_t st) {
+    const int64_t V = vf * rd.n_obj_frames;  // voxels of all object frames
     const size_t sh = T.n_tab * sizeof(double);
     const dim3 grid(remapped_grid(rd.n_slots));
     float *vm = nullptr;
@@ -407,7 +413,8 @@ hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc
 
 // x must be zero on entry for B == 1 (the caller clears it).
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
-                              const float *y, int B, int64_t V, float *x, hipStream_t st) {
+                              const float *y, int B, int64_t vf, float *x, hipStream_t st) {
+    const int64_t V = vf * rd.n_obj_frames;  // voxels of all object frames
     const size_t sh = T.n_tab * sizeof(double) + (B == 1 ? OtfHash<1>::kBytes : OtfHash<4>::kBytes);
     const dim3 grid(remapped_grid(rd.n_slots));
     if (B == 1) {

@@ -44,7 +44,8 @@ class tsp_info(ctypes.Structure):
     _fields_ = [("n_rays", ctypes.c_int64), ("n_voxels", ctypes.c_int64),
                 ("n_segments", ctypes.c_int64), ("n_stored", ctypes.c_int64),
                 ("max_per_ray", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("mode", ctypes.c_int32), ("has_csc", ctypes.c_int32)]
+                ("mode", ctypes.c_int32), ("has_csc", ctypes.c_int32),
+                ("n_obj_frames", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -56,6 +57,7 @@ SIGNATURES = {
     "tsp_geometry_create": (_st, [ctypes.POINTER(tsp_grid_desc), ctypes.POINTER(tsp_cone_view),
                                   ctypes.c_int32, _dp, _dp, ctypes.c_int64,
                                   ctypes.POINTER(_vp)]),
+    "tsp_set_object_frames": (_st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "tsp_trace": (_st, [_vp, ctypes.c_int32, _vp]),
     "tsp_forward": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "tsp_backproject": (_st, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp]),

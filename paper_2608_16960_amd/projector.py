@@ -34,9 +34,12 @@ class Projector:
     rays   (starts, dirs) explicit rays (float64 (R, 3) each)
     mode   "csr" (precomputed segment lists) or "onthefly" (recomputed per call)
     csc    build the voxel-major store for the deterministic adjoint (csr mode)
+    frames dynamic object (Sec. 4.4): object frame of each cone view; objects
+           are then (..., F, Nr, Ne, Na) with F = n_frames or max(frames) + 1
     """
 
-    def __init__(self, grid, views=None, rays=None, mode="csr", csc=True, device=None):
+    def __init__(self, grid, views=None, rays=None, mode="csr", csc=True, device=None,
+                 frames=None, n_frames=None):
         if (views is None) == (rays is None):
             raise ValueError("give either views or rays")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
@@ -73,6 +76,13 @@ class Projector:
                 self.out_shape = (s.shape[0],)
         self._h = handle
         self.mode = mode
+        self.obj_shape = self.shape
+        if frames is not None:
+            fr = np.ascontiguousarray(frames, np.int32).reshape(-1)
+            F = int(n_frames) if n_frames is not None else int(fr.max()) + 1
+            N.check(N.lib.tsp_set_object_frames(
+                self._h, fr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), F))
+            self.obj_shape = (F, *self.shape)
         self.retrace(mode, csc)
 
     # ------------------------------------------------------------------ state
@@ -116,12 +126,14 @@ class Projector:
 
     # ------------------------------------------------------------------ compute
     def forward(self, rho, out=None):
-        """y = F rho.  rho: (..., Nr, Ne, Na) float32 on the projector's GPU.
+        """y = F rho.  rho: (..., *obj_shape) float32 on the projector's GPU,
+        obj_shape = (Nr, Ne, Na), or (F, Nr, Ne, Na) for a dynamic object.
         Returns (..., *out_shape) float32."""
         rho = self._dev_f32(rho, "rho")
-        if tuple(rho.shape[-3:]) != self.shape:
-            raise ValueError(f"rho must end in {self.shape}, got {tuple(rho.shape)}")
-        lead = rho.shape[:-3]
+        k = len(self.obj_shape)
+        if tuple(rho.shape[rho.dim() - k:]) != self.obj_shape:
+            raise ValueError(f"rho must end in {self.obj_shape}, got {tuple(rho.shape)}")
+        lead = rho.shape[:rho.dim() - k]
         B = int(np.prod(lead)) if lead else 1
         y = out if out is not None else torch.empty((*lead, *self.out_shape),
                                                     dtype=torch.float32, device=self.device)
@@ -137,8 +149,8 @@ class Projector:
             raise ValueError(f"y must end in {self.out_shape}, got {tuple(y.shape)}")
         lead = y.shape[:y.dim() - k]
         B = int(np.prod(lead)) if lead else 1
-        x = out if out is not None else torch.empty((*lead, *self.shape), dtype=torch.float32,
-                                                    device=self.device)
+        x = out if out is not None else torch.empty((*lead, *self.obj_shape),
+                                                    dtype=torch.float32, device=self.device)
         if self.mode == "onthefly":
             method = "atomic"
         if B:

@@ -116,6 +116,8 @@ def test_table_limit_is_inclusive():
 def test_null_geometry_calls():
     from paper_2608_16960_amd import native as N
     assert N.lib.tsp_trace(None, N.TSP_MODE_CSR, None) == N.TSP_E_INVALID
+    fr = (ctypes.c_int32 * 1)(0)
+    assert N.lib.tsp_set_object_frames(None, fr, 1) == N.TSP_E_INVALID
     assert N.lib.tsp_forward(None, None, 1, None, None) == N.TSP_E_INVALID
     assert N.lib.tsp_backproject(None, None, 1, None, 1, None) == N.TSP_E_INVALID
     info = N.tsp_info()

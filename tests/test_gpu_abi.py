@@ -79,3 +79,40 @@ def test_projector_falls_back_to_onthefly_adjoint():
     y = P.forward(torch.from_numpy(w.rho).cuda())
     x = P.backproject(y)  # no error: switches to the atomic adjoint
     assert torch.isfinite(x).all() and float(x.abs().sum()) > 0
+
+
+def test_object_frame_errors():
+    """tsp_set_object_frames: frame index out of range, too many frames,
+    after tsp_trace (state), and on explicit rays (unsupported)."""
+    assert torch.cuda.is_available()
+    from paper_2608_16960_amd import native as N
+    w = W.tiny()
+    h, keep = _geometry(N, w)
+    I32 = ctypes.c_int32 * w.views.n_views
+    s = N.stream_handle()
+    try:
+        assert N.lib.tsp_set_object_frames(h, I32(0, 1, 2, 3), 3) == N.TSP_E_INVALID
+        assert N.lib.tsp_set_object_frames(h, I32(0, 0, -1, 0), 2) == N.TSP_E_INVALID
+        assert N.lib.tsp_set_object_frames(h, I32(0, 0, 0, 0), 0) == N.TSP_E_INVALID
+        assert N.lib.tsp_set_object_frames(h, I32(0, 0, 0, 0), 1 << 30) == N.TSP_E_INVALID
+        assert N.lib.tsp_set_object_frames(h, I32(0, 1, 1, 0), 2) == N.TSP_OK
+        assert N.lib.tsp_set_object_frames(h, I32(1, 0, 1, 0), 2) == N.TSP_OK  # replace
+        assert N.lib.tsp_trace(h, N.TSP_MODE_CSR, s) == N.TSP_OK
+        inf = N.tsp_info()
+        assert N.lib.tsp_query(h, ctypes.byref(inf)) == N.TSP_OK and inf.n_obj_frames == 2
+        assert N.lib.tsp_set_object_frames(h, I32(0, 0, 0, 0), 1) == N.TSP_E_STATE
+    finally:
+        N.lib.tsp_geometry_destroy(h)
+    g = w.grid
+    arrs = [np.ascontiguousarray(a, np.float64) for a in g.arrays()]
+    gd = N.tsp_grid_desc(*g.shape, *[a.ctypes.data_as(N._dp) for a in arrs])
+    st, di = W.random_rays(10, np.random.default_rng(0))
+    st, di = np.ascontiguousarray(st), np.ascontiguousarray(di)
+    h2 = ctypes.c_void_p()
+    assert N.lib.tsp_geometry_create(ctypes.byref(gd), None, 0, st.ctypes.data_as(N._dp),
+                                     di.ctypes.data_as(N._dp), 10, ctypes.byref(h2)) == N.TSP_OK
+    try:
+        assert N.lib.tsp_set_object_frames(h2, (ctypes.c_int32 * 1)(0), 1) == \
+            N.TSP_E_UNSUPPORTED
+    finally:
+        N.lib.tsp_geometry_destroy(h2)
