@@ -22,7 +22,11 @@
  *      lies on the cone's own nappe, every hit of every azimuth half-plane,
  *      plus the point where the ray crosses the polar axis when its
  *      projection on the xy-plane passes exactly through the origin (the
- *      azimuth jumps by pi there without touching any half-plane);
+ *      azimuth jumps by pi there without touching any half-plane), and the
+ *      start l = 0 itself, so that a ray starting inside the grid (the
+ *      sunward rays from voxel centroids of Sec. 9.3) integrates from its
+ *      start; for a start outside the grid the first interval lies outside
+ *      and is dropped;
  *   3. sorts them (Sec. 3.3);
  *   4. classifies the midpoint of every positive-length interval by its
  *      spherical coordinates (r, colatitude, azimuth) with an upper-bound
@@ -180,6 +184,9 @@ static int64_t trace_ray(const ogrid *g, const double x[3], const double nin[3],
         tout = -xn + sqrt(dsc_o);
     }
 #define INSIDE(tt) ((tt) > tin - tol && (tt) < tout + tol)
+
+    /* the start of the ray (l = 0) */
+    T[nt++] = 0.0;
 
     /* spheres: |x + n t|^2 = R^2  ->  t^2 + 2 (x.n) t + (|x|^2 - R^2) = 0 */
     for (int k = 0; k <= g->nr; k++) {
