@@ -11,6 +11,9 @@ Contents
     Sec. 3), forward and adjoint;
   - ``dynamic``: forward and adjoint for dynamic (4-D) objects, one object
     frame per view (Sec. 4.4, 4.6), on the oracle's segment lists;
+  - ``atten``: the attenuated emission model (Sec. 9.3, Eqs. 14-18) and its
+    gradient, from the oracle's segment lists (sunward rays from voxel
+    centroids for tau_1, inclusive cumulative sums along each line of sight);
   - ``reg``: anisotropic smoothed total variation and the Adam update;
   - ``conv``: 3x3x3 convolution with circular azimuth padding (PyTorch CPU
     conv3d in float64 as the library step).
