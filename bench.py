@@ -15,8 +15,9 @@ Prints ONE JSON line: rays/s of forward+adjoint as `value`, segments/s and
 per-kernel roofline fractions alongside, the CPU FP64 oracle timed on the host
 cores, and the trace time.  Unless --quick, it also measures (as extra fields)
 the on-the-fly mode on the Large workload (batch 4, no segment storage), the
-stored-list path on the Differentiation workload, and the learned warm start
-(projector calls to reach the plain solver's residual, 200 held-out phantoms).
+stored-list path on the Differentiation workload, the attenuated emission
+model on Medium, and the learned warm start (projector calls to reach the
+plain solver's residual, 200 held-out phantoms).
 """
 import argparse
 import json
@@ -227,6 +228,41 @@ def extra_diff_csr():
             "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS}
 
 
+def extra_atten_medium(reps=10):
+    """Attenuated emission model (Sec. 9.3) on the Medium workload: one
+    forward (sunward optical depths, then the line-of-sight pass with the
+    running absorption) and one backward per call, batch 1."""
+    import numpy as np
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.atten import Attenuated
+    from paper_2608_16960_amd.projector import Projector
+    w = W.medium()
+    P = Projector(w.grid, views=w.views)
+    sig = torch.from_numpy(np.random.default_rng(70).uniform(0.02, 0.3, w.grid.shape)
+                           .astype(np.float32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    M = Attenuated(P, sig, [0.0, 1.0, 0.0])
+    torch.cuda.synchronize()
+    sun_s = time.perf_counter() - t0
+    rho = torch.from_numpy(w.rho).cuda()
+    y, tau = M.forward(rho, keep_tau=True)
+    gy = torch.randn_like(y)
+    f_ms = _time_ms(lambda: M.forward(rho, keep_tau=True), reps)
+    b_ms = _time_ms(lambda: M.backward(rho, tau, gy), reps)
+    inf, infs = P.info(), M.sun.info()
+    R = inf["n_rays"]
+    out = {"workload": f"medium with attenuation: {R} lines of sight, {inf['n_voxels']} sunward "
+                       f"rays, {inf['n_segments']} + {infs['n_segments']} segments, batch 1",
+           "sun_trace_s": sun_s, "forward_ms": f_ms, "backward_ms": b_ms,
+           "forward_rays_per_s": R / f_ms * 1e3, "forward_backward_rays_per_s": R / (f_ms + b_ms) * 1e3}
+    P.close()
+    M.sun.close()
+    return out
+
+
 def extra_learned(epochs=6):
     import numpy as np
     import torch
@@ -368,6 +404,8 @@ def main():
         line["onthefly_large"] = extra_large_onthefly()
         _log("differentiation workload")
         line["diff_csr"] = extra_diff_csr()
+        _log("attenuated model")
+        line["attenuated_medium"] = extra_atten_medium()
         _log("learned warm start")
         line["learned_warm_start"] = extra_learned()
     if not a.no_cpu_baseline:

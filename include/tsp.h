@@ -33,7 +33,10 @@
  *     unit(w + sx u + sy v), sx = (2 (j + 1/2)/W - 1) tan(fov_w/2),
  *     sy = (2 (i + 1/2)/H - 1) tan(fov_h/2).  Ray id = (view*H + i)*W + j.
  *     Measurements are float32 arrays [batch][n_rays].
- *   - Every ray must start outside the outermost sphere (Sec. 4.6).
+ *   - Cone views must sit outside the outermost sphere (Sec. 4.6).  Explicit
+ *     rays may start anywhere, inside the grid too: a ray integrates over
+ *     l >= 0 from its start (Eq. 3), as the sunward rays from voxel
+ *     centroids of Sec. 9.3 need.
  *
  * Ownership and streams
  *   - A geometry owns every device buffer it allocates (tables, view frames,
@@ -123,8 +126,8 @@ typedef struct tsp_geometry tsp_geometry;
  * non-zero length, normalised by the library; Sec. 4.2 Listing 4).
  * Validates the grid (finite, strictly increasing, ranges above), the views
  * (finite, pos outside the outer sphere, fov in (0, 180), equal shapes, pos
- * != look) and the rays (finite, non-zero direction, start outside the outer
- * sphere: TSP_E_INVALID otherwise).  Limits (TSP_E_INVALID beyond them):
+ * != look) and the rays (finite, non-zero direction: TSP_E_INVALID
+ * otherwise).  Limits (TSP_E_INVALID beyond them):
  * fewer than 2^31 voxels and 2^31 rays (after padding cone views to 16x16
  * pixel windows), and nr + ne + 3 na <= 5627 (the boundary tables are staged
  * in workgroup-shared memory).  Uploads boundary tables and per-view
@@ -190,6 +193,58 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
  */
 tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
                            int32_t method, void *stream);
+
+/*
+ * Attenuated emission model (Sec. 9.3, Eqs. 14-18).
+ *
+ * Sunward geometry: one explicit ray per voxel v, starting at v's centroid
+ * (mid-boundaries r_c, theta_c, phi_c of the voxel's boundaries) and running
+ * along sun_dir (host double[3], finite and non-zero; normalised).  Ray v
+ * belongs to voxel v, so the projection of an object along these rays is the
+ * optical depth towards the Sun of every voxel (Eq. 17's F_1).  The result is
+ * an ordinary explicit-ray geometry (released with tsp_geometry_destroy) to
+ * be traced with tsp_trace before use; with the transposed store its adjoint
+ * in tsp_atten_backward is deterministic, otherwise atomic.  Errors as for
+ * tsp_geometry_create.
+ */
+tsp_status tsp_geometry_create_sunward(const tsp_grid_desc *grid, const double *sun_dir,
+                                       tsp_geometry **out);
+
+/*
+ * Attenuated forward for batch objects (Eq. 17):
+ *   s = sigma * rho, tau1 = F_sun s, w = exp(-tau1) * rho,
+ *   y[b][i] = sum_k w[b][v_k] exp(-T_k) len_k,  T_k = sum_{j <= k} s[b][v_j] len_j,
+ * over ray i's segments in order of distance from the detector (Eq. 18: the
+ * sum includes segment k itself).  The constant g phi / 4 pi of Eq. 16 is the
+ * caller's.
+ * g: line-of-sight geometry traced in TSP_MODE_CSR, one object frame;
+ * g_sun: traced geometry from tsp_geometry_create_sunward on the same grid.
+ * rho: device float32 [batch][V]; sigma: device float32 [V], shared by the
+ * batch; y: device float32 [batch][R], overwritten; tau1: device float32
+ * [batch][V] receiving the sunward optical depths (keep them for
+ * tsp_atten_backward), or NULL.  Temporaries (3 floats per voxel and
+ * object) are stream-ordered allocations on `stream`.
+ * Errors: TSP_E_INVALID (NULL, batch < 1, g_sun not one ray per voxel of
+ * g's grid), TSP_E_STATE before tsp_trace, TSP_E_UNSUPPORTED (g on the fly or
+ * with object frames), TSP_E_HIP.
+ */
+tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
+                             const float *sigma, int32_t batch, float *y, float *tau1,
+                             void *stream);
+
+/*
+ * Gradient of sum_b <gy[b], y[b]> with respect to rho for the attenuated
+ * forward: through w (exp(-tau1) gw), through T along each line of sight, and
+ * through tau1 (F_sun^T of -w gw).  The line-of-sight scatter uses atomic
+ * adds, so the result is not bitwise reproducible.
+ * rho, sigma as for tsp_atten_forward; tau1: [batch][V] from
+ * tsp_atten_forward of the same rho; gy: device float32 [batch][R];
+ * grad: device float32 [batch][V], overwritten.  Temporaries: 6 floats per
+ * voxel and object, stream-ordered.  Errors as for tsp_atten_forward.
+ */
+tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
+                              const float *sigma, const float *tau1, const float *gy,
+                              int32_t batch, float *grad, void *stream);
 
 /*
  * Export the canonical segment lists (the region index and length arrays of

@@ -173,6 +173,74 @@ tsp_status sync_stream(hipStream_t st) {
 
 }  // namespace
 
+namespace {
+
+// y = F rho on a traced geometry (either mode).
+hipError_t forward_dispatch(const tsp_geometry *g, const float *rho, int batch, float *y,
+                            hipStream_t st) {
+    if (g->mode == TSP_MODE_CSR)
+        return launch_forward_sell(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                   g->d_slice_len, g->d_vox, g->d_len, rho, batch, g->V, y, st);
+    return launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
+}
+
+// x = F^T y; TSP_ADJ_DETERMINISTIC needs the transposed store (checked by callers).
+hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, float *x,
+                            int method, hipStream_t st) {
+    if (method == TSP_ADJ_DETERMINISTIC)
+        return launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_ent, g->T.nr, g->T.ne, g->T.na,
+                                  y, batch, x, st);
+    hipError_t e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
+    if (e != hipSuccess) return e;
+    if (g->mode == TSP_MODE_CSR)
+        return launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                     g->d_slice_len, g->d_vox, g->d_len, y, batch, g->V, x, st);
+    return launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+}
+
+// Checks shared by the attenuated forward and backward (Sec. 9.3).
+tsp_status atten_check(const tsp_geometry *g, const tsp_geometry *gs, int32_t batch) {
+    if (!g || !gs) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
+    if (g->mode == 0 || gs->mode == 0)
+        return fail(TSP_E_STATE, "attenuated model before tsp_trace");
+    if (g->mode != TSP_MODE_CSR)
+        return fail(TSP_E_UNSUPPORTED, "attenuated model needs the line-of-sight geometry in "
+                                       "TSP_MODE_CSR");
+    if (g->rd.n_obj_frames != 1 || gs->rd.n_obj_frames != 1)
+        return fail(TSP_E_UNSUPPORTED, "attenuated model with object frames");
+    if (gs->R != g->V || gs->V != g->V || gs->device != g->device)
+        return fail(TSP_E_INVALID, "sunward geometry must have one ray per voxel of the same "
+                                   "grid, on the same device");
+    return TSP_OK;
+}
+
+// Stream-ordered temporaries of n floats each, released together.
+struct AsyncBufs {
+    hipStream_t st;
+    std::vector<void *> ps;
+    explicit AsyncBufs(hipStream_t s) : st(s) {}
+    float *get(int64_t n, hipError_t *e) {
+        void *p = nullptr;
+        if (*e == hipSuccess) *e = hipMallocAsync(&p, (size_t)(n > 0 ? n : 1) * sizeof(float), st);
+        if (*e != hipSuccess) return nullptr;
+        ps.push_back(p);
+        return (float *)p;
+    }
+    hipError_t release() {
+        hipError_t r = hipSuccess;
+        for (void *p : ps) {
+            const hipError_t e = hipFreeAsync(p, st);
+            if (r == hipSuccess) r = e;
+        }
+        ps.clear();
+        return r;
+    }
+    ~AsyncBufs() { (void)release(); }
+};
+
+}  // namespace
+
 extern "C" {
 
 const char *tsp_last_error(void) { return g_err.c_str(); }
@@ -269,12 +337,7 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
             if (!finite3(x) || !finite3(d)) return fail(TSP_E_INVALID, "ray not finite");
             const double dn = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
             if (!(dn > 0)) return fail(TSP_E_INVALID, "zero ray direction");
-            if (std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) <= Rout) {
-                char buf[128];
-                std::snprintf(buf, sizeof buf, "ray %lld starts inside the grid's outer sphere",
-                              (long long)i);
-                return fail(TSP_E_INVALID, buf);
-            }
+            // explicit rays may start inside the grid (integral over l >= 0)
             for (int k = 0; k < 3; k++) dirs[3 * i + k] = d[k] / dn;
         }
     }
@@ -604,13 +667,7 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
     if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_forward before tsp_trace");
     DeviceGuard dg(g->device);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (g->mode == TSP_MODE_CSR)
-        e = launch_forward_sell(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                g->d_slice_len, g->d_vox, g->d_len, rho, batch, g->V, y, st);
-    else
-        e = launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
+    const hipError_t e = forward_dispatch(g, rho, batch, y, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("forward: ") + hipGetErrorString(e));
     return TSP_OK;
 }
@@ -624,27 +681,113 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
     if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC)
         return fail(TSP_E_INVALID, "method must be TSP_ADJ_DETERMINISTIC or TSP_ADJ_ATOMIC");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject before tsp_trace");
+    if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
+        return fail(TSP_E_UNSUPPORTED,
+                    "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
     DeviceGuard dg(g->device);
-    hipStream_t st = (hipStream_t)stream;
-    hipError_t e;
-    if (method == TSP_ADJ_DETERMINISTIC) {
-        if (g->mode != TSP_MODE_CSR || !g->d_col_ptr)
-            return fail(TSP_E_UNSUPPORTED,
-                        "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
-        e = launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_ent, g->T.nr, g->T.ne, g->T.na, y,
-                               batch, x, st);
-    } else {
-        e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
-        if (e == hipSuccess) {
-            if (g->mode == TSP_MODE_CSR)
-                e = launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                          g->d_slice_len, g->d_vox, g->d_len, y, batch, g->V, x,
-                                          st);
-            else
-                e = launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+    const hipError_t e = adjoint_dispatch(g, y, batch, x, method, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_geometry_create_sunward(const tsp_grid_desc *grid, const double *sun_dir,
+                                       tsp_geometry **out) {
+    g_err.clear();
+    if (!out) return fail(TSP_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!grid || !grid->r_b || !grid->e_b || !grid->a_b || !sun_dir)
+        return fail(TSP_E_INVALID, "grid or sun_dir is NULL");
+    if (grid->nr < 1 || grid->ne < 1 || grid->na < 1)
+        return fail(TSP_E_INVALID, "grid shape must be >= 1");
+    if (!finite3(sun_dir)) return fail(TSP_E_INVALID, "sun_dir not finite");
+    const double dn = std::sqrt(sun_dir[0] * sun_dir[0] + sun_dir[1] * sun_dir[1] +
+                                sun_dir[2] * sun_dir[2]);
+    if (!(dn > 0)) return fail(TSP_E_INVALID, "zero sun_dir");
+    const int nr = grid->nr, ne = grid->ne, na = grid->na;
+    const int64_t V = (int64_t)nr * ne * na;
+    if (V >= ((int64_t)1 << 31)) return fail(TSP_E_INVALID, "too many voxels (>= 2^31)");
+    // centroids at the mid-boundaries (r_c, theta_c, phi_c), voxel order (ir, ie, ia)
+    std::vector<double> starts((size_t)(3 * V)), dirs((size_t)(3 * V));
+    for (int ir = 0; ir < nr; ir++) {
+        const double rc = 0.5 * (grid->r_b[ir] + grid->r_b[ir + 1]);
+        for (int ie = 0; ie < ne; ie++) {
+            const double tc = 0.5 * (grid->e_b[ie] + grid->e_b[ie + 1]);
+            for (int ia = 0; ia < na; ia++) {
+                const double pc = 0.5 * (grid->a_b[ia] + grid->a_b[ia + 1]);
+                const int64_t v = ((int64_t)ir * ne + ie) * na + ia;
+                starts[3 * v + 0] = rc * std::sin(tc) * std::cos(pc);
+                starts[3 * v + 1] = rc * std::sin(tc) * std::sin(pc);
+                starts[3 * v + 2] = rc * std::cos(tc);
+                for (int k = 0; k < 3; k++) dirs[3 * v + k] = sun_dir[k] / dn;
+            }
         }
     }
-    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
+    return tsp_geometry_create(grid, nullptr, 0, starts.data(), dirs.data(), V, out);
+}
+
+tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
+                             const float *sigma, int32_t batch, float *y, float *tau1,
+                             void *stream) {
+    g_err.clear();
+    tsp_status s;
+    if ((s = atten_check(g, g_sun, batch)) != TSP_OK) return s;
+    if (!rho || !sigma || !y) return fail(TSP_E_INVALID, "rho, sigma or y is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = g->V * batch;
+    hipError_t e = hipSuccess;
+    AsyncBufs tmp(st);
+    float *sv = tmp.get(n, &e);
+    float *t1 = tau1 ? tau1 : tmp.get(n, &e);
+    float *w = tmp.get(n, &e);
+    if (e == hipSuccess) e = launch_atten_s(sigma, rho, g->V, batch, sv, st);
+    if (e == hipSuccess) e = forward_dispatch(g_sun, sv, batch, t1, st);  // tau_1 = F_1 s
+    if (e == hipSuccess) e = launch_atten_w(t1, rho, n, w, st);
+    if (e == hipSuccess)
+        e = launch_fwd_atten(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
+                             g->d_vox, g->d_len, sv, w, batch, g->V, y, st);
+    const hipError_t r = tmp.release();
+    if (e == hipSuccess) e = r;
+    if (e != hipSuccess)
+        return fail(TSP_E_HIP, std::string("attenuated forward: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
+                              const float *sigma, const float *tau1, const float *gy,
+                              int32_t batch, float *grad, void *stream) {
+    g_err.clear();
+    tsp_status s;
+    if ((s = atten_check(g, g_sun, batch)) != TSP_OK) return s;
+    if (!rho || !sigma || !tau1 || !gy || !grad)
+        return fail(TSP_E_INVALID, "rho, sigma, tau1, gy or grad is NULL");
+    DeviceGuard dg(g->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = g->V * batch;
+    const int method = g_sun->d_col_ptr ? TSP_ADJ_DETERMINISTIC : TSP_ADJ_ATOMIC;
+    hipError_t e = hipSuccess;
+    AsyncBufs tmp(st);
+    float *sv = tmp.get(n, &e);
+    float *w = tmp.get(n, &e);
+    float *gw = tmp.get(n, &e);
+    float *gsl = tmp.get(n, &e);
+    float *gt = tmp.get(n, &e);
+    float *gsun = tmp.get(n, &e);
+    if (e == hipSuccess) e = launch_atten_s(sigma, rho, g->V, batch, sv, st);
+    if (e == hipSuccess) e = launch_atten_w(tau1, rho, n, w, st);
+    if (e == hipSuccess) e = launch_zero_f32(gw, n, st);
+    if (e == hipSuccess) e = launch_zero_f32(gsl, n, st);
+    if (e == hipSuccess)
+        e = launch_bwd_atten(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
+                             g->d_vox, g->d_len, sv, w, gy, batch, g->V, gw, gsl, st);
+    if (e == hipSuccess) e = launch_atten_gtau(w, gw, n, gt, st);
+    if (e == hipSuccess) e = adjoint_dispatch(g_sun, gt, batch, gsun, method, st);  // F_1^T
+    if (e == hipSuccess)
+        e = launch_atten_grad(tau1, sigma, gw, gsl, gsun, g->V, batch, grad, st);
+    const hipError_t r = tmp.release();
+    if (e == hipSuccess) e = r;
+    if (e != hipSuccess)
+        return fail(TSP_E_HIP, std::string("attenuated backward: ") + hipGetErrorString(e));
     return TSP_OK;
 }
 

@@ -1,0 +1,212 @@
+// Attenuated emission model (TomoSphero Sec. 9.3, Eqs. 14-18) on gfx950.
+//
+// With s = sigma * rho and w = exp(-tau_1) * rho, where tau_1 is the
+// projection of s along the sunward rays from the voxel centroids (Eq. 17's
+// F_1, an ordinary explicit-ray geometry), a line of sight measures
+//
+//     y = sum_k w[v_k] exp(-T_k) len_k,    T_k = sum_{j <= k} s[v_j] len_j,
+//
+// its segments taken in order of distance from the detector (the inclusive
+// cumulative sum of Eq. 18).  The ray-major store keeps every ray's segments
+// in that order, so one lane walks its ray front to back with a running T:
+// the same stream as the plain forward, two gathers per segment instead of
+// one, and one exp.
+//
+// The backward (the gradient of <g, y> with respect to rho) needs, per
+// segment k of ray i,
+//     dy/dw[v_k] += g_i exp(-T_k) len_k
+//     dy/ds[v_k] -= g_i len_k sum_{m >= k} w[v_m] exp(-T_m) len_m,
+// the suffix sum being y_i minus the running prefix.  A first pass over the
+// ray's segments gives y_i, a second emits both terms; lanes that hit the
+// same voxel in the same step are summed before one atomic add, as in the
+// atomic adjoint.  The chain rule through w and tau_1 (F_1^T) and the
+// elementwise combination run as separate small kernels.
+
+#include "tsp_internal.h"
+
+namespace tsp {
+namespace {
+
+inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// s[b][v] = sigma[v] * rho[b][v]
+__global__ void k_atten_s(const float *sigma, const float *rho, int64_t V, int64_t n, float *s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) s[i] = sigma[i % V] * rho[i];
+}
+
+// w = exp(-tau1) * rho
+__global__ void k_atten_w(const float *tau1, const float *rho, int64_t n, float *w) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = expf(-tau1[i]) * rho[i];
+}
+
+// out = -w * gw  (gradient reaching tau_1)
+__global__ void k_atten_gtau(const float *w, const float *gw, int64_t n, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = -w[i] * gw[i];
+}
+
+// grad = exp(-tau1) * gw + sigma * (gs + gs_sun)
+__global__ void k_atten_grad(const float *tau1, const float *sigma, const float *gw,
+                             const float *gs, const float *gs_sun, int64_t V, int64_t n,
+                             float *grad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) grad[i] = expf(-tau1[i]) * gw[i] + sigma[i % V] * (gs[i] + gs_sun[i]);
+}
+
+// One lane per ray slot of the ray-major store (see tsp_apply.hip for the
+// layout); segment j of the lane at sell_index(base, lane, j), j in order of
+// distance from the detector; padding entries have length 0.
+__global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ cnt_sorted,
+                                                    const int64_t *__restrict__ slice_ptr,
+                                                    const int32_t *__restrict__ slice_len,
+                                                    const int32_t *__restrict__ vox,
+                                                    const float *__restrict__ len,
+                                                    int64_t n_slots, const float *__restrict__ s,
+                                                    const float *__restrict__ w,
+                                                    float *__restrict__ y) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t ray = perm[slot];
+    if (ray < 0) return;
+    const int c = cnt_sorted[slot];
+    const int64_t base = slice_ptr[slot >> 6];
+    const int lane = (int)(slot & 63);
+    float T = 0.0f, acc = 0.0f;
+    for (int j = 0; j < c; j++) {
+        const int64_t i = sell_index(base, lane, j);
+        const int32_t v = __builtin_nontemporal_load(vox + i);
+        const float l = __builtin_nontemporal_load(len + i);
+        T = fmaf(s[v], l, T);
+        acc = fmaf(w[v] * expf(-T), l, acc);
+    }
+    y[ray] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ cnt_sorted,
+                                                    const int64_t *__restrict__ slice_ptr,
+                                                    const int32_t *__restrict__ slice_len,
+                                                    const int32_t *__restrict__ vox,
+                                                    const float *__restrict__ len,
+                                                    int64_t n_slots, const float *__restrict__ s,
+                                                    const float *__restrict__ w,
+                                                    const float *__restrict__ gy, float *gw,
+                                                    float *gs) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
+    const int lane = (int)(slot & 63);
+    const int32_t ray = perm[slot];
+    const int c = (ray >= 0) ? cnt_sorted[slot] : 0;
+    const int m = slice_len[slot >> 6];
+    const int64_t base = slice_ptr[slot >> 6];
+    const float g = (ray >= 0) ? gy[ray] : 0.0f;
+    // pass 1: the ray's measurement (the total that the suffix sums start from)
+    float T = 0.0f, yr = 0.0f;
+    for (int j = 0; j < c; j++) {
+        const int64_t i = sell_index(base, lane, j);
+        const int32_t v = vox[i];
+        const float l = len[i];
+        T = fmaf(s[v], l, T);
+        yr = fmaf(w[v] * expf(-T), l, yr);
+    }
+    // pass 2: both gradient terms of every segment, merged across the wavefront
+    T = 0.0f;
+    float prefix = 0.0f;
+    for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
+        int v = -1;
+        float a = 0.0f, bterm = 0.0f;
+        if (j < c) {
+            const int64_t i = sell_index(base, lane, j);
+            v = vox[i];
+            const float l = len[i];
+            T = fmaf(s[v], l, T);
+            const float E = expf(-T);
+            const float ck = w[v] * E * l;
+            a = g * E * l;
+            bterm = -g * l * (yr - prefix);
+            prefix += ck;
+        }
+        uint64_t pend = __ballot(v >= 0);
+        while (pend) {
+            const int leader = __ffsll((unsigned long long)pend) - 1;
+            const int v0 = __shfl(v, leader, kWave);
+            const bool mine = (v == v0);
+            float sa = mine ? a : 0.0f, sb = mine ? bterm : 0.0f;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                sa += __shfl_xor(sa, o, kWave);
+                sb += __shfl_xor(sb, o, kWave);
+            }
+            if (lane == leader) {
+                atomicAdd(gw + v0, sa);
+                atomicAdd(gs + v0, sb);
+            }
+            pend &= ~__ballot(mine);
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_atten_s(const float *sigma, const float *rho, int64_t V, int B, float *s,
+                          hipStream_t st) {
+    const int64_t n = V * B;
+    hipLaunchKernelGGL(k_atten_s, dim3(blocks_for(n, 256)), dim3(256), 0, st, sigma, rho, V, n,
+                       s);
+    return hipGetLastError();
+}
+
+hipError_t launch_atten_w(const float *tau1, const float *rho, int64_t n, float *w,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_atten_w, dim3(blocks_for(n, 256)), dim3(256), 0, st, tau1, rho, n, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_atten_gtau(const float *w, const float *gw, int64_t n, float *out,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_atten_gtau, dim3(blocks_for(n, 256)), dim3(256), 0, st, w, gw, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_atten_grad(const float *tau1, const float *sigma, const float *gw,
+                             const float *gs, const float *gs_sun, int64_t V, int B, float *grad,
+                             hipStream_t st) {
+    const int64_t n = V * B;
+    hipLaunchKernelGGL(k_atten_grad, dim3(blocks_for(n, 256)), dim3(256), 0, st, tau1, sigma, gw,
+                       gs, gs_sun, V, n, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                            const int64_t *slice_ptr, const int32_t *slice_len,
+                            const int32_t *vox, const float *len, const float *s, const float *w,
+                            int B, int64_t V, float *y, hipStream_t st) {
+    for (int b = 0; b < B; b++) {
+        hipLaunchKernelGGL(k_fwd_atten, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
+                           cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, s + b * V,
+                           w + b * V, y + b * rd.R);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                            const int64_t *slice_ptr, const int32_t *slice_len,
+                            const int32_t *vox, const float *len, const float *s, const float *w,
+                            const float *gy, int B, int64_t V, float *gw, float *gs,
+                            hipStream_t st) {
+    for (int b = 0; b < B; b++) {
+        hipLaunchKernelGGL(k_bwd_atten, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
+                           cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, s + b * V,
+                           w + b * V, gy + b * rd.R, gw + b * V, gs + b * V);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace tsp

@@ -163,6 +163,27 @@ hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *slice_len, const int32_t *vox, const float *len,
                                  const float *y, int B, int64_t vf, float *x, hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
+
+// ---- launchers (tsp_atten.hip): attenuated emission model, one object per
+// launch of the line-of-sight kernels; arrays [B][V] / [B][R] ----
+hipError_t launch_atten_s(const float *sigma, const float *rho, int64_t V, int B, float *s,
+                          hipStream_t st);
+hipError_t launch_atten_w(const float *tau1, const float *rho, int64_t n, float *w,
+                          hipStream_t st);
+hipError_t launch_atten_gtau(const float *w, const float *gw, int64_t n, float *out,
+                             hipStream_t st);
+hipError_t launch_atten_grad(const float *tau1, const float *sigma, const float *gw,
+                             const float *gs, const float *gs_sun, int64_t V, int B, float *grad,
+                             hipStream_t st);
+hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                            const int64_t *slice_ptr, const int32_t *slice_len,
+                            const int32_t *vox, const float *len, const float *s, const float *w,
+                            int B, int64_t V, float *y, hipStream_t st);
+hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                            const int64_t *slice_ptr, const int32_t *slice_len,
+                            const int32_t *vox, const float *len, const float *s, const float *w,
+                            const float *gy, int B, int64_t V, float *gw, float *gs,
+                            hipStream_t st);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
 
 }  // namespace tsp

@@ -211,7 +211,9 @@ struct Walker {
         }
     }
 
-    // Returns false when the ray misses the grid (nothing to walk).
+    // Returns false when the ray misses the grid (nothing to walk).  A ray
+    // may start inside the outer sphere: the walk then begins at l = 0 in the
+    // region that holds the start (l >= 0 only, Eq. 3).
     TSP_HD bool init(const Tab &T, const V3 &x_, const V3 &n_) {
         x = x_;
         n = n_;
@@ -228,33 +230,61 @@ struct Walker {
         const double b2 = cx * cx + cy * cy + cz * cz;
         const double Ro = T.rb[nr];
         tc = -xn;
-        if (!(tc > 0.0) || !(b2 < Ro * Ro)) return false;  // moving away, or misses
+        if (!(b2 < Ro * Ro)) return false;  // misses the outer sphere
         b = sqrt(b2);
         const double hch = sqrt((Ro - b) * (Ro + b));
         tin = tc - hch;
         tout = tc + hch;
+        if (!(tout > 0.0)) return false;  // the sphere lies behind the start
+        const bool inner = tin < 0.0;      // the start is inside the outer sphere
+        if (inner) tin = 0.0;
 
         // radial stream
         kb = count_le(T.rb, nr + 1, b);  // shells kb..nr-1 are crossed twice
-        ir = nr - 1;
-        rk = nr - 1;
-        if (kb <= nr - 1) {
-            rstage = 0;
-            t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+        if (!inner) {
+            ir = nr - 1;
+            rk = nr - 1;
+            if (kb <= nr - 1) {
+                rstage = 0;
+                t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+            } else {
+                rstage = 2;
+                t_r = tout;
+            }
         } else {
-            rstage = 2;
-            t_r = tout;
+            // shell of the start (-1 in the inner hole); inbound crossings of
+            // spheres ir..kb remain while moving towards the centre, else
+            // outbound crossings of ir+1..nr-1, then the exit
+            ir = count_le(T.rb, nr + 1, sqrt(xx)) - 1;
+            if (tc > 0.0 && ir >= kb) {
+                rstage = 0;
+                rk = ir;
+                t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+            } else {
+                rk = ir + 1;
+                if (rk <= nr - 1) {
+                    rstage = 1;
+                    t_r = tc + sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                } else {
+                    rstage = 2;
+                    t_r = tout;
+                }
+            }
         }
 
-        // classification at entry and exit of the outer sphere
+        // classification at entry (or start) and exit of the outer sphere
         const V3 pin = {x.x + n.x * tin, x.y + n.y * tin, x.z + n.z * tin};
         const V3 pout = {x.x + n.x * tout, x.y + n.y * tout, x.z + n.z * tout};
         const double rin = sqrt(pin.x * pin.x + pin.y * pin.y + pin.z * pin.z);
         const double rout = sqrt(pout.x * pout.x + pout.y * pout.y + pout.z * pout.z);
-        ie = class_e(T, pin.z / rin);
+        // A start at the origin, or on the polar axis, lies on region
+        // boundaries: the region the ray enters is the one its direction
+        // points into.
+        ie = (rin > 0.0) ? class_e(T, pin.z / rin) : class_e(T, n.z);
         ie_out = class_e(T, pout.z / rout);
         double phi_in, phi_out;
-        ia = class_a(T, pin.x, pin.y, &phi_in);
+        const bool on_axis = inner && pin.x == 0.0 && pin.y == 0.0;
+        ia = on_axis ? class_a(T, n.x, n.y, &phi_in) : class_a(T, pin.x, pin.y, &phi_in);
         ia_out = class_a(T, pout.x, pout.y, &phi_out);
 
         // elevation stream

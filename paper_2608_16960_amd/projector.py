@@ -31,7 +31,9 @@ class Projector:
 
     grid   Grid (or (r_b, e_b, a_b))
     views  ConeViews (cone beam, detector at the vertex), or
-    rays   (starts, dirs) explicit rays (float64 (R, 3) each)
+    rays   (starts, dirs) explicit rays (float64 (R, 3) each; may start inside the grid)
+    sun_dir  one ray per voxel from its centroid along sun_dir (Sec. 9.3's F_1);
+           its projections are shaped like the grid
     mode   "csr" (precomputed segment lists) or "onthefly" (recomputed per call)
     csc    build the voxel-major store for the deterministic adjoint (csr mode)
     frames dynamic object (Sec. 4.4): object frame of each cone view; objects
@@ -39,9 +41,9 @@ class Projector:
     """
 
     def __init__(self, grid, views=None, rays=None, mode="csr", csc=True, device=None,
-                 frames=None, n_frames=None):
-        if (views is None) == (rays is None):
-            raise ValueError("give either views or rays")
+                 frames=None, n_frames=None, sun_dir=None):
+        if (views is not None) + (rays is not None) + (sun_dir is not None) != 1:
+            raise ValueError("give one of views, rays or sun_dir")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         rb, eb, ab = _grid_arrays(grid)
@@ -64,6 +66,13 @@ class Projector:
                 N.check(N.lib.tsp_geometry_create(ctypes.byref(gd), arr, V, None, None, 0,
                                                   ctypes.byref(handle)))
                 self.out_shape = (V, int(views.H), int(views.W))
+            elif sun_dir is not None:
+                # one sunward ray per voxel centroid (Sec. 9.3, F_1 of Eq. 17)
+                sd = np.ascontiguousarray(sun_dir, np.float64).reshape(3)
+                N.check(N.lib.tsp_geometry_create_sunward(ctypes.byref(gd),
+                                                          sd.ctypes.data_as(N._dp),
+                                                          ctypes.byref(handle)))
+                self.out_shape = self.shape
             else:
                 s = np.ascontiguousarray(rays[0], np.float64).reshape(-1, 3)
                 d = np.ascontiguousarray(rays[1], np.float64).reshape(-1, 3)

@@ -56,7 +56,7 @@ def _view(pos=(10.0, 0.0, 0.0), fov=(30.0, 30.0), shape=(4, 4)):
 
 @pytest.mark.parametrize("case", ["null_grid", "rb_not_increasing", "eb_out_of_range",
                                   "ab_span", "detector_inside", "fov", "both_sources",
-                                  "ray_inside", "zero_dir", "shape_mismatch",
+                                  "ray_nan", "zero_dir", "shape_mismatch",
                                   "tables_exceed_lds"])
 def test_create_validation(case):
     from paper_2608_16960_amd import native as N
@@ -86,8 +86,8 @@ def test_create_validation(case):
         views = (N.tsp_cone_view * 2)(_view(), _view(shape=(4, 5)))
     elif case == "tables_exceed_lds":  # nr + ne + 3 na = 5630 > 5627
         gd, keep = _grid(ab=np.linspace(0.0, 2 * np.pi, 1876 + 1))
-    elif case in ("both_sources", "ray_inside", "zero_dir"):
-        s = np.array([[10.0, 0, 0]] if case != "ray_inside" else [[0.5, 0, 0]])
+    elif case in ("both_sources", "ray_nan", "zero_dir"):
+        s = np.array([[10.0, 0, 0]] if case != "ray_nan" else [[np.nan, 0, 0]])
         d = np.array([[-1.0, 0, 0]] if case != "zero_dir" else [[0.0, 0, 0]])
         starts, dirs = s.ctypes.data_as(N._dp), d.ctypes.data_as(N._dp)
         nrays = 1
