@@ -14,6 +14,7 @@ Contents
   - ``atten``: the attenuated emission model (Sec. 9.3, Eqs. 14-18) and its
     gradient, from the oracle's segment lists (sunward rays from voxel
     centroids for tau_1, inclusive cumulative sums along each line of sight);
+  - ``views``: parallel-beam views (Sec. 4.2, Listing 3), numpy;
   - ``reg``: anisotropic smoothed total variation and the Adam update;
   - ``conv``: 3x3x3 convolution with circular azimuth padding (PyTorch CPU
     conv3d in float64 as the library step).
