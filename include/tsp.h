@@ -103,6 +103,32 @@ typedef struct tsp_cone_view {
     int32_t shape[2];  /* detector (H, W); equal for every view of a geometry (Sec. 4.6) */
 } tsp_cone_view;
 
+/*
+ * A view of either kind (Sec. 4.2, Listings 2-3; Sec. 4.3 stacks views of
+ * any kinds with one detector shape).  Frame: w = unit(look - pos),
+ * u = unit(w x up) (up = +Z when all zero, +X when w is parallel to up),
+ * v = u x w; pixel (i, j) has sx = 2 (j + 1/2) / W - 1 and
+ * sy = 2 (i + 1/2) / H - 1, both in (-1, 1).
+ *   TSP_VIEW_CONE: as tsp_cone_view, extent = full fields of view in
+ *     degrees (rows, columns), in (0, 180); the ray starts at pos and looks
+ *     along unit(w + sx tan(extent[1]/2) u + sy tan(extent[0]/2) v).
+ *   TSP_VIEW_PARALLEL (ParallelGeom): extent = detector height and width in
+ *     grid units, > 0; the ray starts at pos + sx extent[1]/2 u +
+ *     sy extent[0]/2 v and looks along w.  The detector rectangle must lie
+ *     outside the outer sphere.
+ */
+#define TSP_VIEW_CONE 0
+#define TSP_VIEW_PARALLEL 1
+typedef struct tsp_view {
+    int32_t kind;      /* TSP_VIEW_CONE or TSP_VIEW_PARALLEL */
+    int32_t shape[2];  /* detector (H, W); equal for every view of a geometry */
+    int32_t reserved;
+    double pos[3];     /* cone vertex / detector centre, outside the grid */
+    double look[3];    /* point on the optical axis */
+    double up[3];      /* up hint; all zero means +Z */
+    double extent[2];  /* cone: full FOV degrees (rows, cols); parallel: size (rows, cols) */
+} tsp_view;
+
 /* Sizes and state of a geometry. */
 typedef struct tsp_info {
     int64_t n_rays;       /* R */
@@ -139,9 +165,17 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
                                int64_t n_rays, tsp_geometry **out);
 
 /*
+ * As tsp_geometry_create for views of any kinds (tsp_view).  Errors as
+ * there, plus TSP_E_INVALID for an unknown kind, a non-positive parallel
+ * size, or a parallel detector that reaches into the outer sphere.
+ */
+tsp_status tsp_geometry_create_views(const tsp_grid_desc *grid, const tsp_view *views,
+                                     int32_t n_views, tsp_geometry **out);
+
+/*
  * Dynamic objects (Sec. 4.4: the operator applies to a 3-D or a 4-D object;
  * Sec. 4.6: the grid stays the same for every frame).  Assigns object frame
- * frame_of_view[v] to cone view v.  Afterwards tsp_forward reads rho as
+ * frame_of_view[v] to view v (cone or parallel).  Afterwards tsp_forward reads rho as
  * [batch][n_frames][V]; every ray of view v integrates frame
  * frame_of_view[v].  tsp_backproject writes x in the same layout, and frame f
  * receives only the rays of the views assigned to it (zero if none).

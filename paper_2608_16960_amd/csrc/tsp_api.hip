@@ -241,6 +241,12 @@ struct AsyncBufs {
 
 }  // namespace
 
+namespace {
+tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int32_t n_views,
+                           const double *ray_starts, const double *ray_dirs, int64_t n_rays,
+                           tsp_geometry **out);
+}  // namespace
+
 extern "C" {
 
 const char *tsp_last_error(void) { return g_err.c_str(); }
@@ -249,6 +255,49 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
                                int32_t n_views, const double *ray_starts, const double *ray_dirs,
                                int64_t n_rays, tsp_geometry **out) {
     g_err.clear();
+    std::vector<tsp_view> vs;
+    if (views) {
+        if (n_views < 1) {
+            if (out) *out = nullptr;
+            return fail(TSP_E_INVALID, "n_views < 1");
+        }
+        vs.resize((size_t)n_views);
+        for (int v = 0; v < n_views; v++) {
+            tsp_view &t = vs[v];
+            t = tsp_view{};
+            t.kind = TSP_VIEW_CONE;
+            t.shape[0] = views[v].shape[0];
+            t.shape[1] = views[v].shape[1];
+            for (int k = 0; k < 3; k++) {
+                t.pos[k] = views[v].pos[k];
+                t.look[k] = views[v].look[k];
+                t.up[k] = views[v].up[k];
+            }
+            t.extent[0] = views[v].fov_deg[0];
+            t.extent[1] = views[v].fov_deg[1];
+        }
+    }
+    return create_geometry(grid, views ? vs.data() : nullptr, n_views, ray_starts, ray_dirs,
+                           n_rays, out);
+}
+
+tsp_status tsp_geometry_create_views(const tsp_grid_desc *grid, const tsp_view *views,
+                                     int32_t n_views, tsp_geometry **out) {
+    g_err.clear();
+    if (!views) {
+        if (out) *out = nullptr;
+        return fail(TSP_E_INVALID, "views is NULL");
+    }
+    return create_geometry(grid, views, n_views, nullptr, nullptr, 0, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int32_t n_views,
+                           const double *ray_starts, const double *ray_dirs, int64_t n_rays,
+                           tsp_geometry **out) {
     if (!out) return fail(TSP_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!grid) return fail(TSP_E_INVALID, "grid is NULL");
@@ -284,14 +333,20 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
         R = (int64_t)n_views * H * W;
         frames.assign((size_t)n_views * 16, 0.0);
         for (int v = 0; v < n_views; v++) {
-            const tsp_cone_view &cv = views[v];
+            const tsp_view &cv = views[v];
+            const bool cone = cv.kind == TSP_VIEW_CONE;
+            if (!cone && cv.kind != TSP_VIEW_PARALLEL)
+                return fail(TSP_E_INVALID, "view kind must be TSP_VIEW_CONE or TSP_VIEW_PARALLEL");
             if (cv.shape[0] != H || cv.shape[1] != W)
                 return fail(TSP_E_INVALID, "all views must share one detector shape");
             if (!finite3(cv.pos) || !finite3(cv.look) || !finite3(cv.up))
                 return fail(TSP_E_INVALID, "view vectors not finite");
-            for (int k = 0; k < 2; k++)
-                if (!(cv.fov_deg[k] > 0 && cv.fov_deg[k] < 180))
+            for (int k = 0; k < 2; k++) {
+                if (cone && !(cv.extent[k] > 0 && cv.extent[k] < 180))
                     return fail(TSP_E_INVALID, "fov must lie in (0, 180) degrees");
+                if (!cone && !(cv.extent[k] > 0 && std::isfinite(cv.extent[k])))
+                    return fail(TSP_E_INVALID, "parallel detector size must be positive");
+            }
             const double *P = cv.pos;
             if (std::sqrt(P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) <= Rout)
                 return fail(TSP_E_INVALID, "detector inside the grid's outer sphere");
@@ -323,8 +378,28 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
                 f[6 + i] = u[i];
                 f[9 + i] = vv[i];
             }
-            f[12] = std::tan(cv.fov_deg[0] * M_PI / 360.0);
-            f[13] = std::tan(cv.fov_deg[1] * M_PI / 360.0);
+            if (cone) {
+                f[12] = std::tan(cv.extent[0] * M_PI / 360.0);
+                f[13] = std::tan(cv.extent[1] * M_PI / 360.0);
+            } else {
+                // parallel: half sizes; the whole detector rectangle must lie
+                // outside the outer sphere (its point closest to the origin)
+                f[12] = 0.5 * cv.extent[0];
+                f[13] = 0.5 * cv.extent[1];
+                const double ou = -(P[0] * u[0] + P[1] * u[1] + P[2] * u[2]);
+                const double ov = -(P[0] * vv[0] + P[1] * vv[1] + P[2] * vv[2]);
+                const double cu = std::fmin(std::fmax(ou, -f[13]), f[13]);
+                const double cv2 = std::fmin(std::fmax(ov, -f[12]), f[12]);
+                double q2 = 0.0;
+                for (int i = 0; i < 3; i++) {
+                    const double qi = P[i] + cu * u[i] + cv2 * vv[i];
+                    q2 += qi * qi;
+                }
+                if (!(std::sqrt(q2) > Rout))
+                    return fail(TSP_E_INVALID, "parallel detector reaches into the grid's outer "
+                                               "sphere");
+            }
+            f[14] = cone ? 0.0 : 1.0;
         }
     } else {
         if (!ray_starts || !ray_dirs) return fail(TSP_E_INVALID, "ray arrays are NULL");
@@ -436,6 +511,10 @@ tsp_status tsp_geometry_create(const tsp_grid_desc *grid, const tsp_cone_view *v
     *out = g;
     return TSP_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 void tsp_geometry_destroy(tsp_geometry *g) {
     if (!g) return;

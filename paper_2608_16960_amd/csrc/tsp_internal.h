@@ -30,7 +30,10 @@ struct TabDesc {
 struct RayDesc {
     int n_views, H, W, tiles_h, tiles_w;
     int st;                // supertile side in tiles (divides tiles_h and tiles_w)
-    const double *frames;  // per view 16 doubles: pos(3) w(3) u(3) v(3) tan_h tan_w 0 0
+    // per view 16 doubles: pos(3) w(3) u(3) v(3) e_h e_w kind 0, where e_h / e_w
+    // are tan(fov / 2) for a cone view (kind 0) and half the detector size for a
+    // parallel view (kind 1)
+    const double *frames;
     const double *starts;  // explicit: [R][3]
     const double *dirs;    // explicit: [R][3], unit
     int explicit_rays;

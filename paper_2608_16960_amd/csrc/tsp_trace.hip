@@ -56,6 +56,12 @@ __device__ __forceinline__ void ray_of(const RayDesc &rd, int32_t ray, V3 &x, V3
     const double *f = rd.frames + 16 * view;
     const double sy = (2.0 * (i + 0.5) / rd.H - 1.0) * f[12];
     const double sx = (2.0 * (j + 0.5) / rd.W - 1.0) * f[13];
+    if (f[14] != 0.0) {  // parallel beam: pixel centre on the detector plane, along w
+        x = {f[0] + sx * f[6] + sy * f[9], f[1] + sx * f[7] + sy * f[10],
+             f[2] + sx * f[8] + sy * f[11]};
+        n = {f[3], f[4], f[5]};
+        return;
+    }
     double d0 = f[3] + sx * f[6] + sy * f[9];
     double d1 = f[4] + sx * f[7] + sy * f[10];
     double d2 = f[5] + sx * f[8] + sy * f[11];

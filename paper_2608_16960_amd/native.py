@@ -40,6 +40,17 @@ class tsp_cone_view(ctypes.Structure):
                 ("shape", ctypes.c_int32 * 2)]
 
 
+TSP_VIEW_CONE = 0
+TSP_VIEW_PARALLEL = 1
+
+
+class tsp_view(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("shape", ctypes.c_int32 * 2),
+                ("reserved", ctypes.c_int32), ("pos", ctypes.c_double * 3),
+                ("look", ctypes.c_double * 3), ("up", ctypes.c_double * 3),
+                ("extent", ctypes.c_double * 2)]
+
+
 class tsp_info(ctypes.Structure):
     _fields_ = [("n_rays", ctypes.c_int64), ("n_voxels", ctypes.c_int64),
                 ("n_segments", ctypes.c_int64), ("n_stored", ctypes.c_int64),
@@ -57,6 +68,8 @@ SIGNATURES = {
     "tsp_geometry_create": (_st, [ctypes.POINTER(tsp_grid_desc), ctypes.POINTER(tsp_cone_view),
                                   ctypes.c_int32, _dp, _dp, ctypes.c_int64,
                                   ctypes.POINTER(_vp)]),
+    "tsp_geometry_create_views": (_st, [ctypes.POINTER(tsp_grid_desc), ctypes.POINTER(tsp_view),
+                                        ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "tsp_set_object_frames": (_st, [_vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "tsp_geometry_create_sunward": (_st, [ctypes.POINTER(tsp_grid_desc), _dp,
                                           ctypes.POINTER(ctypes.c_void_p)]),

@@ -26,11 +26,36 @@ def _grid_arrays(grid):
     return tuple(np.ascontiguousarray(a, np.float64) for a in grid)
 
 
+def _view_array(views):
+    """tsp_view array from ConeViews / ParallelViews or a list of them (a
+    collection of views of any kinds with one detector shape, Sec. 4.3)."""
+    stacks = list(views) if isinstance(views, (list, tuple)) else [views]
+    items = []
+    for st in stacks:
+        cone = hasattr(st, "fov_deg")
+        ext = st.fov_deg if cone else st.size
+        for v in range(st.pos.shape[0]):
+            items.append((N.TSP_VIEW_CONE if cone else N.TSP_VIEW_PARALLEL, st.pos[v], st.look[v],
+                          st.up[v], ext[v], int(st.H), int(st.W)))
+    if len({(it[5], it[6]) for it in items}) != 1:
+        raise ValueError("all views of a collection must share one detector shape")
+    arr = (N.tsp_view * len(items))()
+    for i, (kind, pos, look, up, ext, H, W) in enumerate(items):
+        arr[i].kind = kind
+        arr[i].shape[:] = [H, W]
+        arr[i].pos[:] = [float(a) for a in pos]
+        arr[i].look[:] = [float(a) for a in look]
+        arr[i].up[:] = [float(a) for a in up]
+        arr[i].extent[:] = [float(a) for a in ext]
+    return arr, items[0][5], items[0][6]
+
+
 class Projector:
     """Spherical-grid line-integral projector y = F rho on one GPU.
 
     grid   Grid (or (r_b, e_b, a_b))
-    views  ConeViews (cone beam, detector at the vertex), or
+    views  ConeViews (cone beam, detector at the vertex), ParallelViews, or a
+           list of them (a collection with one detector shape), or
     rays   (starts, dirs) explicit rays (float64 (R, 3) each; may start inside the grid)
     sun_dir  one ray per voxel from its centroid along sun_dir (Sec. 9.3's F_1);
            its projections are shaped like the grid
@@ -55,17 +80,10 @@ class Projector:
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             if views is not None:
-                V = views.pos.shape[0]
-                arr = (N.tsp_cone_view * V)()
-                for v in range(V):
-                    arr[v].pos[:] = [float(a) for a in views.pos[v]]
-                    arr[v].look[:] = [float(a) for a in views.look[v]]
-                    arr[v].up[:] = [float(a) for a in views.up[v]]
-                    arr[v].fov_deg[:] = [float(a) for a in views.fov_deg[v]]
-                    arr[v].shape[:] = [int(views.H), int(views.W)]
-                N.check(N.lib.tsp_geometry_create(ctypes.byref(gd), arr, V, None, None, 0,
-                                                  ctypes.byref(handle)))
-                self.out_shape = (V, int(views.H), int(views.W))
+                arr, H, W = _view_array(views)
+                N.check(N.lib.tsp_geometry_create_views(ctypes.byref(gd), arr, len(arr),
+                                                        ctypes.byref(handle)))
+                self.out_shape = (len(arr), H, W)
             elif sun_dir is not None:
                 # one sunward ray per voxel centroid (Sec. 9.3, F_1 of Eq. 17)
                 sd = np.ascontiguousarray(sun_dir, np.float64).reshape(3)

@@ -72,6 +72,33 @@ class ConeViews:
 
 
 @dataclass
+class ParallelViews:
+    """A stack of equal-shape parallel-beam views (ParallelGeom, Sec. 4.2):
+    rays start on the detector rectangle (centre pos, `size` = (height,
+    width) in grid units) and all run along unit(look - pos)."""
+    pos: np.ndarray          # (V, 3)
+    look: np.ndarray         # (V, 3)
+    up: np.ndarray           # (V, 3)
+    size: np.ndarray         # (V, 2)
+    H: int
+    W: int
+
+    @property
+    def n_views(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def n_rays(self) -> int:
+        return self.n_views * self.H * self.W
+
+
+def parallel_views_at(pos, size, H, W, look=None, up=None) -> ParallelViews:
+    c = views_at(pos, (1.0, 1.0), H, W, look, up)
+    sz = np.broadcast_to(np.asarray(size, np.float64), (c.n_views, 2)).copy()
+    return ParallelViews(c.pos, c.look, c.up, sz, int(H), int(W))
+
+
+@dataclass
 class Workload:
     name: str
     grid: Grid

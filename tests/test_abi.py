@@ -100,6 +100,39 @@ def test_create_validation(case):
     assert len(N.lib.tsp_last_error()) > 0
 
 
+@pytest.mark.parametrize("case", ["kind", "size", "reaches_in", "ok_off_axis"])
+def test_view_kinds_validation(case):
+    """tsp_geometry_create_views: unknown kind, non-positive parallel size,
+    a parallel detector reaching into the outer sphere (rejected before any
+    device call); a parallel detector beside the sphere passes validation."""
+    from paper_2608_16960_amd import native as N
+    gd, keep = _grid()  # outer radius 2
+    v = N.tsp_view()
+    v.kind = N.TSP_VIEW_PARALLEL
+    v.shape[:] = (4, 4)
+    v.pos[:] = (10.0, 0.0, 0.0)
+    v.extent[:] = (3.0, 3.0)
+    if case == "kind":
+        v.kind = 7
+    elif case == "size":
+        v.extent[:] = (3.0, 0.0)
+    elif case == "reaches_in":
+        v.pos[:] = (2.5, 0.0, 0.0)
+        v.look[:] = (2.5, 5.0, 0.0)  # looks sideways: the detector plane cuts the ball
+    elif case == "ok_off_axis":  # closest detector point (1, 0, 2.5), radius 2.69
+        v.pos[:] = (2.5, 0.0, 4.0)
+        v.look[:] = (2.5, 5.0, 4.0)
+    out = ctypes.c_void_p()
+    st = N.lib.tsp_geometry_create_views(ctypes.byref(gd), (N.tsp_view * 1)(v), 1,
+                                         ctypes.byref(out))
+    if case == "ok_off_axis":
+        assert st != N.TSP_E_INVALID, N.lib.tsp_last_error()
+        if out.value:
+            N.lib.tsp_geometry_destroy(out)
+    else:
+        assert st == N.TSP_E_INVALID and not out.value
+
+
 def test_table_limit_is_inclusive():
     """nr + ne + 3 na = 5627 passes validation (without a GPU the call then
     fails in the HIP runtime, not in argument checking)."""
