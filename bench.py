@@ -199,6 +199,41 @@ def extra_large_onthefly():
                     "fp64_valu from rocprofv3 FP64 instruction counters (profiles)"}
 
 
+def extra_large_csr(reps=5):
+    """Large workload from stored segment lists: on one MI355X the ray-major
+    and voxel-major stores (about 8 bytes per segment each, 8.46e9 segments)
+    fit in HBM, the transpose built in passes that fit the rest; batch 4,
+    deterministic adjoint."""
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.projector import Projector
+    w = W.large()
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = Projector(w.grid, views=w.views)
+    torch.cuda.synchronize()
+    trace_s = time.perf_counter() - t0
+    inf = P.info()
+    R, V, S, B = inf["n_rays"], inf["n_voxels"], inf["n_segments"], 4
+    rho = torch.from_numpy(w.rho).cuda()
+    y = P.forward(rho)
+    x = torch.empty_like(rho)
+    f_ms = _time_ms(lambda: P.forward(rho, out=y), reps)
+    a_ms = _time_ms(lambda: P.backproject(y, "deterministic", out=x), reps)
+    fb, ab = 8 * S + 8 * R + 4 * B * R + 4 * B * V, 8 * S + 8 * V + 4 * B * V + 4 * B * R
+    P.close()
+    del y, x, rho
+    torch.cuda.empty_cache()
+    return {"workload": f"large from stored lists: {R} rays, {S} segments, batch {B}",
+            "trace_s": trace_s, "device_GB": inf["device_bytes"] / 1e9,
+            "forward_ms": f_ms, "adjoint_ms": a_ms,
+            "forward_rays_per_s": B * R / f_ms * 1e3, "adjoint_rays_per_s": B * R / a_ms * 1e3,
+            "forward_hbm_frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
+            "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS}
+
+
 def extra_diff_csr():
     import torch
 
@@ -430,6 +465,8 @@ def main():
         torch.cuda.empty_cache()
         _log("large on-the-fly")
         line["onthefly_large"] = extra_large_onthefly()
+        _log("large from stored lists")
+        line["stored_large"] = extra_large_csr()
         _log("differentiation workload")
         line["diff_csr"] = extra_diff_csr()
         _log("explicit rays")

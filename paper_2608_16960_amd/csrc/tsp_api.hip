@@ -512,6 +512,136 @@ tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int
     return TSP_OK;
 }
 
+// Voxel-major (transposed) store: col_ptr [FV + 1] and col_ent [S], entries of
+// each (frame, voxel) key in ray order.  Built in passes over key ranges, so
+// that the temporaries (two key buffers and one value buffer, 16 bytes per
+// entry, plus the sort workspace; the sorted values land in the store itself)
+// fit the free device memory, or the cap TSP_MAX_DEVICE_BYTES; the
+// environment variable TSP_TRANSPOSE_MAX_ENTRIES caps the entries per pass
+// further.  Every pass is a stable sort of a contiguous key range, so the
+// result does not depend on the number of passes.
+tsp_status build_transpose(tsp_geometry *g, hipStream_t st) {
+    const int64_t S = g->S, FV = g->FV(), R = g->R;
+    const int nr = g->T.nr, ne = g->T.ne, na = g->T.na;
+    const RayDesc &rd = g->rd;
+    tsp_status s;
+    if ((s = dalloc_n(g, &g->d_col_ptr, FV + 1, "column offsets")) != TSP_OK) return s;
+    if ((s = dalloc_n(g, &g->d_col_ent, S, "voxel-major store")) != TSP_OK) return s;
+
+    const int64_t fixed = 16 * (R + 2) + 8 * scan_tmp_elems(R) + 4096;
+    int64_t cap = S;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
+        int64_t avail = (int64_t)fr - margin - fixed;
+        const int64_t dcap = device_cap();
+        if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - fixed);
+        cap = std::min<int64_t>(cap, avail / 17);
+    } else {
+        (void)hipGetLastError();
+    }
+    if (const char *e = std::getenv("TSP_TRANSPOSE_MAX_ENTRIES")) {
+        const long long v = std::atoll(e);
+        if (v > 0) cap = std::min<int64_t>(cap, v);
+    }
+    if (cap < 1 && S > 0) return fail(TSP_E_NOMEM, "no device memory left for the transpose");
+    cap = std::max<int64_t>(cap, 1);
+
+    // key ranges [cuts[p], cuts[p+1]) of at most cap entries each
+    std::vector<int64_t> cuts{0};
+    hipError_t e = hipSuccess;
+    if (cap < S) {
+        const int shift = std::max(0, bits_for(FV) - 12);
+        const int nb = (int)((FV - 1) >> shift) + 1;
+        unsigned long long *hist = nullptr;
+        if ((s = dalloc_n(g, &hist, nb, "key histogram")) != TSP_OK) return s;
+        e = launch_zero_f32((float *)hist, 2 * (int64_t)nb, st);
+        if (e == hipSuccess)
+            e = launch_key_hist(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, nr, ne,
+                                na, shift, nb, hist, st);
+        std::vector<unsigned long long> h((size_t)nb);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess)
+            e = hipMemcpy(h.data(), hist, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost);
+        dfree(g, hist);
+        if (e != hipSuccess) return fail(TSP_E_HIP, std::string("key histogram: ") +
+                                                        hipGetErrorString(e));
+        int64_t acc = 0;
+        for (int b = 0; b < nb; b++) {
+            if ((int64_t)h[b] > cap)
+                return fail(TSP_E_NOMEM, "transpose: one key bucket exceeds the memory for a pass");
+            if (acc + (int64_t)h[b] > cap && acc > 0) {
+                cuts.push_back((int64_t)b << shift);
+                acc = 0;
+            }
+            acc += (int64_t)h[b];
+        }
+    }
+    cuts.push_back(FV);
+    const int64_t nmax = std::min<int64_t>(cap, S);
+
+    int32_t *k1 = nullptr, *k2 = nullptr, *cnt = nullptr;
+    uint64_t *v1 = nullptr;
+    int64_t *crow = nullptr, *stmp = nullptr;
+    void *ws = nullptr;
+    auto free_all = [&]() {
+        dfree(g, k1);
+        dfree(g, k2);
+        dfree(g, v1);
+        dfree(g, cnt);
+        dfree(g, crow);
+        dfree(g, stmp);
+        dfree(g, ws);
+    };
+    if ((s = dalloc_n(g, &k1, nmax, "transpose keys")) != TSP_OK ||
+        (s = dalloc_n(g, &k2, nmax, "transpose keys")) != TSP_OK ||
+        (s = dalloc_n(g, &v1, nmax, "transpose values")) != TSP_OK ||
+        (s = dalloc_n(g, &cnt, R, "transpose counts")) != TSP_OK ||
+        (s = dalloc_n(g, &crow, R + 1, "transpose offsets")) != TSP_OK ||
+        (s = dalloc_n(g, &stmp, scan_tmp_elems(R), "scan")) != TSP_OK ||
+        (s = dalloc(g, &ws, (int64_t)radix_ws_bytes(nmax), "sort workspace")) != TSP_OK) {
+        free_all();
+        return s;
+    }
+    int64_t base = 0;
+    const int bits = bits_for(FV);
+    const bool one_pass = cuts.size() == 2;
+    for (size_t p = 0; p + 1 < cuts.size() && e == hipSuccess; p++) {
+        const int32_t lo = (int32_t)cuts[p], hi = (int32_t)cuts[p + 1];
+        // one pass takes every segment: its offsets are the rows of the store
+        const int64_t *rows = one_pass ? g->d_row_ptr : crow;
+        int64_t np = S;
+        if (!one_pass) {
+            e = launch_count_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, nr,
+                                   ne, na, lo, hi, cnt, st);
+            if (e == hipSuccess) e = launch_scan_i32(cnt, R, 1, crow, stmp, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&np, crow + R, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+        if (e != hipSuccess) break;
+        if (np > nmax || base + np > S) {
+            free_all();
+            return fail(TSP_E_HIP, "transpose: pass larger than planned");
+        }
+        uint64_t *dst = g->d_col_ent + base;
+        int in_second = 0;
+        e = launch_expand_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox,
+                                g->d_len, rows, nr, ne, na, lo, hi, k1, v1, st);
+        if (e == hipSuccess) e = launch_radix_sort(k1, v1, k2, dst, np, bits, ws, &in_second, st);
+        if (e == hipSuccess && !in_second) e = launch_copy_u64(v1, dst, np, st);
+        if (e == hipSuccess)
+            e = launch_col_ptr_range(in_second ? k2 : k1, np, lo, hi - lo, base, g->d_col_ptr,
+                                     st);
+        base += np;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    free_all();
+    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
+    if (base != S) return fail(TSP_E_HIP, "transpose: entry count mismatch");
+    return TSP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -670,68 +800,9 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
     scan_tmp = nullptr;
 
     if (want_csc) {
-        const int64_t S = g->S;
-        int32_t *k1 = nullptr, *k2 = nullptr;
-        uint64_t *v1 = nullptr, *v2 = nullptr;
-        void *ws = nullptr;
-        auto free_sort = [&]() {
-            dfree(g, k1);
-            dfree(g, k2);
-            dfree(g, v1);
-            dfree(g, v2);
-            dfree(g, ws);
-        };
-        if ((s = dalloc_n(g, &k1, S, "sort keys")) != TSP_OK ||
-            (s = dalloc_n(g, &k2, S, "sort keys")) != TSP_OK ||
-            (s = dalloc_n(g, &v1, S, "sort values")) != TSP_OK ||
-            (s = dalloc_n(g, &v2, S, "sort values")) != TSP_OK ||
-            (s = dalloc(g, &ws, (int64_t)radix_ws_bytes(S), "sort workspace")) != TSP_OK) {
-            free_sort();
+        if ((s = build_transpose(g, st)) != TSP_OK) {
             release_stores(g);
             return s;
-        }
-        int in_second = 0;
-        e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len, ns,
-                          g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, k1, v1, nullptr, nullptr,
-                          st);
-        if (e == hipSuccess)
-            e = launch_radix_sort(k1, v1, k2, v2, S, bits_for(g->FV()), ws, &in_second, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) {
-            free_sort();
-            release_stores(g);
-            return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
-        }
-        int32_t *ks = in_second ? k2 : k1;
-        uint64_t *vs = in_second ? v2 : v1;
-        // the sorted values are the store: keep them, release the rest
-        if (in_second) {
-            dfree_p(g, k1);
-            dfree_p(g, v1);
-        } else {
-            dfree_p(g, k2);
-            dfree_p(g, v2);
-        }
-        dfree_p(g, ws);
-        if ((s = dalloc_n(g, &g->d_col_ptr, g->FV() + 1, "column offsets")) != TSP_OK) {
-            free_sort();
-            release_stores(g);
-            return s;
-        }
-        e = launch_col_ptr(ks, S, g->FV(), g->d_col_ptr, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (in_second) {
-            v2 = nullptr;
-            dfree_p(g, k2);
-        } else {
-            v1 = nullptr;
-            dfree_p(g, k1);
-        }
-        g->d_col_ent = vs;
-        free_sort();
-        if (e != hipSuccess) {
-            release_stores(g);
-            return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
         }
     }
     g->mode = TSP_MODE_CSR;
@@ -881,8 +952,7 @@ tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, f
     if (row_ptr) e = launch_copy_i64(g->d_row_ptr, row_ptr, g->R + 1, st);
     if (e == hipSuccess && (vox || len))
         e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
-                          g->rd.n_slots, g->d_row_ptr, g->T.nr, g->T.ne, g->T.na, nullptr,
-                          nullptr, vox, len, st);
+                          g->rd.n_slots, g->d_row_ptr, vox, len, st);
     if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
     return TSP_OK;
 }

@@ -28,20 +28,39 @@ __device__ __forceinline__ v4f ld_nt(const v4f *p) { return __builtin_nontempora
 __device__ __forceinline__ int32_t ld_nt(const int32_t *p) { return __builtin_nontemporal_load(p); }
 __device__ __forceinline__ float ld_nt(const float *p) { return __builtin_nontemporal_load(p); }
 
+// A batch lane group: NB = 1, 2 or 4 objects' values of one voxel (or one
+// ray slot), loaded with one 4-, 8- or 16-byte access.
+template <int NB> struct YVec;
+template <> struct YVec<1> {
+    using T = float;
+    __device__ static float get(const T &v, int) { return v; }
+    __device__ static void set(T &v, int, float f) { v = f; }
+};
+template <> struct YVec<2> {
+    using T = float2;
+    __device__ static float get(const T &v, int b) { return b ? v.y : v.x; }
+    __device__ static void set(T &v, int b, float f) { (b ? v.y : v.x) = f; }
+};
+template <> struct YVec<4> {
+    using T = float4;
+    __device__ static float get(const T &v, int b) {
+        return b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w;
+    }
+    __device__ static void set(T &v, int b, float f) {
+        (b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w) = f;
+    }
+};
+
 template <int NB>
 __device__ __forceinline__ void fwd_quad(const v4i v, const v4f l, int j, int c,
-                                         const float *__restrict__ rho, int nb, int64_t V,
+                                         const typename YVec<NB>::T *__restrict__ rho,
                                          float *acc) {
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         const bool ok = j + i < c;  // padding entries hold voxel 0, length 0
+        const typename YVec<NB>::T r = rho[v[i]];
 #pragma unroll
-        for (int b = 0; b < NB; b++) {
-            if (b < nb) {
-                const float r = rho[b * V + v[i]];
-                acc[b] = fmaf(l[i], ok ? r : 0.0f, acc[b]);
-            }
-        }
+        for (int b = 0; b < NB; b++) acc[b] = fmaf(l[i], ok ? YVec<NB>::get(r, b) : 0.0f, acc[b]);
     }
 }
 
@@ -52,11 +71,11 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
                                                    const int32_t *__restrict__ slice_len,
                                                    const int32_t *__restrict__ vox,
                                                    const float *__restrict__ len, int64_t n_slots,
-                                                   const float *__restrict__ rho, int nb,
-                                                   int64_t V, int64_t R, float *__restrict__ y,
+                                                   const typename YVec<NB>::T *__restrict__ rho,
+                                                   int nb, int64_t R, float *__restrict__ y,
                                                    const int32_t *__restrict__ obj_frame,
                                                    int64_t hw, int64_t vf) {
-    // V: batch stride of rho (voxels of all object frames); vf: one frame
+    // rho: voxel-major, NB objects per voxel (all object frames); vf: voxels of one frame
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int64_t s = slot >> 6;
@@ -80,12 +99,12 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
             l[u] = ld_nt(lp + (int64_t)(q + u) * kWave);
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) fwd_quad<NB>(v[u], l[u], 4 * (q + u), c, rho, nb, V, acc);
+        for (int u = 0; u < 4; u++) fwd_quad<NB>(v[u], l[u], 4 * (q + u), c, rho, acc);
     }
     for (; q < nq; q++) {
         const v4i v = ld_nt(vp + (int64_t)q * kWave);
         const v4f l = ld_nt(lp + (int64_t)q * kWave);
-        fwd_quad<NB>(v, l, 4 * q, c, rho, nb, V, acc);
+        fwd_quad<NB>(v, l, 4 * q, c, rho, acc);
     }
     if (ray >= 0) {
 #pragma unroll
@@ -94,28 +113,18 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
     }
 }
 
-// Batch lane group of the slot-ordered copy of y: NB = 1, 2 or 4 values per
-// slot, loaded with one 4-, 8- or 16-byte access.
-template <int NB> struct YVec;
-template <> struct YVec<1> {
-    using T = float;
-    __device__ static float get(const T &v, int) { return v; }
-    __device__ static void set(T &v, int, float f) { v = f; }
-};
-template <> struct YVec<2> {
-    using T = float2;
-    __device__ static float get(const T &v, int b) { return b ? v.y : v.x; }
-    __device__ static void set(T &v, int b, float f) { (b ? v.y : v.x) = f; }
-};
-template <> struct YVec<4> {
-    using T = float4;
-    __device__ static float get(const T &v, int b) {
-        return b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w;
-    }
-    __device__ static void set(T &v, int b, float f) {
-        (b == 0 ? v.x : b == 1 ? v.y : b == 2 ? v.z : v.w) = f;
-    }
-};
+// dst[v] = (src[b][v] for b < nb), zero in unused lanes: a batch of objects
+// packed voxel-major for the forward's gathers.
+template <int NB>
+__global__ void k_pack(const float *__restrict__ src, int nb, int64_t n,
+                       typename YVec<NB>::T *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    typename YVec<NB>::T v;
+#pragma unroll
+    for (int b = 0; b < NB; b++) YVec<NB>::set(v, b, b < nb ? src[b * n + i] : 0.0f);
+    dst[i] = v;
+}
 
 // yt[s] = (y[b][natural_ray(s)] for b < nb), zero for padding slots and for
 // the unused lanes of the last group.
@@ -254,33 +263,57 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
+template <int NB>
+static hipError_t fwd_chunk(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                            const int64_t *slice_ptr, const int32_t *slice_len,
+                            const int32_t *vox, const float *len, const float *rho, int nb,
+                            int64_t vf, int64_t FV, float *y, void *packed, hipStream_t st) {
+    using T = typename YVec<NB>::T;
+    const T *r = (const T *)rho;
+    if (NB > 1) {
+        hipLaunchKernelGGL(k_pack<NB>, dim3(blocks_for(FV, 256)), dim3(256), 0, st, rho, nb, FV,
+                           (T *)packed);
+        r = (const T *)packed;
+    }
+    hipLaunchKernelGGL(k_fwd_sell<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
+                       cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, r, nb, rd.R, y,
+                       rd.obj_frame, (int64_t)rd.H * rd.W, vf);
+    return hipGetLastError();
+}
+
 hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
                                const int32_t *vox, const float *len, const float *rho, int B,
                                int64_t vf, float *y, hipStream_t st) {
-    const int64_t FV = vf * rd.n_obj_frames, R = rd.R, hw = (int64_t)rd.H * rd.W;
-    const int64_t n_slots = rd.n_slots;
-    for (int b0 = 0; b0 < B; b0 += 4) {
-        const int nb = (B - b0 < 4) ? (B - b0) : 4;
-        const float *r = rho + (int64_t)b0 * FV;
-        float *yy = y + (int64_t)b0 * R;
-        const dim3 g(blocks_for(n_slots, 256));
-        if (nb == 1)
-            hipLaunchKernelGGL(k_fwd_sell<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
-                               vf);
-        else if (nb == 2)
-            hipLaunchKernelGGL(k_fwd_sell<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
-                               vf);
-        else
-            hipLaunchKernelGGL(k_fwd_sell<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, r, nb, FV, R, yy, rd.obj_frame, hw,
-                               vf);
-        hipError_t e = hipGetLastError();
+    // batches: objects packed voxel-major (4, 8 or 16 bytes per voxel) so that
+    // one gather per segment serves every object of a group of up to four
+    const int64_t FV = vf * rd.n_obj_frames;
+    const int width = B >= 3 ? 4 : B;
+    void *packed = nullptr;
+    hipError_t e = hipSuccess;
+    if (B > 1) {
+        e = hipMallocAsync(&packed, (size_t)FV * width * sizeof(float), st);
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    for (int b0 = 0; b0 < B && e == hipSuccess; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *r = rho + (int64_t)b0 * FV;
+        float *yy = y + (int64_t)b0 * rd.R;
+        if (nb == 1)
+            e = fwd_chunk<1>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
+                             yy, packed, st);
+        else if (nb == 2)
+            e = fwd_chunk<2>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
+                             yy, packed, st);
+        else
+            e = fwd_chunk<4>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
+                             yy, packed, st);
+    }
+    if (packed) {
+        const hipError_t f = hipFreeAsync(packed, st);
+        if (e == hipSuccess) e = f;
+    }
+    return e;
 }
 
 template <int NB>

@@ -135,18 +135,34 @@ hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *o
 int64_t scan_tmp_elems(int64_t n);
 hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
                                  int32_t *cnt_ray, hipStream_t st);
+// Canonical CSR (ray-major, row_ptr order) export of the sliced store.
 hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                          const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                         int64_t n_slots, const int64_t *row_ptr, int nr, int ne, int na,
-                         int32_t *keys, uint64_t *vals, int32_t *out_vox, float *out_len,
-                         hipStream_t st);
+                         int64_t n_slots, const int64_t *row_ptr, int32_t *out_vox,
+                         float *out_len, hipStream_t st);
 // stable LSD radix sort of (key, val) by key (key < 2^key_bits); result lands in
 // (keys, vals) or (keys2, vals2): returns through *in_second whether it is the second.
 hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
                              int64_t n, int key_bits, void *ws, int *in_second, hipStream_t st);
 size_t radix_ws_bytes(int64_t n);
-hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int64_t *col_ptr,
-                          hipStream_t st);
+// Transpose in passes over key ranges [lo, hi) (bounded temporary memory):
+// coarse key histogram (bucket = key >> shift, nb <= key_hist_buckets()),
+// per-ray counts in a range, compacted expansion in ray order, and the
+// range's column offsets with a base.
+int key_hist_buckets();
+hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                           const int64_t *slice_ptr, const int32_t *vox, int nr, int ne, int na,
+                           int shift, int nb, unsigned long long *hist, hipStream_t st);
+hipError_t launch_count_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                              const int64_t *slice_ptr, const int32_t *vox, int nr, int ne,
+                              int na, int32_t lo, int32_t hi, int32_t *cnt_ray, hipStream_t st);
+hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                               const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                               const int64_t *crow, int nr, int ne, int na, int32_t lo,
+                               int32_t hi, int32_t *keys, uint64_t *vals, hipStream_t st);
+hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
+                                int64_t base, int64_t *col_ptr, hipStream_t st);
+hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st);
 
 // ---- launchers (tsp_apply.hip) ----
 // vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.

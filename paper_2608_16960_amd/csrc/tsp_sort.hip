@@ -144,9 +144,8 @@ __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t 
                                                  const int32_t *cnt_sorted,
                                                  const int64_t *slice_ptr, const int32_t *vox,
                                                  const float *len, int64_t n_slots,
-                                                 const int64_t *row_ptr, int nr, int ne,
-                                                 int na, int32_t *keys, uint64_t *vals,
-                                                 int32_t *out_vox, float *out_len) {
+                                                 const int64_t *row_ptr, int32_t *out_vox,
+                                                 float *out_len) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int32_t r = perm[slot];
@@ -155,21 +154,121 @@ __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t 
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
     const int64_t dst = row_ptr[r];
-    const int64_t ns = natural_slot(rd, slot, r);
-    // key: object frame of the ray's view, then the voxel in angular-major order
-    const int32_t fbase =
-        (int32_t)frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, r, (int64_t)nr * ne * na);
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
-        const int32_t v = vox[i];
-        const float l = len[i];
-        if (keys) {
-            keys[dst + j] = fbase + angular_major(v, nr, ne, na);
-            vals[dst + j] = (uint64_t)(uint32_t)ns | ((uint64_t)__float_as_uint(l) << 32);
-        }
-        if (out_vox) out_vox[dst + j] = v;
-        if (out_len) out_len[dst + j] = l;
+        if (out_vox) out_vox[dst + j] = vox[i];
+        if (out_len) out_len[dst + j] = len[i];
     }
+}
+
+// Voxel-major key of a segment of ray r in voxel v: object frame of the
+// ray's view, then the voxel in angular-major order.
+__device__ __forceinline__ int32_t seg_key(const RayDesc &rd, int32_t r, int32_t v, int nr,
+                                           int ne, int na) {
+    return (int32_t)frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, r, (int64_t)nr * ne * na) +
+           angular_major(v, nr, ne, na);
+}
+
+// Coarse histogram of the keys (bucket = key >> shift, nb <= kHistBuckets)
+// over the ray-major store, to cut the transpose into passes of bounded size.
+constexpr int kHistBuckets = 4096;
+__global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_t *perm,
+                                                   const int32_t *cnt_sorted,
+                                                   const int64_t *slice_ptr, const int32_t *vox,
+                                                   int64_t n_slots, int nr, int ne, int na,
+                                                   int shift, int nb,
+                                                   unsigned long long *hist) {
+    __shared__ unsigned h[kHistBuckets];
+    for (int i = threadIdx.x; i < nb; i += 256) h[i] = 0;
+    __syncthreads();
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot < n_slots) {
+        const int32_t r = perm[slot];
+        if (r >= 0) {
+            const int c = cnt_sorted[slot];
+            const int64_t base = slice_ptr[slot >> 6];
+            const int lane = (int)(slot & 63);
+            for (int j = 0; j < c; j++) {
+                const int32_t k = seg_key(rd, r, vox[sell_index(base, lane, j)], nr, ne, na);
+                atomicAdd(&h[k >> shift], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += 256)
+        if (h[i]) atomicAdd(hist + i, (unsigned long long)h[i]);
+}
+
+// Per ray: number of its segments whose key lies in [lo, hi).
+__global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int32_t *perm,
+                                                      const int32_t *cnt_sorted,
+                                                      const int64_t *slice_ptr,
+                                                      const int32_t *vox, int64_t n_slots,
+                                                      int nr, int ne, int na, int32_t lo,
+                                                      int32_t hi, int32_t *cnt_ray) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t r = perm[slot];
+    if (r < 0) return;
+    const int c = cnt_sorted[slot];
+    const int64_t base = slice_ptr[slot >> 6];
+    const int lane = (int)(slot & 63);
+    int n = 0;
+    for (int j = 0; j < c; j++) {
+        const int32_t k = seg_key(rd, r, vox[sell_index(base, lane, j)], nr, ne, na);
+        n += (k >= lo && k < hi);
+    }
+    cnt_ray[r] = n;
+}
+
+// Segments with keys in [lo, hi), compacted in ray order (ray r's at
+// crow[r] ...), as (key, natural slot | length bits << 32) for the sort.
+__global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const int32_t *perm,
+                                                       const int32_t *cnt_sorted,
+                                                       const int64_t *slice_ptr,
+                                                       const int32_t *vox, const float *len,
+                                                       int64_t n_slots, const int64_t *crow,
+                                                       int nr, int ne, int na, int32_t lo,
+                                                       int32_t hi, int32_t *keys,
+                                                       uint64_t *vals) {
+    const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (slot >= n_slots) return;
+    const int32_t r = perm[slot];
+    if (r < 0) return;
+    const int c = cnt_sorted[slot];
+    const int64_t base = slice_ptr[slot >> 6];
+    const int lane = (int)(slot & 63);
+    const uint64_t ns = (uint64_t)(uint32_t)natural_slot(rd, slot, r);
+    int64_t dst = crow[r];
+    for (int j = 0; j < c; j++) {
+        const int64_t i = sell_index(base, lane, j);
+        const int32_t k = seg_key(rd, r, vox[i], nr, ne, na);
+        if (k >= lo && k < hi) {
+            keys[dst] = k;
+            vals[dst] = ns | ((uint64_t)__float_as_uint(len[i]) << 32);
+            dst++;
+        }
+    }
+}
+
+// col_ptr[key0 + t] = base + (first index of keys >= key0 + t), t = 0..nk.
+__global__ void k_col_ptr_range(const int32_t *keys, int64_t n, int64_t key0, int64_t nk,
+                                int64_t base, int64_t *col_ptr) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > nk) return;
+    const int64_t v = key0 + t;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    col_ptr[v] = base + lo;
+}
+
+__global__ void k_copy_u64(const uint64_t *s, uint64_t *d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = s[i];
 }
 
 // ------------------------------------------------------------ radix sort
@@ -248,18 +347,6 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin, const ui
     }
 }
 
-__global__ void k_col_ptr(const int32_t *keys, int64_t n, int64_t V, int64_t *col_ptr) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v > V) return;
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {  // first index with key >= v
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < v) lo = mid + 1;
-        else hi = mid;
-    }
-    col_ptr[v] = lo;
-}
-
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
 }  // namespace
@@ -296,12 +383,10 @@ hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted,
 
 hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                          const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                         int64_t n_slots, const int64_t *row_ptr, int nr, int ne, int na,
-                         int32_t *keys, uint64_t *vals, int32_t *out_vox, float *out_len,
-                         hipStream_t st) {
+                         int64_t n_slots, const int64_t *row_ptr, int32_t *out_vox,
+                         float *out_len, hipStream_t st) {
     hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, rd, perm,
-                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, nr, ne, na, keys, vals,
-                       out_vox, out_len);
+                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, out_vox, out_len);
     return hipGetLastError();
 }
 
@@ -351,10 +436,44 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
     return hipSuccess;
 }
 
-hipError_t launch_col_ptr(const int32_t *sorted_keys, int64_t n, int64_t V, int64_t *col_ptr,
-                          hipStream_t st) {
-    hipLaunchKernelGGL(k_col_ptr, dim3(blocks_for(V + 1, 256)), dim3(256), 0, st, sorted_keys, n,
-                       V, col_ptr);
+int key_hist_buckets() { return kHistBuckets; }
+
+hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                           const int64_t *slice_ptr, const int32_t *vox, int nr, int ne, int na,
+                           int shift, int nb, unsigned long long *hist, hipStream_t st) {
+    hipLaunchKernelGGL(k_key_hist, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, perm,
+                       cnt_sorted, slice_ptr, vox, rd.n_slots, nr, ne, na, shift, nb, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                              const int64_t *slice_ptr, const int32_t *vox, int nr, int ne,
+                              int na, int32_t lo, int32_t hi, int32_t *cnt_ray, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_range, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
+                       perm, cnt_sorted, slice_ptr, vox, rd.n_slots, nr, ne, na, lo, hi, cnt_ray);
+    return hipGetLastError();
+}
+
+hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
+                               const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                               const int64_t *crow, int nr, int ne, int na, int32_t lo,
+                               int32_t hi, int32_t *keys, uint64_t *vals, hipStream_t st) {
+    hipLaunchKernelGGL(k_expand_range, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
+                       perm, cnt_sorted, slice_ptr, vox, len, rd.n_slots, crow, nr, ne, na, lo,
+                       hi, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
+                                int64_t base, int64_t *col_ptr, hipStream_t st) {
+    hipLaunchKernelGGL(k_col_ptr_range, dim3(blocks_for(nk + 1, 256)), dim3(256), 0, st,
+                       sorted_keys, n, key0, nk, base, col_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, d, n);
     return hipGetLastError();
 }
 
