@@ -142,7 +142,7 @@ __global__ __launch_bounds__(256) void k_tile_y(const RayDesc rd, const float *_
 
 // Deterministic adjoint: one wavefront per voxel of the voxel-major store,
 // lanes stride its entries (eight per lane in flight), fixed butterfly sum.
-// Keys run over object frames, then voxels in angular-major order; x is
+// Keys run over object frames, then voxels in store-key order; x is
 // [nf][V] per object (nf = 1 for a static object).
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
@@ -153,12 +153,20 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
     constexpr int UNR = 8;
     const int64_t V = (int64_t)nr * ne * na;
     const int64_t FV = V * nf;
-    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    // Workgroups reach the 8 XCDs round-robin.  Remap so that each XCD takes
+    // chunks of 64 consecutive workgroups (256 consecutive keys) in turn: the
+    // voxels of a chunk share y lines in that XCD's L2, while the chunks
+    // still interleave finely enough to keep the XCDs' loads even.
+    constexpr int64_t kChunk = 64;
+    const int64_t nbk = gridDim.x, full = nbk / (8 * kChunk) * (8 * kChunk);
+    const int64_t bx = blockIdx.x, q = bx / 8;
+    const int64_t lb = (bx < full) ? ((q / kChunk) * 8 + bx % 8) * kChunk + q % kChunk : bx;
+    const int64_t key = (lb * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (key >= FV) return;  // uniform over the wavefront
     const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
     const int64_t f = key / V;
-    const int64_t v = f * V + from_angular_major(key - f * V, nr, ne, na);
+    const int64_t v = f * V + store_voxel(key - f * V, nr, ne, na);
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;

@@ -98,18 +98,33 @@ __host__ __device__ __forceinline__ int64_t sell_index(int64_t base, int lane, i
     return base + (int64_t)(j >> 2) * 256 + lane * 4 + (j & 3);
 }
 
-// Voxel (ir, ie, ia) <-> angular-major key (ie * na + ia) * nr + ir, the order
-// of the voxel-major store.
-__host__ __device__ __forceinline__ int32_t angular_major(int32_t v, int nr, int ne, int na) {
+// Voxel (ir, ie, ia) <-> its key in the voxel-major store: the (ie, ia)
+// cells are taken in 4 x 4 tiles (row-major over tiles, row-major inside a
+// tile, edge tiles partial), and all shells of one cell are consecutive.
+// Consecutive keys are then voxels that every view sees in one compact patch
+// of its detector, so the wavefronts working on them share cache lines of y.
+constexpr int kKeyTile = 4;
+__host__ __device__ __forceinline__ int32_t store_key(int32_t v, int nr, int ne, int na) {
+    const int T = kKeyTile;
     const int ir = v / (ne * na), ie = (v / na) % ne, ia = v % na;
-    return (ie * na + ia) * nr + ir;
+    const int te = ie / T, ta = ia / T;
+    const int he = min(T, ne - te * T), ha = min(T, na - ta * T);
+    const int cell = te * T * na + ta * he * T + (ie - te * T) * ha + (ia - ta * T);
+    return cell * nr + ir;
 }
-__host__ __device__ __forceinline__ int32_t from_angular_major(int64_t k, int nr, int ne,
+__host__ __device__ __forceinline__ int32_t store_voxel(int64_t k, int nr, int ne,
                                                                int na) {
+    const int T = kKeyTile;
     const int ir = (int)(k % nr);
-    const int64_t q = k / nr;
-    const int ia = (int)(q % na), ie = (int)(q / na);
-    return (ir * ne + ie) * na + ia;
+    const int cell = (int)(k / nr);
+    const int nte = (ne + T - 1) / T;
+    const int te = min(cell / (T * na), nte - 1);
+    const int rem = cell - te * T * na;
+    const int he = min(T, ne - te * T);
+    const int ta = rem / (he * T);
+    const int rem2 = rem - ta * he * T;
+    const int ha = min(T, na - ta * T);
+    return (ir * ne + te * T + rem2 / ha) * na + ta * T + rem2 % ha;
 }
 
 // ---- launchers (tsp_trace.hip) ----
@@ -170,7 +185,7 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
                                const int64_t *slice_ptr, const int32_t *slice_len,
                                const int32_t *vox, const float *len, const float *rho, int B,
                                int64_t vf, float *y, hipStream_t st);
-// col_ptr is indexed by object frame, then the angular-major key; each entry
+// col_ptr is indexed by object frame, then the voxel's store key; each entry
 // packs (natural slot of the ray, length bits) as low / high 32 bits; x is
 // written in (frame, r, e, a) order.  y is first copied into slot order
 // (batch interleaved) in a stream-ordered temporary.

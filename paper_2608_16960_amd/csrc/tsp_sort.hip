@@ -11,10 +11,10 @@
 // Voxel-major store: the canonical (ray-ordered) segments are sorted by voxel
 // with a stable LSD radix sort (8-bit digits), so every voxel's list keeps
 // increasing ray order and the adjoint sums it in a fixed order.  Voxels are
-// keyed angular-major (all shells of one (e, a) cell, then the next cell): the
-// rays through consecutive lists are then a thin fan per view, so the
-// measurements they gather stay in L2 (in (r, e, a) order every shell needs
-// nearly every ray).
+// keyed by store_key (all shells of one (e, a) cell together, the cells in
+// 4 x 4 tiles): the rays through consecutive lists then form one compact fan
+// per view, so the measurements they gather stay in L2 (in (r, e, a) order
+// every shell needs nearly every ray).
 
 #include "tsp_internal.h"
 
@@ -162,11 +162,11 @@ __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t 
 }
 
 // Voxel-major key of a segment of ray r in voxel v: object frame of the
-// ray's view, then the voxel in angular-major order.
+// ray's view, then the voxel's store key.
 __device__ __forceinline__ int32_t seg_key(const RayDesc &rd, int32_t r, int32_t v, int nr,
                                            int ne, int na) {
     return (int32_t)frame_base(rd.obj_frame, (int64_t)rd.H * rd.W, r, (int64_t)nr * ne * na) +
-           angular_major(v, nr, ne, na);
+           store_key(v, nr, ne, na);
 }
 
 // Coarse histogram of the keys (bucket = key >> shift, nb <= kHistBuckets)
