@@ -83,6 +83,19 @@ __global__ void k_reduce_parts(const float *part, int nb, int stride, int count,
     out[j] = s;
 }
 
+// out[g][j] = sum over b in [g * per, min(nb, (g + 1) * per)) of part[b * stride + j], in
+// increasing b; the first stage of a two-stage fixed-order reduction.
+__global__ void k_reduce_groups(const float *part, int nb, int stride, int count, int per,
+                                float *out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (j >= count) return;
+    const int b1 = min(nb, (g + 1) * per);
+    float s = 0.0f;
+    for (int b = g * per; b < b1; b++) s += part[(int64_t)b * stride + j];
+    out[(int64_t)g * count + j] = s;
+}
+
 __device__ __forceinline__ float block_sum(float v, float *sh) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -278,44 +291,75 @@ __global__ __launch_bounds__(256) void k_conv_out_bwd_data(const uint16_t *x, co
 
 constexpr int kChunk = 1024;  // voxels per block of the channel sums
 constexpr int kRowsPerBlk = 16;  // azimuth rows per block of the small weight gradients
+constexpr int kSub = 8;          // voxel subsets per block (threads per channel)
 
 // mode 0 (input layer):  part[blk][t*32+o] = sum_p dz[p][o] * xin[p + off(t)]
 //                        part[blk][864+o]  = sum_p dz[p][o]
 // mode 1 (output layer): part[blk][t*32+i] = sum_p dout[p] * x[p + off(t)][i]
 //                        part[blk][864]    = sum_p dout[p]
-// A block walks kRowsPerBlk azimuth rows; thread jo owns outputs jo, jo+256, ...
+// Thread (c, s) owns channel c and azimuth positions s, s + 8, ... of the
+// block's rows, with the 27 tap sums in registers: each gradient value is
+// loaded once per voxel, the single-channel operand is a broadcast load.  The
+// 8 subsets are added in a fixed order through LDS.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_small_wgrad(const float *xin, const uint16_t *xb,
                                                      const uint16_t *dzb, const float *dout,
                                                      Dims d, float *part, int n_out) {
+    __shared__ float sh[kSub][28][C];
+    const int c = threadIdx.x % C, sub = threadIdx.x / C;
     const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
     const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlk;
-    for (int jo = threadIdx.x; jo < n_out; jo += 256) {
-        float s = 0.0f;
-        const bool bias = jo >= 27 * C;
-        const int t = bias ? 13 : jo / C, c = jo % C;
-        const int dr = t / 9 - 1, de = (t / 3) % 3 - 1, da = t % 3 - 1;
-        for (int64_t row = r0; row < r0 + kRowsPerBlk && row < rows; row++) {
-            const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
-            const int n = (int)(row / d.D1 / d.D0);
-            const int ii = i + dr, jj = j + de;
-            if (ii < 0 || ii >= d.D0 || jj < 0 || jj >= d.D1) continue;
-            const int64_t pb = row * d.D2;
-            const int64_t qb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
-            for (int k = 0; k < d.D2; k++) {
-                int kk = k + da;
-                kk = kk < 0 ? kk + d.D2 : (kk >= d.D2 ? kk - d.D2 : kk);
-                const int64_t p = pb + k, q = qb + kk;
+    float acc[27], bacc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 27; t++) acc[t] = 0.0f;
+    for (int64_t row = r0; row < r0 + kRowsPerBlk && row < rows; row++) {
+        const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
+        const int n = (int)(row / d.D1 / d.D0);
+        int64_t nb9[9];  // neighbour rows (dr, de), -1 outside the r / e range (zero padding)
+#pragma unroll
+        for (int q = 0; q < 9; q++) {
+            const int ii = i + q / 3 - 1, jj = j + q % 3 - 1;
+            nb9[q] = (ii < 0 || ii >= d.D0 || jj < 0 || jj >= d.D1)
+                         ? -1
+                         : (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
+        }
+        const int64_t pb = row * d.D2;
+        for (int k = sub; k < d.D2; k += kSub) {
+            const int64_t p = pb + k;
+            const float g = (MODE == 0) ? bf2f(dzb[p * C + c]) : dout[p];
+            bacc += g;
+            const int km = (k == 0) ? d.D2 - 1 : k - 1, kp = (k == d.D2 - 1) ? 0 : k + 1;
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                if (nb9[q] < 0) continue;
+                const int64_t qb = nb9[q];
+                const int64_t q0 = qb + km, q1 = qb + k, q2 = qb + kp;  // da = -1, 0, +1
+                float x0, x1, x2;
                 if (MODE == 0) {
-                    const float g = bf2f(dzb[p * C + c]);
-                    s = fmaf(g, bias ? 1.0f : xin[q], s);
+                    x0 = xin[q0];
+                    x1 = xin[q1];
+                    x2 = xin[q2];
                 } else {
-                    const float g = dout[p];
-                    s = fmaf(g, bias ? 1.0f : bf2f(xb[q * C + c]), s);
+                    x0 = bf2f(xb[q0 * C + c]);
+                    x1 = bf2f(xb[q1 * C + c]);
+                    x2 = bf2f(xb[q2 * C + c]);
                 }
+                acc[q * 3 + 0] = fmaf(g, x0, acc[q * 3 + 0]);
+                acc[q * 3 + 1] = fmaf(g, x1, acc[q * 3 + 1]);
+                acc[q * 3 + 2] = fmaf(g, x2, acc[q * 3 + 2]);
             }
         }
-        part[(int64_t)blockIdx.x * n_out + jo] = s;
+    }
+#pragma unroll
+    for (int t = 0; t < 27; t++) sh[sub][t][c] = acc[t];
+    sh[sub][27][c] = bacc;
+    __syncthreads();
+    for (int jo = threadIdx.x; jo < n_out; jo += 256) {
+        const int t = jo / C, cc = jo % C;  // t == 27: the bias row
+        float v = 0.0f;
+#pragma unroll
+        for (int u = 0; u < kSub; u++) v += sh[u][t][cc];
+        part[(int64_t)blockIdx.x * n_out + jo] = v;
     }
 }
 
@@ -524,6 +568,25 @@ inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per
 
 int wgrad_blocks(int64_t rows) { return (int)(rows < 256 ? rows : 256); }
 
+constexpr int kRedGroups = 16;  // first-stage groups of the partial reductions
+
+// out[j] = sum over the nb partial rows part[b * stride + j], j < count, in a
+// fixed order: kRedGroups groups of consecutive rows summed in parallel into
+// tmp [kRedGroups][count], then the group sums.
+void reduce_parts(const float *part, int nb, int stride, int count, float *out, float *tmp,
+                  hipStream_t st) {
+    if (nb <= 2 * kRedGroups) {
+        hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(count, 256)), dim3(256), 0, st, part, nb,
+                           stride, count, out);
+        return;
+    }
+    const int per = (nb + kRedGroups - 1) / kRedGroups;
+    hipLaunchKernelGGL(k_reduce_groups, dim3(nblk(count, 256), kRedGroups), dim3(256), 0, st, part,
+                       nb, stride, count, per, tmp);
+    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(count, 256)), dim3(256), 0, st, tmp, kRedGroups,
+                       count, count, out);
+}
+
 bool dims_ok(int N, int D0, int D1, int D2) { return N > 0 && D0 > 0 && D1 > 0 && D2 > 0; }
 
 tspnn_status hipret(hipError_t e, const char *what) {
@@ -602,7 +665,9 @@ size_t tspnn_conv_workspace(int32_t N, int32_t D0, int32_t D1, int32_t D2) {
     const size_t b = sizeof(float) * (size_t)rblk * (27 * C + C);
     const size_t c = sizeof(float) * (size_t)chunks * C;
     size_t mx = a > b ? a : b;
-    return (mx > c ? mx : c) + 256;
+    mx = mx > c ? mx : c;
+    // the first-stage group sums of reduce_parts follow the partials
+    return mx + sizeof(float) * (size_t)kRedGroups * 27 * C * C + 256;
 }
 
 tspnn_status tspnn_conv_in_fwd(const float *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
@@ -657,13 +722,12 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
     const int nb = wgrad_blocks(rows);
     float *part = (float *)work;
     hipLaunchKernelGGL(k_conv_wgrad_mfma, dim3(nb), dim3(256), 0, st, x, dz, d, part);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C * C, 256)), dim3(256), 0, st, part, nb,
-                       27 * C * C, 27 * C * C, dw);
+    reduce_parts(part, nb, 27 * C * C, 27 * C * C, dw, part + (int64_t)nb * 27 * C * C, st);
     if (db) {
         const int64_t nv = d.vox();
         const int nc = (int)((nv + kChunk - 1) / kChunk);
         hipLaunchKernelGGL(k_chan_sum, dim3(nc), dim3(256), 0, st, dz, nv, part);
-        hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part, nc, C, C, db);
+        reduce_parts(part, nc, C, C, db, part + (int64_t)nc * C, st);
     }
     return hipret(hipGetLastError(), "tspnn_conv_bwd_weight");
 }
@@ -681,10 +745,10 @@ tspnn_status tspnn_conv_in_bwd_weight(const float *x, const uint16_t *dz, int32_
     float *part = (float *)work;
     hipLaunchKernelGGL(k_small_wgrad<0>, dim3(nc), dim3(256), 0, st, x, (const uint16_t *)nullptr,
                        dz, (const float *)nullptr, d, part, n_out);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C, 256)), dim3(256), 0, st, part, nc, n_out,
-                       27 * C, dw);
+    float *tmp = part + (int64_t)nc * n_out;
+    reduce_parts(part, nc, n_out, 27 * C, dw, tmp, st);
     // bias sums live at offset 27*C of every partial row
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part + 27 * C, nc, n_out, C, db);
+    reduce_parts(part + 27 * C, nc, n_out, C, db, tmp, st);
     return hipret(hipGetLastError(), "tspnn_conv_in_bwd_weight");
 }
 
@@ -713,9 +777,9 @@ tspnn_status tspnn_conv_out_bwd(const uint16_t *x, const float *dout, int32_t N,
     float *part = (float *)work;
     hipLaunchKernelGGL(k_small_wgrad<1>, dim3(nc), dim3(256), 0, st, (const float *)nullptr, x,
                        (const uint16_t *)nullptr, dout, d, part, n_out);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(27 * C, 256)), dim3(256), 0, st, part, nc, n_out,
-                       27 * C, dw);
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(64), 0, st, part + 27 * C, nc, n_out, 1, db);
+    float *tmp = part + (int64_t)nc * n_out;
+    reduce_parts(part, nc, n_out, 27 * C, dw, tmp, st);
+    reduce_parts(part + 27 * C, nc, n_out, 1, db, tmp, st);
     if (dz_in)
         hipLaunchKernelGGL(k_conv_out_bwd_data, dim3(nblk(d.vox(), 256)), dim3(256), 0, st, x, dout,
                            d, w, dz_in);
