@@ -193,11 +193,13 @@ tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
 /*
  * Precompute steps 1-3 (Sec. 3.1-3.3) for every ray.
  *   TSP_MODE_CSR: counts segments per ray, then stores the canonical segment
- *     lists (voxel index int32 + length float32 per segment) in a ray-major
- *     store, and unless TSP_TRACE_NO_CSC is set also a voxel-major
- *     (transposed) store for the deterministic adjoint.  Needs about 8 bytes
- *     per segment per store plus 20 bytes per segment of temporary space
- *     while the transposed store is built.  TSP_E_NOMEM when that exceeds
+ *     lists in a ray-major store (a float32 length and a one-byte voxel step
+ *     per segment, about 5 bytes), and unless TSP_TRACE_NO_CSC is set also
+ *     a voxel-major (transposed) store for the deterministic adjoint (8 bytes
+ *     per segment).  The transposed store is built in passes whose temporary
+ *     space (about 17 bytes per segment of a pass) fits the free device
+ *     memory; the environment variable TSP_TRANSPOSE_MAX_ENTRIES caps the
+ *     segments of one pass.  TSP_E_NOMEM when the stores themselves exceed
  *     the device or the cap in the environment variable TSP_MAX_DEVICE_BYTES
  *     (the caller may then retry with TSP_MODE_ONTHEFLY).
  *   TSP_MODE_ONTHEFLY: only counts segments (for tsp_query) and stores no

@@ -67,7 +67,7 @@ struct tsp_geometry {
     // ray-major sliced store
     int32_t *d_perm = nullptr, *d_cnt_sorted = nullptr, *d_slice_len = nullptr;
     int64_t *d_slice_ptr = nullptr;
-    int32_t *d_vox = nullptr;
+    uint8_t *d_code = nullptr;  // entry codes (voxel steps, escapes)
     float *d_len = nullptr;
     int64_t *d_row_ptr = nullptr;
     // voxel-major store
@@ -137,7 +137,7 @@ void release_stores(tsp_geometry *g) {
     dfree_p(g, g->d_cnt_sorted);
     dfree_p(g, g->d_slice_len);
     dfree_p(g, g->d_slice_ptr);
-    dfree_p(g, g->d_vox);
+    dfree_p(g, g->d_code);
     dfree_p(g, g->d_len);
     dfree_p(g, g->d_row_ptr);
     dfree_p(g, g->d_col_ptr);
@@ -180,7 +180,8 @@ hipError_t forward_dispatch(const tsp_geometry *g, const float *rho, int batch, 
                             hipStream_t st) {
     if (g->mode == TSP_MODE_CSR)
         return launch_forward_sell(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                   g->d_slice_len, g->d_vox, g->d_len, rho, batch, g->V, y, st);
+                                   g->d_slice_len, g->d_code, g->d_len, rho, batch, g->V,
+                                   g->T.na, g->T.ne * g->T.na, y, st);
     return launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
 }
 
@@ -194,7 +195,8 @@ hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, fl
     if (e != hipSuccess) return e;
     if (g->mode == TSP_MODE_CSR)
         return launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                     g->d_slice_len, g->d_vox, g->d_len, y, batch, g->V, x, st);
+                                     g->d_slice_len, g->d_code, g->d_len, y, batch, g->V,
+                                     g->T.na, g->T.ne * g->T.na, x, st);
     return launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
 }
 
@@ -557,8 +559,8 @@ tsp_status build_transpose(tsp_geometry *g, hipStream_t st) {
         if ((s = dalloc_n(g, &hist, nb, "key histogram")) != TSP_OK) return s;
         e = launch_zero_f32((float *)hist, 2 * (int64_t)nb, st);
         if (e == hipSuccess)
-            e = launch_key_hist(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, nr, ne,
-                                na, shift, nb, hist, st);
+            e = launch_key_hist(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
+                                g->d_len, nr, ne, na, shift, nb, hist, st);
         std::vector<unsigned long long> h((size_t)nb);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e == hipSuccess)
@@ -612,8 +614,8 @@ tsp_status build_transpose(tsp_geometry *g, hipStream_t st) {
         const int64_t *rows = one_pass ? g->d_row_ptr : crow;
         int64_t np = S;
         if (!one_pass) {
-            e = launch_count_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, nr,
-                                   ne, na, lo, hi, cnt, st);
+            e = launch_count_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
+                                   g->d_len, nr, ne, na, lo, hi, cnt, st);
             if (e == hipSuccess) e = launch_scan_i32(cnt, R, 1, crow, stmp, st);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(&np, crow + R, sizeof(int64_t), hipMemcpyDeviceToHost, st);
@@ -626,7 +628,7 @@ tsp_status build_transpose(tsp_geometry *g, hipStream_t st) {
         }
         uint64_t *dst = g->d_col_ent + base;
         int in_second = 0;
-        e = launch_expand_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox,
+        e = launch_expand_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
                                 g->d_len, rows, nr, ne, na, lo, hi, k1, v1, st);
         if (e == hipSuccess) e = launch_radix_sort(k1, v1, k2, dst, np, bits, ws, &in_second, st);
         if (e == hipSuccess && !in_second) e = launch_copy_u64(v1, dst, np, st);
@@ -707,21 +709,27 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
     const int64_t ns = rd.n_slots;
     tsp_status s;
 
-    // pass 1: count canonical segments per ray
-    int32_t *cnt_nat = nullptr;
+    // pass 1: store entries and canonical segments per ray (entries only in
+    // CSR mode, where they lay out the store)
+    const bool csr = base_mode == TSP_MODE_CSR;
+    int32_t *cnt_nat = nullptr, *seg_nat = nullptr;
     int64_t *counters = nullptr;  // [0] total (u64), [1] max count (int), [2] fill error (int)
-    if ((s = dalloc_n(g, &cnt_nat, ns, "counts")) != TSP_OK) return s;
-    if ((s = dalloc_n(g, &counters, 4, "counters")) != TSP_OK) {
-        dfree(g, cnt_nat);
-        return s;
-    }
     auto free_tmp = [&]() {
         dfree(g, cnt_nat);
+        dfree(g, seg_nat);
         dfree(g, counters);
+        cnt_nat = seg_nat = nullptr;
+        counters = nullptr;
     };
+    if ((csr && (s = dalloc_n(g, &cnt_nat, ns, "entry counts")) != TSP_OK) ||
+        (csr && (s = dalloc_n(g, &seg_nat, ns, "segment counts")) != TSP_OK) ||
+        (s = dalloc_n(g, &counters, 4, "counters")) != TSP_OK) {
+        free_tmp();
+        return s;
+    }
     hipError_t e = hipMemsetAsync(counters, 0, 4 * sizeof(int64_t), st);
     if (e == hipSuccess)
-        e = launch_count(g->T, g->d_tab, rd, cnt_nat, (unsigned long long *)counters,
+        e = launch_count(g->T, g->d_tab, rd, cnt_nat, seg_nat, (unsigned long long *)counters,
                          (int *)(counters + 1), st);
     int64_t host_ctr[4] = {0, 0, 0, 0};
     if (e == hipSuccess)
@@ -772,10 +780,10 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
     g->n_stored = n_stored;
 
     // pass 2: fill the sliced ray-major store
-    if ((s = dalloc_n(g, &g->d_vox, n_stored, "segment voxels")) != TSP_OK) return abort_all(s);
+    if ((s = dalloc_n(g, &g->d_code, n_stored, "entry codes")) != TSP_OK) return abort_all(s);
     if ((s = dalloc_n(g, &g->d_len, n_stored, "segment lengths")) != TSP_OK) return abort_all(s);
     e = launch_fill(g->T, g->d_tab, rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                    g->d_slice_len, g->d_vox, g->d_len, (int *)(counters + 2), st);
+                    g->d_slice_len, g->d_code, g->d_len, (int *)(counters + 2), st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_ctr, counters, sizeof host_ctr, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -790,7 +798,7 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
         dfree(g, cnt_ray);
         return abort_all(s);
     }
-    e = launch_scatter_counts(g->d_perm, g->d_cnt_sorted, ns, cnt_ray, st);
+    e = launch_scatter_nat(rd, seg_nat, cnt_ray, st);
     if (e == hipSuccess) e = launch_scan_i32(cnt_ray, g->R, 1, g->d_row_ptr, scan_tmp, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dfree(g, cnt_ray);
@@ -895,7 +903,8 @@ tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, c
     if (e == hipSuccess) e = launch_atten_w(t1, rho, n, w, st);
     if (e == hipSuccess)
         e = launch_fwd_atten(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
-                             g->d_vox, g->d_len, sv, w, batch, g->V, y, st);
+                             g->d_code, g->d_len, sv, w, batch, g->V, g->T.na,
+                             g->T.ne * g->T.na, y, st);
     const hipError_t r = tmp.release();
     if (e == hipSuccess) e = r;
     if (e != hipSuccess)
@@ -929,7 +938,8 @@ tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, 
     if (e == hipSuccess) e = launch_zero_f32(gsl, n, st);
     if (e == hipSuccess)
         e = launch_bwd_atten(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
-                             g->d_vox, g->d_len, sv, w, gy, batch, g->V, gw, gsl, st);
+                             g->d_code, g->d_len, sv, w, gy, batch, g->V, g->T.na,
+                             g->T.ne * g->T.na, gw, gsl, st);
     if (e == hipSuccess) e = launch_atten_gtau(w, gw, n, gt, st);
     if (e == hipSuccess) e = adjoint_dispatch(g_sun, gt, batch, gsun, method, st);  // F_1^T
     if (e == hipSuccess)
@@ -951,8 +961,8 @@ tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, f
     hipError_t e = hipSuccess;
     if (row_ptr) e = launch_copy_i64(g->d_row_ptr, row_ptr, g->R + 1, st);
     if (e == hipSuccess && (vox || len))
-        e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_vox, g->d_len,
-                          g->rd.n_slots, g->d_row_ptr, vox, len, st);
+        e = launch_expand(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code, g->d_len,
+                          g->rd.n_slots, g->d_row_ptr, g->T.na, g->T.ne * g->T.na, vox, len, st);
     if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
     return TSP_OK;
 }

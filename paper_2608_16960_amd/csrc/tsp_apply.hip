@@ -51,16 +51,20 @@ template <> struct YVec<4> {
     }
 };
 
+// Four entries of one lane: codes (one byte each, entry 0 lowest) and lengths.
 template <int NB>
-__device__ __forceinline__ void fwd_quad(const v4i v, const v4f l, int j, int c,
+__device__ __forceinline__ void fwd_quad(uint32_t cw, const v4f l, int j, int c, int na,
+                                         int nena, int32_t &v,
                                          const typename YVec<NB>::T *__restrict__ rho,
                                          float *acc) {
 #pragma unroll
     for (int i = 0; i < 4; i++) {
-        const bool ok = j + i < c;  // padding entries hold voxel 0, length 0
-        const typename YVec<NB>::T r = rho[v[i]];
+        const int cd = (cw >> (8 * i)) & 255;
+        const float li = decode_entry(cd, l[i], v, na, nena);
+        const bool ok = j + i < c && cd != kCodeEsc;  // escapes and padding add nothing
+        const typename YVec<NB>::T r = rho[v];
 #pragma unroll
-        for (int b = 0; b < NB; b++) acc[b] = fmaf(l[i], ok ? YVec<NB>::get(r, b) : 0.0f, acc[b]);
+        for (int b = 0; b < NB; b++) acc[b] = fmaf(li, ok ? YVec<NB>::get(r, b) : 0.0f, acc[b]);
     }
 }
 
@@ -69,12 +73,12 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
                                                    const int32_t *__restrict__ cnt_sorted,
                                                    const int64_t *__restrict__ slice_ptr,
                                                    const int32_t *__restrict__ slice_len,
-                                                   const int32_t *__restrict__ vox,
+                                                   const uint8_t *__restrict__ code,
                                                    const float *__restrict__ len, int64_t n_slots,
                                                    const typename YVec<NB>::T *__restrict__ rho,
                                                    int nb, int64_t R, float *__restrict__ y,
                                                    const int32_t *__restrict__ obj_frame,
-                                                   int64_t hw, int64_t vf) {
+                                                   int64_t hw, int64_t vf, int na, int nena) {
     // rho: voxel-major, NB objects per voxel (all object frames); vf: voxels of one frame
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
@@ -84,27 +88,29 @@ __global__ __launch_bounds__(256) void k_fwd_sell(const int32_t *__restrict__ pe
     rho += (ray >= 0) ? frame_base(obj_frame, hw, ray, vf) : 0;
     const int c = cnt_sorted[slot];
     const int nq = slice_len[s] >> 2;  // quads of segments in this slice
-    const v4i *vp = (const v4i *)(vox + slice_ptr[s]) + lane;
+    const uint32_t *cp = (const uint32_t *)(code + slice_ptr[s]) + lane;
     const v4f *lp = (const v4f *)(len + slice_ptr[s]) + lane;
+    int32_t v = 0;
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
     int q = 0;
     for (; q + 4 <= nq; q += 4) {
-        v4i v[4];
+        uint32_t cw[4];
         v4f l[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-            v[u] = ld_nt(vp + (int64_t)(q + u) * kWave);
+            cw[u] = __builtin_nontemporal_load(cp + (int64_t)(q + u) * kWave);
             l[u] = ld_nt(lp + (int64_t)(q + u) * kWave);
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) fwd_quad<NB>(v[u], l[u], 4 * (q + u), c, rho, acc);
+        for (int u = 0; u < 4; u++)
+            fwd_quad<NB>(cw[u], l[u], 4 * (q + u), c, na, nena, v, rho, acc);
     }
     for (; q < nq; q++) {
-        const v4i v = ld_nt(vp + (int64_t)q * kWave);
+        const uint32_t cw = __builtin_nontemporal_load(cp + (int64_t)q * kWave);
         const v4f l = ld_nt(lp + (int64_t)q * kWave);
-        fwd_quad<NB>(v, l, 4 * q, c, rho, acc);
+        fwd_quad<NB>(cw, l, 4 * q, c, na, nena, v, rho, acc);
     }
     if (ray >= 0) {
 #pragma unroll
@@ -211,12 +217,12 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
                                                      const int32_t *__restrict__ cnt_sorted,
                                                      const int64_t *__restrict__ slice_ptr,
                                                      const int32_t *__restrict__ slice_len,
-                                                     const int32_t *__restrict__ vox,
+                                                     const uint8_t *__restrict__ code,
                                                      const float *__restrict__ len,
                                                      int64_t n_slots, const float *__restrict__ y,
                                                      int nb, int64_t V, int64_t R, float *x,
                                                      const int32_t *__restrict__ obj_frame,
-                                                     int64_t hw, int64_t vf) {
+                                                     int64_t hw, int64_t vf, int na, int nena) {
     // V: batch stride of x (voxels of all object frames); vf: one frame
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
@@ -229,13 +235,15 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
     float yv[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) yv[b] = (ray >= 0 && b < nb) ? y[b * R + ray] : 0.0f;
+    int32_t vraw = 0;
     for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
         int v = -1;
         float l = 0.0f;
         if (j < c) {
             const int64_t i = sell_index(base, lane, j);
-            v = fb + vox[i];
-            l = len[i];
+            const int cd = code[i];
+            l = decode_entry(cd, len[i], vraw, na, nena);
+            v = (cd == kCodeEsc) ? -1 : fb + vraw;
         }
         float cb[NB];
 #pragma unroll
@@ -274,8 +282,9 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 template <int NB>
 static hipError_t fwd_chunk(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
-                            const int32_t *vox, const float *len, const float *rho, int nb,
-                            int64_t vf, int64_t FV, float *y, void *packed, hipStream_t st) {
+                            const uint8_t *code, const float *len, const float *rho, int nb,
+                            int64_t vf, int64_t FV, int na, int nena, float *y, void *packed,
+                            hipStream_t st) {
     using T = typename YVec<NB>::T;
     const T *r = (const T *)rho;
     if (NB > 1) {
@@ -284,15 +293,15 @@ static hipError_t fwd_chunk(const RayDesc &rd, const int32_t *perm, const int32_
         r = (const T *)packed;
     }
     hipLaunchKernelGGL(k_fwd_sell<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
-                       cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, r, nb, rd.R, y,
-                       rd.obj_frame, (int64_t)rd.H * rd.W, vf);
+                       cnt_sorted, slice_ptr, slice_len, code, len, rd.n_slots, r, nb, rd.R, y,
+                       rd.obj_frame, (int64_t)rd.H * rd.W, vf, na, nena);
     return hipGetLastError();
 }
 
 hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
-                               const int32_t *vox, const float *len, const float *rho, int B,
-                               int64_t vf, float *y, hipStream_t st) {
+                               const uint8_t *code, const float *len, const float *rho, int B,
+                               int64_t vf, int na, int nena, float *y, hipStream_t st) {
     // batches: objects packed voxel-major (4, 8 or 16 bytes per voxel) so that
     // one gather per segment serves every object of a group of up to four
     const int64_t FV = vf * rd.n_obj_frames;
@@ -308,14 +317,14 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
         const float *r = rho + (int64_t)b0 * FV;
         float *yy = y + (int64_t)b0 * rd.R;
         if (nb == 1)
-            e = fwd_chunk<1>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
-                             yy, packed, st);
+            e = fwd_chunk<1>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
+                             FV, na, nena, yy, packed, st);
         else if (nb == 2)
-            e = fwd_chunk<2>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
-                             yy, packed, st);
+            e = fwd_chunk<2>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
+                             FV, na, nena, yy, packed, st);
         else
-            e = fwd_chunk<4>(rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, r, nb, vf, FV,
-                             yy, packed, st);
+            e = fwd_chunk<4>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
+                             FV, na, nena, yy, packed, st);
     }
     if (packed) {
         const hipError_t f = hipFreeAsync(packed, st);
@@ -362,8 +371,9 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const u
 
 hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                                 const int32_t *slice_len, const int32_t *vox, const float *len,
-                                 const float *y, int B, int64_t vf, float *x, hipStream_t st) {
+                                 const int32_t *slice_len, const uint8_t *code, const float *len,
+                                 const float *y, int B, int64_t vf, int na, int nena, float *x,
+                                 hipStream_t st) {
     const int64_t FV = vf * rd.n_obj_frames, R = rd.R, hw = (int64_t)rd.H * rd.W;
     const int64_t n_slots = rd.n_slots;
     for (int b0 = 0; b0 < B; b0 += 4) {
@@ -373,16 +383,16 @@ hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
         const dim3 g(blocks_for(n_slots, 256));
         if (nb == 1)
             hipLaunchKernelGGL(k_adj_atomic<1>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
-                               vf);
+                               slice_len, code, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf, na, nena);
         else if (nb == 2)
             hipLaunchKernelGGL(k_adj_atomic<2>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
-                               vf);
+                               slice_len, code, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf, na, nena);
         else
             hipLaunchKernelGGL(k_adj_atomic<4>, g, dim3(256), 0, st, perm, cnt_sorted, slice_ptr,
-                               slice_len, vox, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
-                               vf);
+                               slice_len, code, len, n_slots, yy, nb, FV, R, xx, rd.obj_frame, hw,
+                               vf, na, nena);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -56,16 +56,17 @@ __global__ void k_atten_grad(const float *tau1, const float *sigma, const float 
 }
 
 // One lane per ray slot of the ray-major store (see tsp_apply.hip for the
-// layout); segment j of the lane at sell_index(base, lane, j), j in order of
-// distance from the detector; padding entries have length 0.
+// layout); entry j of the lane at sell_index(base, lane, j), j in order of
+// distance from the detector, voxels rebuilt from the entry codes; escape
+// and padding entries carry no length.
 __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cnt_sorted,
                                                     const int64_t *__restrict__ slice_ptr,
                                                     const int32_t *__restrict__ slice_len,
-                                                    const int32_t *__restrict__ vox,
+                                                    const uint8_t *__restrict__ code,
                                                     const float *__restrict__ len,
                                                     int64_t n_slots, const float *__restrict__ s,
-                                                    const float *__restrict__ w,
+                                                    const float *__restrict__ w, int na, int nena,
                                                     float *__restrict__ y) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
@@ -75,10 +76,12 @@ __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ p
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
     float T = 0.0f, acc = 0.0f;
+    int32_t v = 0;
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
-        const int32_t v = __builtin_nontemporal_load(vox + i);
-        const float l = __builtin_nontemporal_load(len + i);
+        const int cd = __builtin_nontemporal_load(code + i);
+        const float l = decode_entry(cd, __builtin_nontemporal_load(len + i), v, na, nena);
+        if (cd == kCodeEsc) continue;
         T = fmaf(s[v], l, T);
         acc = fmaf(w[v] * expf(-T), l, acc);
     }
@@ -89,12 +92,12 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                                                     const int32_t *__restrict__ cnt_sorted,
                                                     const int64_t *__restrict__ slice_ptr,
                                                     const int32_t *__restrict__ slice_len,
-                                                    const int32_t *__restrict__ vox,
+                                                    const uint8_t *__restrict__ code,
                                                     const float *__restrict__ len,
                                                     int64_t n_slots, const float *__restrict__ s,
                                                     const float *__restrict__ w,
-                                                    const float *__restrict__ gy, float *gw,
-                                                    float *gs) {
+                                                    const float *__restrict__ gy, int na,
+                                                    int nena, float *gw, float *gs) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
     const int lane = (int)(slot & 63);
@@ -105,23 +108,29 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
     const float g = (ray >= 0) ? gy[ray] : 0.0f;
     // pass 1: the ray's measurement (the total that the suffix sums start from)
     float T = 0.0f, yr = 0.0f;
+    int32_t vr = 0;
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
-        const int32_t v = vox[i];
-        const float l = len[i];
-        T = fmaf(s[v], l, T);
-        yr = fmaf(w[v] * expf(-T), l, yr);
+        const int cd = code[i];
+        const float l = decode_entry(cd, len[i], vr, na, nena);
+        if (cd == kCodeEsc) continue;
+        T = fmaf(s[vr], l, T);
+        yr = fmaf(w[vr] * expf(-T), l, yr);
     }
     // pass 2: both gradient terms of every segment, merged across the wavefront
     T = 0.0f;
     float prefix = 0.0f;
+    vr = 0;
     for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
         int v = -1;
-        float a = 0.0f, bterm = 0.0f;
+        float a = 0.0f, bterm = 0.0f, l = 0.0f;
         if (j < c) {
             const int64_t i = sell_index(base, lane, j);
-            v = vox[i];
-            const float l = len[i];
+            const int cd = code[i];
+            l = decode_entry(cd, len[i], vr, na, nena);
+            if (cd != kCodeEsc) v = vr;
+        }
+        if (v >= 0) {
             T = fmaf(s[v], l, T);
             const float E = expf(-T);
             const float ck = w[v] * E * l;
@@ -182,12 +191,12 @@ hipError_t launch_atten_grad(const float *tau1, const float *sigma, const float 
 
 hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
-                            const int32_t *vox, const float *len, const float *s, const float *w,
-                            int B, int64_t V, float *y, hipStream_t st) {
+                            const uint8_t *code, const float *len, const float *s, const float *w,
+                            int B, int64_t V, int na, int nena, float *y, hipStream_t st) {
     for (int b = 0; b < B; b++) {
         hipLaunchKernelGGL(k_fwd_atten, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
-                           cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, s + b * V,
-                           w + b * V, y + b * rd.R);
+                           cnt_sorted, slice_ptr, slice_len, code, len, rd.n_slots, s + b * V,
+                           w + b * V, na, nena, y + b * rd.R);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -196,13 +205,13 @@ hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
 
 hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
-                            const int32_t *vox, const float *len, const float *s, const float *w,
-                            const float *gy, int B, int64_t V, float *gw, float *gs,
-                            hipStream_t st) {
+                            const uint8_t *code, const float *len, const float *s, const float *w,
+                            const float *gy, int B, int64_t V, int na, int nena, float *gw,
+                            float *gs, hipStream_t st) {
     for (int b = 0; b < B; b++) {
         hipLaunchKernelGGL(k_bwd_atten, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
-                           cnt_sorted, slice_ptr, slice_len, vox, len, rd.n_slots, s + b * V,
-                           w + b * V, gy + b * rd.R, gw + b * V, gs + b * V);
+                           cnt_sorted, slice_ptr, slice_len, code, len, rd.n_slots, s + b * V,
+                           w + b * V, gy + b * rd.R, na, nena, gw + b * V, gs + b * V);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

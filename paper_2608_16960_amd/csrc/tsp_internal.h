@@ -90,6 +90,41 @@ __host__ __device__ __forceinline__ int64_t natural_slot(const RayDesc &rd, int6
     return (in_window & ~(int64_t)(kWindow - 1)) | lane;
 }
 
+// Ray-major store entries: a float32 length and a one-byte code.  Along a ray
+// the next voxel almost always differs from the previous one by one step of
+// one index (ir, ie or ia by +-1, ia wrapping round), so the code holds the
+// step and the voxel index is rebuilt by a running sum:
+//   0 stay (delta 0), 1 / 2 = +-1, 3 / 4 = +-na, 5 / 6 = +-ne*na,
+//   7 / 8 = +-(na - 1) (an azimuth step across the cut of a cyclic grid),
+//   kCodeEsc: the entry's length slot holds the next voxel index itself
+//   (int32 bits) and the entry contributes nothing; the segment follows as a
+//   "stay" entry.
+// Every ray opens with an escape.  Padding entries are "stay" with length 0.
+constexpr int kCodeEsc = 15;
+__host__ __device__ __forceinline__ int32_t step_delta(int c, int na, int nena) {
+    const int32_t mag = (c <= 2) ? 1 : (c <= 4) ? na : (c <= 6) ? nena : na - 1;
+    return (c == 0 || c == kCodeEsc) ? 0 : ((c & 1) ? mag : -mag);
+}
+__host__ __device__ __forceinline__ int step_code(int32_t dv, int na, int nena) {
+    if (dv == 0) return 0;
+    if (dv == 1) return 1;
+    if (dv == -1) return 2;
+    if (dv == na) return 3;
+    if (dv == -na) return 4;
+    if (dv == nena) return 5;
+    if (dv == -nena) return 6;
+    if (dv == na - 1) return 7;
+    if (dv == -(na - 1)) return 8;
+    return kCodeEsc;
+}
+// One decoding step: updates the running voxel v, returns the segment length
+// the entry carries (0 for an escape or padding).
+__device__ __forceinline__ float decode_entry(int c, float l, int32_t &v, int na, int nena) {
+    const bool esc = c == kCodeEsc;
+    v = esc ? __float_as_int(l) : v + step_delta(c, na, nena);
+    return esc ? 0.0f : l;
+}
+
 // Ray-major sliced store: slice s holds 64 rays (one per lane); segment j of
 // lane l sits at slice_ptr[s] + 256 (j / 4) + 4 l + (j % 4), so each lane
 // reads four consecutive segments with one 16-byte load and a wavefront reads
@@ -129,11 +164,15 @@ __host__ __device__ __forceinline__ int32_t store_voxel(int64_t k, int nr, int n
 
 // ---- launchers (tsp_trace.hip) ----
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
-                        unsigned long long *total, int *maxcnt, hipStream_t st);
+                        int32_t *seg_nat, unsigned long long *total, int *maxcnt,
+                        hipStream_t st);
 hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
                        const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                       const int32_t *slice_len, int32_t *vox, float *len, int *err,
+                       const int32_t *slice_len, uint8_t *code, float *len, int *err,
                        hipStream_t st);
+// cnt_ray[natural_ray(s)] = seg_nat[s] for every natural slot s with a ray
+hipError_t launch_scatter_nat(const RayDesc &rd, const int32_t *seg_nat, int32_t *cnt_ray,
+                              hipStream_t st);
 // vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.
 hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *rho, int B, int64_t vf, float *y, hipStream_t st);
@@ -148,13 +187,11 @@ hipError_t launch_window_sort(const RayDesc &rd, const int32_t *cnt_nat, int32_t
 hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *out,
                            int64_t *tmp, hipStream_t st);
 int64_t scan_tmp_elems(int64_t n);
-hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
-                                 int32_t *cnt_ray, hipStream_t st);
 // Canonical CSR (ray-major, row_ptr order) export of the sliced store.
 hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                         const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                         int64_t n_slots, const int64_t *row_ptr, int32_t *out_vox,
-                         float *out_len, hipStream_t st);
+                         const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                         int64_t n_slots, const int64_t *row_ptr, int na, int nena,
+                         int32_t *out_vox, float *out_len, hipStream_t st);
 // stable LSD radix sort of (key, val) by key (key < 2^key_bits); result lands in
 // (keys, vals) or (keys2, vals2): returns through *in_second whether it is the second.
 hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint64_t *vals2,
@@ -166,13 +203,15 @@ size_t radix_ws_bytes(int64_t n);
 // range's column offsets with a base.
 int key_hist_buckets();
 hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                           const int64_t *slice_ptr, const int32_t *vox, int nr, int ne, int na,
-                           int shift, int nb, unsigned long long *hist, hipStream_t st);
+                           const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                           int nr, int ne, int na, int shift, int nb, unsigned long long *hist,
+                           hipStream_t st);
 hipError_t launch_count_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                              const int64_t *slice_ptr, const int32_t *vox, int nr, int ne,
-                              int na, int32_t lo, int32_t hi, int32_t *cnt_ray, hipStream_t st);
+                              const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                              int nr, int ne, int na, int32_t lo, int32_t hi, int32_t *cnt_ray,
+                              hipStream_t st);
 hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                               const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                               const int64_t *slice_ptr, const uint8_t *code, const float *len,
                                const int64_t *crow, int nr, int ne, int na, int32_t lo,
                                int32_t hi, int32_t *keys, uint64_t *vals, hipStream_t st);
 hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
@@ -183,8 +222,8 @@ hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_
 // vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.
 hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
-                               const int32_t *vox, const float *len, const float *rho, int B,
-                               int64_t vf, float *y, hipStream_t st);
+                               const uint8_t *code, const float *len, const float *rho, int B,
+                               int64_t vf, int na, int nena, float *y, hipStream_t st);
 // col_ptr is indexed by object frame, then the voxel's store key; each entry
 // packs (natural slot of the ray, length bits) as low / high 32 bits; x is
 // written in (frame, r, e, a) order.  y is first copied into slot order
@@ -194,8 +233,9 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const u
                               hipStream_t st);
 hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                                 const int32_t *slice_len, const int32_t *vox, const float *len,
-                                 const float *y, int B, int64_t vf, float *x, hipStream_t st);
+                                 const int32_t *slice_len, const uint8_t *code, const float *len,
+                                 const float *y, int B, int64_t vf, int na, int nena, float *x,
+                                 hipStream_t st);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st);
 
 // ---- launchers (tsp_atten.hip): attenuated emission model, one object per
@@ -211,13 +251,13 @@ hipError_t launch_atten_grad(const float *tau1, const float *sigma, const float 
                              hipStream_t st);
 hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
-                            const int32_t *vox, const float *len, const float *s, const float *w,
-                            int B, int64_t V, float *y, hipStream_t st);
+                            const uint8_t *code, const float *len, const float *s, const float *w,
+                            int B, int64_t V, int na, int nena, float *y, hipStream_t st);
 hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
-                            const int32_t *vox, const float *len, const float *s, const float *w,
-                            const float *gy, int B, int64_t V, float *gw, float *gs,
-                            hipStream_t st);
+                            const uint8_t *code, const float *len, const float *s, const float *w,
+                            const float *gy, int B, int64_t V, int na, int nena, float *gw,
+                            float *gs, hipStream_t st);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
 
 }  // namespace tsp

@@ -132,20 +132,21 @@ __global__ __launch_bounds__(256) void k_scan_apply(const int32_t *in, int64_t n
 
 // ------------------------------------------------------------ canonical order
 
-__global__ void k_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
-                                 int32_t *cnt_ray) {
+__global__ void k_scatter_nat(const RayDesc rd, const int32_t *seg_nat, int32_t *cnt_ray) {
     const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= n_slots) return;
-    const int32_t r = perm[slot];
-    if (r >= 0) cnt_ray[r] = cnt_sorted[slot];
+    if (slot >= rd.n_slots) return;
+    const int32_t r = natural_ray(rd, slot);
+    if (r >= 0) cnt_ray[r] = seg_nat[slot];
 }
 
+// Canonical CSR export: ray r's segments at row_ptr[r] ... in order, escape
+// entries dropped.
 __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t *perm,
                                                  const int32_t *cnt_sorted,
-                                                 const int64_t *slice_ptr, const int32_t *vox,
+                                                 const int64_t *slice_ptr, const uint8_t *code,
                                                  const float *len, int64_t n_slots,
-                                                 const int64_t *row_ptr, int32_t *out_vox,
-                                                 float *out_len) {
+                                                 const int64_t *row_ptr, int na, int nena,
+                                                 int32_t *out_vox, float *out_len) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int32_t r = perm[slot];
@@ -153,11 +154,16 @@ __global__ __launch_bounds__(256) void k_expand(const RayDesc rd, const int32_t 
     const int c = cnt_sorted[slot];
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
-    const int64_t dst = row_ptr[r];
+    int64_t dst = row_ptr[r];
+    int32_t v = 0;
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
-        if (out_vox) out_vox[dst + j] = vox[i];
-        if (out_len) out_len[dst + j] = len[i];
+        const int cd = code[i];
+        const float l = decode_entry(cd, len[i], v, na, nena);
+        if (cd == kCodeEsc) continue;
+        if (out_vox) out_vox[dst] = v;
+        if (out_len) out_len[dst] = l;
+        dst++;
     }
 }
 
@@ -174,8 +180,8 @@ __device__ __forceinline__ int32_t seg_key(const RayDesc &rd, int32_t r, int32_t
 constexpr int kHistBuckets = 4096;
 __global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_t *perm,
                                                    const int32_t *cnt_sorted,
-                                                   const int64_t *slice_ptr, const int32_t *vox,
-                                                   int64_t n_slots, int nr, int ne, int na,
+                                                   const int64_t *slice_ptr, const uint8_t *code,
+                                                   const float *len, int64_t n_slots, int nr, int ne, int na,
                                                    int shift, int nb,
                                                    unsigned long long *hist) {
     __shared__ unsigned h[kHistBuckets];
@@ -188,9 +194,13 @@ __global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_
             const int c = cnt_sorted[slot];
             const int64_t base = slice_ptr[slot >> 6];
             const int lane = (int)(slot & 63);
+            int32_t v = 0;
             for (int j = 0; j < c; j++) {
-                const int32_t k = seg_key(rd, r, vox[sell_index(base, lane, j)], nr, ne, na);
-                atomicAdd(&h[k >> shift], 1u);
+                const int64_t i = sell_index(base, lane, j);
+                const int cd = code[i];
+                decode_entry(cd, len[i], v, na, ne * na);
+                if (cd == kCodeEsc) continue;
+                atomicAdd(&h[seg_key(rd, r, v, nr, ne, na) >> shift], 1u);
             }
         }
     }
@@ -203,7 +213,8 @@ __global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_
 __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int32_t *perm,
                                                       const int32_t *cnt_sorted,
                                                       const int64_t *slice_ptr,
-                                                      const int32_t *vox, int64_t n_slots,
+                                                      const uint8_t *code, const float *len,
+                                                      int64_t n_slots,
                                                       int nr, int ne, int na, int32_t lo,
                                                       int32_t hi, int32_t *cnt_ray) {
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -214,8 +225,13 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
     int n = 0;
+    int32_t v = 0;
     for (int j = 0; j < c; j++) {
-        const int32_t k = seg_key(rd, r, vox[sell_index(base, lane, j)], nr, ne, na);
+        const int64_t i = sell_index(base, lane, j);
+        const int cd = code[i];
+        decode_entry(cd, len[i], v, na, ne * na);
+        if (cd == kCodeEsc) continue;
+        const int32_t k = seg_key(rd, r, v, nr, ne, na);
         n += (k >= lo && k < hi);
     }
     cnt_ray[r] = n;
@@ -226,7 +242,7 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
 __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const int32_t *perm,
                                                        const int32_t *cnt_sorted,
                                                        const int64_t *slice_ptr,
-                                                       const int32_t *vox, const float *len,
+                                                       const uint8_t *code, const float *len,
                                                        int64_t n_slots, const int64_t *crow,
                                                        int nr, int ne, int na, int32_t lo,
                                                        int32_t hi, int32_t *keys,
@@ -240,12 +256,16 @@ __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const in
     const int lane = (int)(slot & 63);
     const uint64_t ns = (uint64_t)(uint32_t)natural_slot(rd, slot, r);
     int64_t dst = crow[r];
+    int32_t v = 0;
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
-        const int32_t k = seg_key(rd, r, vox[i], nr, ne, na);
+        const int cd = code[i];
+        const float l = decode_entry(cd, len[i], v, na, ne * na);
+        if (cd == kCodeEsc) continue;
+        const int32_t k = seg_key(rd, r, v, nr, ne, na);
         if (k >= lo && k < hi) {
             keys[dst] = k;
-            vals[dst] = ns | ((uint64_t)__float_as_uint(len[i]) << 32);
+            vals[dst] = ns | ((uint64_t)__float_as_uint(l) << 32);
             dst++;
         }
     }
@@ -374,19 +394,20 @@ hipError_t launch_scan_i32(const int32_t *in, int64_t n, int64_t mul, int64_t *o
     return hipGetLastError();
 }
 
-hipError_t launch_scatter_counts(const int32_t *perm, const int32_t *cnt_sorted, int64_t n_slots,
-                                 int32_t *cnt_ray, hipStream_t st) {
-    hipLaunchKernelGGL(k_scatter_counts, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, perm,
-                       cnt_sorted, n_slots, cnt_ray);
+hipError_t launch_scatter_nat(const RayDesc &rd, const int32_t *seg_nat, int32_t *cnt_ray,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_nat, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
+                       seg_nat, cnt_ray);
     return hipGetLastError();
 }
 
 hipError_t launch_expand(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                         const int64_t *slice_ptr, const int32_t *vox, const float *len,
-                         int64_t n_slots, const int64_t *row_ptr, int32_t *out_vox,
-                         float *out_len, hipStream_t st) {
+                         const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                         int64_t n_slots, const int64_t *row_ptr, int na, int nena,
+                         int32_t *out_vox, float *out_len, hipStream_t st) {
     hipLaunchKernelGGL(k_expand, dim3(blocks_for(n_slots, 256)), dim3(256), 0, st, rd, perm,
-                       cnt_sorted, slice_ptr, vox, len, n_slots, row_ptr, out_vox, out_len);
+                       cnt_sorted, slice_ptr, code, len, n_slots, row_ptr, na, nena, out_vox,
+                       out_len);
     return hipGetLastError();
 }
 
@@ -439,27 +460,30 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
 int key_hist_buckets() { return kHistBuckets; }
 
 hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                           const int64_t *slice_ptr, const int32_t *vox, int nr, int ne, int na,
-                           int shift, int nb, unsigned long long *hist, hipStream_t st) {
+                           const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                           int nr, int ne, int na, int shift, int nb, unsigned long long *hist,
+                           hipStream_t st) {
     hipLaunchKernelGGL(k_key_hist, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, perm,
-                       cnt_sorted, slice_ptr, vox, rd.n_slots, nr, ne, na, shift, nb, hist);
+                       cnt_sorted, slice_ptr, code, len, rd.n_slots, nr, ne, na, shift, nb, hist);
     return hipGetLastError();
 }
 
 hipError_t launch_count_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                              const int64_t *slice_ptr, const int32_t *vox, int nr, int ne,
-                              int na, int32_t lo, int32_t hi, int32_t *cnt_ray, hipStream_t st) {
+                              const int64_t *slice_ptr, const uint8_t *code, const float *len,
+                              int nr, int ne, int na, int32_t lo, int32_t hi, int32_t *cnt_ray,
+                              hipStream_t st) {
     hipLaunchKernelGGL(k_count_range, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
-                       perm, cnt_sorted, slice_ptr, vox, rd.n_slots, nr, ne, na, lo, hi, cnt_ray);
+                       perm, cnt_sorted, slice_ptr, code, len, rd.n_slots, nr, ne, na, lo, hi,
+                       cnt_ray);
     return hipGetLastError();
 }
 
 hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
-                               const int64_t *slice_ptr, const int32_t *vox, const float *len,
+                               const int64_t *slice_ptr, const uint8_t *code, const float *len,
                                const int64_t *crow, int nr, int ne, int na, int32_t lo,
                                int32_t hi, int32_t *keys, uint64_t *vals, hipStream_t st) {
     hipLaunchKernelGGL(k_expand_range, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd,
-                       perm, cnt_sorted, slice_ptr, vox, len, rd.n_slots, crow, nr, ne, na, lo,
+                       perm, cnt_sorted, slice_ptr, code, len, rd.n_slots, crow, nr, ne, na, lo,
                        hi, keys, vals);
     return hipGetLastError();
 }

@@ -72,25 +72,46 @@ __device__ __forceinline__ void ray_of(const RayDesc &rd, int32_t ray, V3 &x, V3
 
 // ---------------------------------------------------------------- visitors
 
+// Entries of the ray-major store (codec in tsp_internal.h): one per segment,
+// two where the voxel does not follow from the previous one by a coded step
+// (always for the first segment).
 struct CountVis {
-    int n = 0;
-    __device__ void seg(int, double) { n++; }
+    int n = 0;     // store entries
+    int segs = 0;  // canonical segments
+    int32_t prev = -1;
+    int na, nena;
+    __device__ void seg(int v, double) {
+        n += (prev < 0 || step_code(v - prev, na, nena) == kCodeEsc) ? 2 : 1;
+        prev = v;
+        segs++;
+    }
 };
 
 struct FillVis {
-    int32_t *vox;
+    uint8_t *code;
     float *len;
     int64_t base;
     int lane;
     int cap;
+    int na, nena;
     int n = 0;
-    __device__ void seg(int v, double l) {
+    int32_t prev = -1;
+    __device__ void put(int c, float l) {
         if (n < cap) {
             const int64_t i = sell_index(base, lane, n);
-            vox[i] = v;
-            len[i] = (float)l;
+            code[i] = (uint8_t)c;
+            len[i] = l;
         }
         n++;
+    }
+    __device__ void seg(int v, double l) {
+        int c = (prev < 0) ? kCodeEsc : step_code(v - prev, na, nena);
+        if (c == kCodeEsc) {
+            put(kCodeEsc, __int_as_float(v));
+            c = 0;
+        }
+        put(c, (float)l);
+        prev = v;
     }
 };
 
@@ -135,9 +156,11 @@ __device__ __forceinline__ int wave_max_i(int v) {
     return v;
 }
 
+// Per natural slot: store entries (cnt_nat) and canonical segments (seg_nat,
+// may be null); total and maxcnt over segments.
 __global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, RayDesc rd,
-                                                int32_t *cnt_nat, unsigned long long *total,
-                                                int *maxcnt) {
+                                                int32_t *cnt_nat, int32_t *seg_nat,
+                                                unsigned long long *total, int *maxcnt) {
     extern __shared__ double lds[];
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
@@ -145,14 +168,19 @@ __global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, Ray
     int c = 0;
     if (slot < rd.n_slots) {
         const int32_t ray = natural_ray(rd, slot);
+        int e = 0;
         if (ray >= 0) {
             V3 x, n;
             ray_of(rd, ray, x, n);
             CountVis vis;
+            vis.na = D.na;
+            vis.nena = D.ne * D.na;
             trace_ray(T, x, n, vis);
-            c = vis.n;
+            c = vis.segs;
+            e = vis.n;
         }
-        cnt_nat[slot] = c;
+        if (cnt_nat) cnt_nat[slot] = e;
+        if (seg_nat) seg_nat[slot] = c;
     }
     const int s = wave_sum_i(c);
     const int m = wave_max_i(c);
@@ -165,7 +193,7 @@ __global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, Ray
 __global__ __launch_bounds__(256) void k_fill(TabDesc D, const double *tab, RayDesc rd,
                                                const int32_t *perm, const int32_t *cnt_sorted,
                                                const int64_t *slice_ptr,
-                                               const int32_t *slice_len, int32_t *vox,
+                                               const int32_t *slice_len, uint8_t *code,
                                                float *len, int *err) {
     extern __shared__ double lds[];
     stage_tables(D, tab, lds);
@@ -182,14 +210,14 @@ __global__ __launch_bounds__(256) void k_fill(TabDesc D, const double *tab, RayD
     if (ray >= 0) {
         V3 x, nn;
         ray_of(rd, ray, x, nn);
-        FillVis vis{vox, len, base, lane, cap};
+        FillVis vis{code, len, base, lane, cap, D.na, D.ne * D.na};
         trace_ray(T, x, nn, vis);
         n = vis.n;
         if (n != cap) atomicOr(err, 1);
     }
     for (int j = min(n, cap); j < m; j++) {  // padding up to the slice length
         const int64_t i = sell_index(base, lane, j);
-        vox[i] = 0;
+        code[i] = 0;
         len[i] = 0.0f;
     }
 }
@@ -348,18 +376,19 @@ inline unsigned grid_of(int64_t n_slots) { return (unsigned)((n_slots + 255) / 2
 }  // namespace
 
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
-                        unsigned long long *total, int *maxcnt, hipStream_t st) {
+                        int32_t *seg_nat, unsigned long long *total, int *maxcnt,
+                        hipStream_t st) {
     hipLaunchKernelGGL(k_count, dim3(grid_of(rd.n_slots)), dim3(256), T.n_tab * sizeof(double),
-                       st, T, tab, rd, cnt_nat, total, maxcnt);
+                       st, T, tab, rd, cnt_nat, seg_nat, total, maxcnt);
     return hipGetLastError();
 }
 
 hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
                        const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
-                       const int32_t *slice_len, int32_t *vox, float *len, int *err,
+                       const int32_t *slice_len, uint8_t *code, float *len, int *err,
                        hipStream_t st) {
     hipLaunchKernelGGL(k_fill, dim3(grid_of(rd.n_slots)), dim3(256), T.n_tab * sizeof(double), st,
-                       T, tab, rd, perm, cnt_sorted, slice_ptr, slice_len, vox, len, err);
+                       T, tab, rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, err);
     return hipGetLastError();
 }
 
