@@ -195,11 +195,14 @@ tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
  *   TSP_MODE_CSR: counts segments per ray, then stores the canonical segment
  *     lists in a ray-major store (a float32 length and a one-byte voxel step
  *     per segment, about 5 bytes), and unless TSP_TRACE_NO_CSC is set also
- *     a voxel-major (transposed) store for the deterministic adjoint (8 bytes
- *     per segment).  The transposed store is built in passes whose temporary
- *     space (about 17 bytes per segment of a pass) fits the free device
- *     memory; the environment variable TSP_TRANSPOSE_MAX_ENTRIES caps the
- *     segments of one pass.  TSP_E_NOMEM when the stores themselves exceed
+ *     a voxel-major (transposed) store for the deterministic adjoint (a
+ *     float32 length and a one-byte slot increase per segment, plus escapes
+ *     and padding: about 5.1 bytes).  The transposed store is built by
+ *     sorting in passes whose temporary space (about 25 bytes per segment of
+ *     a pass) fits the free device memory; the environment variable
+ *     TSP_TRANSPOSE_MAX_ENTRIES caps the segments of one pass.  With more
+ *     than one pass the segments are sorted twice (once to size the store,
+ *     once to fill it).  TSP_E_NOMEM when the stores themselves exceed
  *     the device or the cap in the environment variable TSP_MAX_DEVICE_BYTES
  *     (the caller may then retry with TSP_MODE_ONTHEFLY).
  *   TSP_MODE_ONTHEFLY: only counts segments (for tsp_query) and stores no

@@ -71,8 +71,9 @@ struct tsp_geometry {
     float *d_len = nullptr;
     int64_t *d_row_ptr = nullptr;
     // voxel-major store
-    int64_t *d_col_ptr = nullptr;
-    uint64_t *d_col_ent = nullptr;  // (ray slot, length bits) per entry
+    int64_t *d_col_ptr = nullptr;   // [FV + 1] block offsets per key
+    uint8_t *d_col_code = nullptr;  // slot increases and escapes
+    float *d_col_len = nullptr;
     // dynamic objects: object frame per cone view (null for a static object)
     int32_t *d_obj_frame = nullptr;
     int64_t FV() const { return V * rd.n_obj_frames; }
@@ -141,7 +142,8 @@ void release_stores(tsp_geometry *g) {
     dfree_p(g, g->d_len);
     dfree_p(g, g->d_row_ptr);
     dfree_p(g, g->d_col_ptr);
-    dfree_p(g, g->d_col_ent);
+    dfree_p(g, g->d_col_code);
+    dfree_p(g, g->d_col_len);
     g->mode = 0;
     g->S = g->max_per_ray = g->n_stored = 0;
 }
@@ -189,8 +191,8 @@ hipError_t forward_dispatch(const tsp_geometry *g, const float *rho, int batch, 
 hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, float *x,
                             int method, hipStream_t st) {
     if (method == TSP_ADJ_DETERMINISTIC)
-        return launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_ent, g->T.nr, g->T.ne, g->T.na,
-                                  y, batch, x, st);
+        return launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_code, g->d_col_len, g->T.nr,
+                                  g->T.ne, g->T.na, y, batch, x, st);
     hipError_t e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
     if (e != hipSuccess) return e;
     if (g->mode == TSP_MODE_CSR)
@@ -514,133 +516,247 @@ tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int
     return TSP_OK;
 }
 
-// Voxel-major (transposed) store: col_ptr [FV + 1] and col_ent [S], entries of
-// each (frame, voxel) key in ray order.  Built in passes over key ranges, so
-// that the temporaries (two key buffers and one value buffer, 16 bytes per
-// entry, plus the sort workspace; the sorted values land in the store itself)
-// fit the free device memory, or the cap TSP_MAX_DEVICE_BYTES; the
-// environment variable TSP_TRANSPOSE_MAX_ENTRIES caps the entries per pass
-// further.  Every pass is a stable sort of a contiguous key range, so the
-// result does not depend on the number of passes.
-tsp_status build_transpose(tsp_geometry *g, hipStream_t st) {
-    const int64_t S = g->S, FV = g->FV(), R = g->R;
+// Voxel-major (transposed) store, packed: per (frame, voxel) key the
+// (natural slot, length) of its segments in slot order, split into 64 lane
+// runs and delta-coded (see kSlotEsc); col_ptr [FV + 1] holds the offsets of
+// the keys' blocks in col_code / col_len.  The lists come from stable radix
+// sorts of the segments by key over contiguous key ranges (passes), sized so
+// that the temporaries (two key and two value buffers, 24 bytes per entry,
+// plus the sort workspace) fit the free device memory or the cap
+// TSP_MAX_DEVICE_BYTES; the environment variable TSP_TRANSPOSE_MAX_ENTRIES
+// caps the entries per pass further.  A first sweep over the passes sizes
+// every key's block; a single pass is then packed from its sorted buffers,
+// several passes are expanded and sorted once more to be packed.  Each key's
+// list is the same whatever the passes, so the store does not depend on them.
+// srow [n_slots + 1]: offsets of every natural slot's segments (exclusive
+// scan of the canonical segment counts in natural slot order).
+tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st) {
+    const int64_t S = g->S, FV = g->FV(), NS = g->rd.n_slots;
     const int nr = g->T.nr, ne = g->T.ne, na = g->T.na;
     const RayDesc &rd = g->rd;
     tsp_status s;
-    if ((s = dalloc_n(g, &g->d_col_ptr, FV + 1, "column offsets")) != TSP_OK) return s;
-    if ((s = dalloc_n(g, &g->d_col_ent, S, "voxel-major store")) != TSP_OK) return s;
-
-    const int64_t fixed = 16 * (R + 2) + 8 * scan_tmp_elems(R) + 4096;
-    int64_t cap = S;
-    size_t fr = 0, tot = 0;
-    if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-        const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
-        int64_t avail = (int64_t)fr - margin - fixed;
-        const int64_t dcap = device_cap();
-        if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - fixed);
-        cap = std::min<int64_t>(cap, avail / 17);
-    } else {
-        (void)hipGetLastError();
-    }
-    if (const char *e = std::getenv("TSP_TRANSPOSE_MAX_ENTRIES")) {
-        const long long v = std::atoll(e);
-        if (v > 0) cap = std::min<int64_t>(cap, v);
-    }
-    if (cap < 1 && S > 0) return fail(TSP_E_NOMEM, "no device memory left for the transpose");
-    cap = std::max<int64_t>(cap, 1);
-
-    // key ranges [cuts[p], cuts[p+1]) of at most cap entries each
-    std::vector<int64_t> cuts{0};
     hipError_t e = hipSuccess;
-    if (cap < S) {
-        const int shift = std::max(0, bits_for(FV) - 12);
-        const int nb = (int)((FV - 1) >> shift) + 1;
-        unsigned long long *hist = nullptr;
-        if ((s = dalloc_n(g, &hist, nb, "key histogram")) != TSP_OK) return s;
-        e = launch_zero_f32((float *)hist, 2 * (int64_t)nb, st);
-        if (e == hipSuccess)
-            e = launch_key_hist(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
-                                g->d_len, nr, ne, na, shift, nb, hist, st);
-        std::vector<unsigned long long> h((size_t)nb);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e == hipSuccess)
-            e = hipMemcpy(h.data(), hist, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost);
-        dfree(g, hist);
-        if (e != hipSuccess) return fail(TSP_E_HIP, std::string("key histogram: ") +
-                                                        hipGetErrorString(e));
-        int64_t acc = 0;
-        for (int b = 0; b < nb; b++) {
-            if ((int64_t)h[b] > cap)
-                return fail(TSP_E_NOMEM, "transpose: one key bucket exceeds the memory for a pass");
-            if (acc + (int64_t)h[b] > cap && acc > 0) {
-                cuts.push_back((int64_t)b << shift);
-                acc = 0;
-            }
-            acc += (int64_t)h[b];
-        }
-    }
-    cuts.push_back(FV);
-    const int64_t nmax = std::min<int64_t>(cap, S);
+    if ((s = dalloc_n(g, &g->d_col_ptr, FV + 1, "column offsets")) != TSP_OK) return s;
 
-    int32_t *k1 = nullptr, *k2 = nullptr, *cnt = nullptr;
-    uint64_t *v1 = nullptr;
-    int64_t *crow = nullptr, *stmp = nullptr;
+    int32_t *k1 = nullptr, *k2 = nullptr, *cnt = nullptr, *m = nullptr;
+    uint64_t *v1 = nullptr, *v2 = nullptr;
+    int64_t *crow = nullptr, *stmp = nullptr, *cptr = nullptr;
     void *ws = nullptr;
-    auto free_all = [&]() {
-        dfree(g, k1);
-        dfree(g, k2);
-        dfree(g, v1);
-        dfree(g, cnt);
-        dfree(g, crow);
-        dfree(g, stmp);
+    auto free_pass_bufs = [&]() {
+        dfree_p(g, k1);
+        dfree_p(g, k2);
+        dfree_p(g, v1);
+        dfree_p(g, v2);
         dfree(g, ws);
+        ws = nullptr;
     };
-    if ((s = dalloc_n(g, &k1, nmax, "transpose keys")) != TSP_OK ||
-        (s = dalloc_n(g, &k2, nmax, "transpose keys")) != TSP_OK ||
-        (s = dalloc_n(g, &v1, nmax, "transpose values")) != TSP_OK ||
-        (s = dalloc_n(g, &cnt, R, "transpose counts")) != TSP_OK ||
-        (s = dalloc_n(g, &crow, R + 1, "transpose offsets")) != TSP_OK ||
-        (s = dalloc_n(g, &stmp, scan_tmp_elems(R), "scan")) != TSP_OK ||
-        (s = dalloc(g, &ws, (int64_t)radix_ws_bytes(nmax), "sort workspace")) != TSP_OK) {
+    auto free_all = [&]() {
+        free_pass_bufs();
+        dfree_p(g, cnt);
+        dfree_p(g, m);
+        dfree_p(g, crow);
+        dfree_p(g, stmp);
+        dfree_p(g, cptr);
+    };
+    auto hip_fail = [&](const char *what) {
+        const std::string msg = std::string("transpose: ") + what + ": " + hipGetErrorString(e);
+        free_all();
+        return fail(TSP_E_HIP, msg);
+    };
+    if ((s = dalloc_n(g, &cnt, NS, "transpose counts")) != TSP_OK ||
+        (s = dalloc_n(g, &crow, NS + 1, "transpose offsets")) != TSP_OK ||
+        (s = dalloc_n(g, &stmp, scan_tmp_elems(std::max(NS, FV)), "scan")) != TSP_OK ||
+        (s = dalloc_n(g, &m, FV, "row counts")) != TSP_OK ||
+        (s = dalloc_n(g, &cptr, FV + 1, "pass column offsets")) != TSP_OK) {
         free_all();
         return s;
     }
-    int64_t base = 0;
+
+    // entries per pass that the free memory (and the caps) allow
+    auto pass_cap = [&]() -> int64_t {
+        int64_t cap = S;
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
+            int64_t avail = (int64_t)fr - margin - 4096;
+            const int64_t dcap = device_cap();
+            if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - 4096);
+            cap = std::min<int64_t>(cap, avail / 25);
+        } else {
+            (void)hipGetLastError();
+        }
+        if (const char *ev = std::getenv("TSP_TRANSPOSE_MAX_ENTRIES")) {
+            const long long v = std::atoll(ev);
+            if (v > 0) cap = std::min<int64_t>(cap, v);
+        }
+        return cap;
+    };
+    // key ranges [cuts[p], cuts[p+1]) of at most cap entries each, from a
+    // coarse key histogram taken once
+    const int shift = std::max(0, bits_for(FV) - 12);
+    const int nbk = (int)((FV - 1) >> shift) + 1;
+    std::vector<unsigned long long> h;
+    auto plan = [&](int64_t cap, std::vector<int64_t> &cuts) -> tsp_status {
+        cuts.assign(1, 0);
+        if (cap < 1 && S > 0) return fail(TSP_E_NOMEM, "no device memory left for the transpose");
+        if (cap < S) {
+            if (h.empty()) {
+                unsigned long long *hist = nullptr;
+                tsp_status t;
+                if ((t = dalloc_n(g, &hist, nbk, "key histogram")) != TSP_OK) return t;
+                e = launch_zero_f32((float *)hist, 2 * (int64_t)nbk, st);
+                if (e == hipSuccess)
+                    e = launch_key_hist(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                        g->d_code, g->d_len, nr, ne, na, shift, nbk, hist, st);
+                h.resize((size_t)nbk);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e == hipSuccess)
+                    e = hipMemcpy(h.data(), hist, sizeof(unsigned long long) * nbk,
+                                  hipMemcpyDeviceToHost);
+                dfree(g, hist);
+                if (e != hipSuccess) {
+                    h.clear();
+                    return fail(TSP_E_HIP, std::string("key histogram: ") + hipGetErrorString(e));
+                }
+            }
+            int64_t acc = 0;
+            for (int b = 0; b < nbk; b++) {
+                if ((int64_t)h[b] > cap)
+                    return fail(TSP_E_NOMEM,
+                                "transpose: one key bucket exceeds the memory for a pass");
+                if (acc + (int64_t)h[b] > cap && acc > 0) {
+                    cuts.push_back((int64_t)b << shift);
+                    acc = 0;
+                }
+                acc += (int64_t)h[b];
+            }
+        }
+        cuts.push_back(FV);
+        return TSP_OK;
+    };
+    // temporaries for passes of at most n entries
+    int64_t nmax = 0;
+    auto alloc_pass_bufs = [&](int64_t n) -> tsp_status {
+        nmax = n;
+        tsp_status t;
+        if ((t = dalloc_n(g, &k1, n, "transpose keys")) != TSP_OK ||
+            (t = dalloc_n(g, &k2, n, "transpose keys")) != TSP_OK ||
+            (t = dalloc_n(g, &v1, n, "transpose values")) != TSP_OK ||
+            (t = dalloc_n(g, &v2, n, "transpose values")) != TSP_OK ||
+            (t = dalloc(g, &ws, (int64_t)radix_ws_bytes(n), "sort workspace")) != TSP_OK)
+            return t;
+        return TSP_OK;
+    };
+    // one pass: the segments with keys in [lo, hi) sorted by key into `vals`,
+    // each key's list at cptr[key] .. cptr[key + 1] (relative to the pass)
     const int bits = bits_for(FV);
-    const bool one_pass = cuts.size() == 2;
-    for (size_t p = 0; p + 1 < cuts.size() && e == hipSuccess; p++) {
-        const int32_t lo = (int32_t)cuts[p], hi = (int32_t)cuts[p + 1];
-        // one pass takes every segment: its offsets are the rows of the store
-        const int64_t *rows = one_pass ? g->d_row_ptr : crow;
-        int64_t np = S;
-        if (!one_pass) {
-            e = launch_count_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
-                                   g->d_len, nr, ne, na, lo, hi, cnt, st);
-            if (e == hipSuccess) e = launch_scan_i32(cnt, R, 1, crow, stmp, st);
+    auto run_pass = [&](int32_t lo, int32_t hi, bool whole, int64_t &np,
+                        const uint64_t *&vals) -> tsp_status {
+        // a pass over every key takes every segment: srow lays it out
+        const int64_t *rows = whole ? srow : crow;
+        np = S;
+        if (!whole) {
+            e = launch_zero_f32((float *)cnt, NS, st);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(&np, crow + R, sizeof(int64_t), hipMemcpyDeviceToHost, st);
+                e = launch_count_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
+                                       g->d_len, nr, ne, na, lo, hi, cnt, st);
+            if (e == hipSuccess) e = launch_scan_i32(cnt, NS, 1, crow, stmp, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&np, crow + NS, sizeof(int64_t), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
         }
-        if (e != hipSuccess) break;
-        if (np > nmax || base + np > S) {
-            free_all();
-            return fail(TSP_E_HIP, "transpose: pass larger than planned");
-        }
-        uint64_t *dst = g->d_col_ent + base;
+        if (np > nmax) return fail(TSP_E_HIP, "transpose: pass larger than planned");
         int in_second = 0;
         e = launch_expand_range(rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_code,
                                 g->d_len, rows, nr, ne, na, lo, hi, k1, v1, st);
-        if (e == hipSuccess) e = launch_radix_sort(k1, v1, k2, dst, np, bits, ws, &in_second, st);
-        if (e == hipSuccess && !in_second) e = launch_copy_u64(v1, dst, np, st);
+        if (e == hipSuccess) e = launch_radix_sort(k1, v1, k2, v2, np, bits, ws, &in_second, st);
         if (e == hipSuccess)
-            e = launch_col_ptr_range(in_second ? k2 : k1, np, lo, hi - lo, base, g->d_col_ptr,
-                                     st);
-        base += np;
+            e = launch_col_ptr_range(in_second ? k2 : k1, np, lo, hi - lo, 0, cptr, st);
+        if (e != hipSuccess) return fail(TSP_E_HIP, hipGetErrorString(e));
+        vals = in_second ? v2 : v1;
+        return TSP_OK;
+    };
+    auto pass_entries = [&](const std::vector<int64_t> &cuts) {
+        return cuts.size() == 2 ? S : std::min<int64_t>(S, pass_cap());
+    };
+
+    // sweep 1: the rows every key takes, then the block offsets
+    std::vector<int64_t> cuts;
+    if ((s = plan(pass_cap(), cuts)) != TSP_OK ||
+        (s = alloc_pass_bufs(pass_entries(cuts))) != TSP_OK) {
+        free_all();
+        return s;
     }
+    bool whole = cuts.size() == 2;
+    int64_t total = 0, np = 0;
+    const uint64_t *vals = nullptr;
+    for (size_t p = 0; p + 1 < cuts.size(); p++) {
+        const int32_t lo = (int32_t)cuts[p], hi = (int32_t)cuts[p + 1];
+        if ((s = run_pass(lo, hi, whole, np, vals)) != TSP_OK) {
+            free_all();
+            return s;
+        }
+        total += np;
+        e = launch_pack_count(cptr + lo, vals, hi - lo, m + lo, st);
+        if (e != hipSuccess) return hip_fail("row counts");
+    }
+    if (total != S) {
+        free_all();
+        return fail(TSP_E_HIP, "transpose: entry count mismatch");
+    }
+    int64_t P = 0;
+    e = launch_scan_i32(m, FV, kWave, g->d_col_ptr, stmp, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&P, g->d_col_ptr + FV, sizeof(int64_t), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail("store offsets");
+
+    // the packed store (5 bytes per entry); a single pass keeps its sorted
+    // buffers when the store fits beside them
+    bool keep = false;
+    if (whole) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
+            const int64_t dcap = device_cap();
+            keep = (int64_t)fr - margin >= 5 * P + 4096 &&
+                   (dcap <= 0 || g->bytes + 5 * P + 4096 <= dcap);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    if (!keep) free_pass_bufs();
+    if ((s = dalloc_n(g, &g->d_col_code, P, "voxel-major codes")) != TSP_OK ||
+        (s = dalloc_n(g, &g->d_col_len, P, "voxel-major lengths")) != TSP_OK) {
+        free_all();
+        return s;
+    }
+    if (keep) {
+        e = launch_pack_fill(cptr, vals, FV, g->d_col_ptr, g->d_col_code, g->d_col_len, st);
+        if (e != hipSuccess) return hip_fail("pack");
+    } else {
+        // sweep 2: sort again, in passes that fit beside the store, and pack
+        if ((s = plan(pass_cap(), cuts)) != TSP_OK ||
+            (s = alloc_pass_bufs(pass_entries(cuts))) != TSP_OK) {
+            free_all();
+            return s;
+        }
+        whole = cuts.size() == 2;
+        for (size_t p = 0; p + 1 < cuts.size(); p++) {
+            const int32_t lo = (int32_t)cuts[p], hi = (int32_t)cuts[p + 1];
+            if ((s = run_pass(lo, hi, whole, np, vals)) != TSP_OK) {
+                free_all();
+                return s;
+            }
+            e = launch_pack_fill(cptr + lo, vals, hi - lo, g->d_col_ptr + lo, g->d_col_code,
+                                 g->d_col_len, st);
+            if (e != hipSuccess) return hip_fail("pack");
+        }
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail("pack");
     free_all();
-    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("transpose: ") + hipGetErrorString(e));
-    if (base != S) return fail(TSP_E_HIP, "transpose: entry count mismatch");
     return TSP_OK;
 }
 
@@ -803,15 +919,30 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     dfree(g, cnt_ray);
     if (e != hipSuccess) return abort_all(fail(TSP_E_HIP, hipGetErrorString(e)));
-    free_tmp();
-    dfree(g, scan_tmp);
-    scan_tmp = nullptr;
 
     if (want_csc) {
-        if ((s = build_transpose(g, st)) != TSP_OK) {
+        // segment offsets in natural slot order, for the transpose
+        int64_t *srow = nullptr;
+        if ((s = dalloc_n(g, &srow, ns + 1, "slot offsets")) != TSP_OK) return abort_all(s);
+        e = launch_scan_i32(seg_nat, ns, 1, srow, scan_tmp, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        free_tmp();
+        dfree(g, scan_tmp);
+        scan_tmp = nullptr;
+        if (e != hipSuccess) {
+            dfree(g, srow);
+            return abort_all(fail(TSP_E_HIP, hipGetErrorString(e)));
+        }
+        s = build_transpose(g, srow, st);
+        dfree(g, srow);
+        if (s != TSP_OK) {
             release_stores(g);
             return s;
         }
+    } else {
+        free_tmp();
+        dfree(g, scan_tmp);
+        scan_tmp = nullptr;
     }
     g->mode = TSP_MODE_CSR;
     return TSP_OK;

@@ -146,14 +146,73 @@ __global__ __launch_bounds__(256) void k_tile_y(const RayDesc rd, const float *_
     yt[s] = v;
 }
 
-// Deterministic adjoint: one wavefront per voxel of the voxel-major store,
-// lanes stride its entries (eight per lane in flight), fixed butterfly sum.
+// Deterministic adjoint from the packed voxel-major store.
+//
+// Inclusive prefix sum over the 64 lanes of a wavefront: Hillis-Steele
+// steps within rows of 16 lanes (DPP row shifts), then the broadcasts of
+// lane 15 of each row to the next (rows 1 and 3) and of lane 31 to rows 2
+// and 3.  Lanes that a step gives no source (the first k of a row for a
+// shift by k, the rows outside the mask of a broadcast) keep the old value
+// 0, the identity of the sum.  Every lane must be active.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
+// N rows of a packed voxel-major list (lane l: entry l of each row) into
+// the lane sums; `run` is the slot before the first row.
+template <int NB, int N>
+__device__ __forceinline__ void adj_rows(const uint8_t *__restrict__ cp,
+                                         const float *__restrict__ lp, int lane, uint32_t smax,
+                                         const typename YVec<NB>::T *__restrict__ yt,
+                                         uint32_t &run, float *acc) {
+    int cd[N];
+    float l[N];
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        cd[u] = __builtin_nontemporal_load(cp + u * kWave);
+        l[u] = __builtin_nontemporal_load(lp + u * kWave);
+    }
+    uint32_t sl[N];
+#pragma unroll
+    for (int u = 0; u < N; u++)
+        sl[u] = wave_incl_sum(cd[u] == kSlotEsc ? __float_as_uint(l[u]) : (uint32_t)cd[u]);
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        const uint32_t tot = __builtin_amdgcn_readlane(sl[u], 63);
+        sl[u] += run;
+        run += tot;
+    }
+#pragma unroll
+    for (int u = 0; u < N; u++) {
+        const bool ok = cd[u] != kSlotEsc && l[u] != 0.0f;  // escapes, padding: nothing
+        const uint32_t si = sl[u] < smax ? sl[u] : smax;
+        const typename YVec<NB>::T yv = yt[si];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const float t = fmaf(l[u], YVec<NB>::get(yv, b), acc[b]);
+            acc[b] = ok ? t : acc[b];
+        }
+    }
+}
+
 // Keys run over object frames, then voxels in store-key order; x is
-// [nf][V] per object (nf = 1 for a static object).
+// [nf][V] per object (nf = 1 for a static object).  One wavefront per key
+// takes the key's packed list a row of 64 entries at a time (lane l entry
+// l), eight rows in flight: each lane's slot is the running slot before the
+// row plus the prefix sum of the row's increases (escapes carry theirs in
+// the length slot).  A fixed butterfly adds the 64 lane sums, so the order
+// never depends on timing: x is bitwise reproducible.
 template <int NB>
-__global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_ptr,
-                                                  const uint64_t *__restrict__ col_ent, int nr,
-                                                  int ne, int na, int nf,
+__global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_base,
+                                                  const uint8_t *__restrict__ code,
+                                                  const float *__restrict__ len, int nr, int ne,
+                                                  int na, int nf, int64_t n_slots,
                                                   const typename YVec<NB>::T *__restrict__ yt,
                                                   int nb, float *__restrict__ x) {
     constexpr int UNR = 8;
@@ -167,35 +226,29 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
     const int64_t nbk = gridDim.x, full = nbk / (8 * kChunk) * (8 * kChunk);
     const int64_t bx = blockIdx.x, q = bx / 8;
     const int64_t lb = (bx < full) ? ((q / kChunk) * 8 + bx % 8) * kChunk + q % kChunk : bx;
-    const int64_t key = (lb * 256 + threadIdx.x) >> 6;
+    // the key is uniform over the wavefront: keep it (and the list bounds,
+    // the loop and the running slot) in scalar registers
+    const int64_t key = lb * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    if (key >= FV) return;  // uniform over the wavefront
-    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+    if (key >= FV) return;
+    const int64_t base = col_base[key];
+    const int nrow = (int)((col_base[key + 1] - base) >> 6);
     const int64_t f = key / V;
     const int64_t v = f * V + store_voxel(key - f * V, nr, ne, na);
+    const uint8_t *cp = code + base + lane;
+    const float *lp = len + base + lane;
+    const uint32_t smax = (uint32_t)(n_slots - 1);
     float acc[NB];
 #pragma unroll
     for (int b = 0; b < NB; b++) acc[b] = 0.0f;
-    int64_t k = lo + lane;
-    for (; k + (UNR - 1) * kWave < hi; k += UNR * kWave) {
-        uint64_t e[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; u++) e[u] = __builtin_nontemporal_load(col_ent + k + kWave * u);
-#pragma unroll
-        for (int u = 0; u < UNR; u++) {
-            const typename YVec<NB>::T yv = yt[(uint32_t)e[u]];
-            const float l = __uint_as_float((uint32_t)(e[u] >> 32));
-#pragma unroll
-            for (int b = 0; b < NB; b++) acc[b] = fmaf(l, YVec<NB>::get(yv, b), acc[b]);
-        }
-    }
-    for (; k < hi; k += kWave) {
-        const uint64_t e = __builtin_nontemporal_load(col_ent + k);
-        const typename YVec<NB>::T yv = yt[(uint32_t)e];
-        const float l = __uint_as_float((uint32_t)(e >> 32));
-#pragma unroll
-        for (int b = 0; b < NB; b++) acc[b] = fmaf(l, YVec<NB>::get(yv, b), acc[b]);
-    }
+    uint32_t run = 0;
+    int r = 0;
+    for (; r + UNR <= nrow; r += UNR)
+        adj_rows<NB, UNR>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt, run,
+                          acc);
+    for (; r < nrow; r++)
+        adj_rows<NB, 1>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt, run,
+                        acc);
 #pragma unroll
     for (int b = 0; b < NB; b++) {
 #pragma unroll
@@ -334,21 +387,22 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
 }
 
 template <int NB>
-static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_ptr,
-                                const uint64_t *col_ent, int nr, int ne, int na, const float *y,
+static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
+                                const float *len, int nr, int ne, int na, const float *y,
                                 int nb, float *x, void *yt, hipStream_t st) {
     using T = typename YVec<NB>::T;
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     hipLaunchKernelGGL(k_tile_y<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, y,
                        nb, (T *)yt);
     hipLaunchKernelGGL(k_adj_csc<NB>, dim3(blocks_for(FV * kWave, 256)), dim3(256), 0, st,
-                       col_ptr, col_ent, nr, ne, na, rd.n_obj_frames, (const T *)yt, nb, x);
+                       col_base, code, len, nr, ne, na, rd.n_obj_frames, rd.n_slots,
+                       (const T *)yt, nb, x);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
-                              int nr, int ne, int na, const float *y, int B, float *x,
-                              hipStream_t st) {
+hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
+                              const float *len, int nr, int ne, int na, const float *y, int B,
+                              float *x, hipStream_t st) {
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     const int width = B >= 3 ? 4 : B;
     void *yt = nullptr;
@@ -359,11 +413,11 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const u
         const float *yy = y + (int64_t)b0 * rd.R;
         float *xx = x + (int64_t)b0 * FV;
         if (nb == 1)
-            e = adj_csc_chunk<1>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<1>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
         else if (nb == 2)
-            e = adj_csc_chunk<2>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<2>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
         else
-            e = adj_csc_chunk<4>(rd, col_ptr, col_ent, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<4>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
     }
     const hipError_t f = hipFreeAsync(yt, st);
     return e != hipSuccess ? e : f;

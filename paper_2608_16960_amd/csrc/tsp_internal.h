@@ -125,6 +125,16 @@ __device__ __forceinline__ float decode_entry(int c, float l, int32_t &v, int na
     return esc ? 0.0f : l;
 }
 
+// Voxel-major store entries: a float32 length and a one-byte code.  Each
+// (frame, voxel) list is sorted by natural slot; the code is the slot's
+// increase over the previous entry's (0 ... 254) or kSlotEsc, an entry whose
+// length slot carries the increase instead (uint32 bits) and that contributes
+// nothing.  Every list opens with an escape (increase from slot 0) and is
+// padded to whole rows of 64 entries with code 0, length 0; a wavefront takes
+// a row at a time, lane l entry l, and rebuilds the slots by a prefix sum.
+constexpr int kSlotEsc = 255;
+constexpr int kSlotMaxStep = 254;
+
 // Ray-major sliced store: slice s holds 64 rays (one per lane); segment j of
 // lane l sits at slice_ptr[s] + 256 (j / 4) + 4 l + (j % 4), so each lane
 // reads four consecutive segments with one 16-byte load and a wavefront reads
@@ -199,8 +209,9 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
 size_t radix_ws_bytes(int64_t n);
 // Transpose in passes over key ranges [lo, hi) (bounded temporary memory):
 // coarse key histogram (bucket = key >> shift, nb <= key_hist_buckets()),
-// per-ray counts in a range, compacted expansion in ray order, and the
-// range's column offsets with a base.
+// counts in a range per natural slot (cnt_ray: [n_slots], zeroed first),
+// compacted expansion in natural slot order (crow: [n_slots + 1] offsets),
+// and the range's column offsets with a base.
 int key_hist_buckets();
 hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                            const int64_t *slice_ptr, const uint8_t *code, const float *len,
@@ -217,6 +228,13 @@ hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int
 hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
                                 int64_t base, int64_t *col_ptr, hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st);
+// Packing of the sorted voxel-major entries (col_ptr [nkeys + 1], ent =
+// slot | length bits << 32): per key the rows of 64 entries its packed list
+// takes, then the packed lists at base[key] (base = exclusive scan of 64 rows).
+hipError_t launch_pack_count(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
+                             int32_t *rows, hipStream_t st);
+hipError_t launch_pack_fill(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
+                            const int64_t *base, uint8_t *code, float *len, hipStream_t st);
 
 // ---- launchers (tsp_apply.hip) ----
 // vf: voxels of one object frame; rho / x hold rd.n_obj_frames frames per object.
@@ -224,13 +242,14 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
                                const int64_t *slice_ptr, const int32_t *slice_len,
                                const uint8_t *code, const float *len, const float *rho, int B,
                                int64_t vf, int na, int nena, float *y, hipStream_t st);
-// col_ptr is indexed by object frame, then the voxel's store key; each entry
-// packs (natural slot of the ray, length bits) as low / high 32 bits; x is
-// written in (frame, r, e, a) order.  y is first copied into slot order
-// (batch interleaved) in a stream-ordered temporary.
-hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_ptr, const uint64_t *col_ent,
-                              int nr, int ne, int na, const float *y, int B, float *x,
-                              hipStream_t st);
+// col_base is indexed by object frame, then the voxel's store key: the
+// packed voxel-major store (codes and lengths, see kSlotEsc) of key k spans
+// entries col_base[k] .. col_base[k+1]; x is written in (frame, r, e, a)
+// order.  y is first copied into slot order (batch interleaved) in a
+// stream-ordered temporary.
+hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
+                              const float *len, int nr, int ne, int na, const float *y, int B,
+                              float *x, hipStream_t st);
 hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *cnt_sorted, const int64_t *slice_ptr,
                                  const int32_t *slice_len, const uint8_t *code, const float *len,

@@ -209,7 +209,8 @@ __global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_
         if (h[i]) atomicAdd(hist + i, (unsigned long long)h[i]);
 }
 
-// Per ray: number of its segments whose key lies in [lo, hi).
+// Per natural slot of a ray: number of its segments whose key lies in
+// [lo, hi) (slots without a ray are left as they are: zero them first).
 __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int32_t *perm,
                                                       const int32_t *cnt_sorted,
                                                       const int64_t *slice_ptr,
@@ -224,6 +225,7 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
     const int c = cnt_sorted[slot];
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
+    const int64_t nslot = natural_slot(rd, slot, r);
     int n = 0;
     int32_t v = 0;
     for (int j = 0; j < c; j++) {
@@ -234,11 +236,13 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
         const int32_t k = seg_key(rd, r, v, nr, ne, na);
         n += (k >= lo && k < hi);
     }
-    cnt_ray[r] = n;
+    cnt_ray[nslot] = n;
 }
 
-// Segments with keys in [lo, hi), compacted in ray order (ray r's at
-// crow[r] ...), as (key, natural slot | length bits << 32) for the sort.
+// Segments with keys in [lo, hi), compacted in natural slot order (the ray
+// in natural slot s writes at crow[s] ...), as (key, natural slot | length
+// bits << 32) for the sort: every key's entries then come out of the stable
+// sort in increasing slot order.
 __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const int32_t *perm,
                                                        const int32_t *cnt_sorted,
                                                        const int64_t *slice_ptr,
@@ -254,8 +258,9 @@ __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const in
     const int c = cnt_sorted[slot];
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
-    const uint64_t ns = (uint64_t)(uint32_t)natural_slot(rd, slot, r);
-    int64_t dst = crow[r];
+    const int64_t nslot = natural_slot(rd, slot, r);
+    const uint64_t ns = (uint64_t)(uint32_t)nslot;
+    int64_t dst = crow[nslot];
     int32_t v = 0;
     for (int j = 0; j < c; j++) {
         const int64_t i = sell_index(base, lane, j);
@@ -284,6 +289,75 @@ __global__ void k_col_ptr_range(const int32_t *keys, int64_t n, int64_t key0, in
         else hi = mid;
     }
     col_ptr[v] = base + lo;
+}
+
+// Packing of the sorted voxel-major lists (one wavefront per key).  Entry i
+// of a list needs an escape before it when it is the list's first or when
+// its slot increase over entry i - 1 exceeds kSlotMaxStep.
+__device__ __forceinline__ bool needs_escape(int64_t i, int64_t lo, uint32_t slot,
+                                             uint32_t prev) {
+    return i == lo || slot - prev > (uint32_t)kSlotMaxStep;
+}
+
+// Rows of 64 entries that each key's packed list takes (escapes included).
+__global__ __launch_bounds__(256) void k_pack_count(const int64_t *col_ptr, const uint64_t *ent,
+                                                     int64_t nkeys, int32_t *rows) {
+    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (key >= nkeys) return;  // uniform over the wavefront
+    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+    int64_t n = 0;
+    for (int64_t i = lo + lane; i < hi; i += kWave) {
+        const uint32_t slot = (uint32_t)ent[i];
+        const uint32_t prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
+        n += needs_escape(i, lo, slot, prev) ? 2 : 1;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, kWave);
+    if (lane == 0) rows[key] = (int32_t)((n + kWave - 1) / kWave);
+}
+
+// The packed list of each key at base[key] ... base[key + 1], padded with
+// code 0, length 0.  Entries are taken 64 at a time; an entry's position is
+// its index plus the escapes written up to it (ballot and popcount).
+__global__ __launch_bounds__(256) void k_pack_fill(const int64_t *col_ptr, const uint64_t *ent,
+                                                    int64_t nkeys, const int64_t *base,
+                                                    uint8_t *code, float *len) {
+    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (key >= nkeys) return;  // uniform over the wavefront
+    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+    const int64_t p0 = base[key], p1 = base[key + 1];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t written = 0;
+    for (int64_t c = lo; c < hi; c += kWave) {  // uniform over the wavefront
+        const int64_t i = c + lane;
+        const bool valid = i < hi;
+        uint32_t slot = 0, prev = 0;
+        float l = 0.0f;
+        if (valid) {
+            const uint64_t e = ent[i];
+            slot = (uint32_t)e;
+            l = __uint_as_float((uint32_t)(e >> 32));
+            prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
+        }
+        const bool esc = valid && needs_escape(i, lo, slot, prev);
+        const uint64_t eb = __ballot(esc);
+        const int64_t p = p0 + written + lane + __popcll(eb & below) + (esc ? 1 : 0);
+        if (esc) {
+            code[p - 1] = (uint8_t)kSlotEsc;
+            len[p - 1] = __uint_as_float(slot - prev);
+        }
+        if (valid) {
+            code[p] = esc ? (uint8_t)0 : (uint8_t)(slot - prev);
+            len[p] = l;
+        }
+        written += __popcll(__ballot(valid)) + __popcll(eb);
+    }
+    for (int64_t q = p0 + written + lane; q < p1; q += kWave) {
+        code[q] = 0;
+        len[q] = 0.0f;
+    }
 }
 
 __global__ void k_copy_u64(const uint64_t *s, uint64_t *d, int64_t n) {
@@ -492,6 +566,22 @@ hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t k
                                 int64_t base, int64_t *col_ptr, hipStream_t st) {
     hipLaunchKernelGGL(k_col_ptr_range, dim3(blocks_for(nk + 1, 256)), dim3(256), 0, st,
                        sorted_keys, n, key0, nk, base, col_ptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_count(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
+                             int32_t *m, hipStream_t st) {
+    if (nkeys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_count, dim3(blocks_for(nkeys * kWave, 256)), dim3(256), 0, st,
+                       col_ptr, ent, nkeys, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_fill(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
+                            const int64_t *base, uint8_t *code, float *len, hipStream_t st) {
+    if (nkeys <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_fill, dim3(blocks_for(nkeys * kWave, 256)), dim3(256), 0, st,
+                       col_ptr, ent, nkeys, base, code, len);
     return hipGetLastError();
 }
 
