@@ -46,6 +46,10 @@ def _args():
                    help="after timing, run a plain 1 GiB device copy (counter calibration)")
     p.add_argument("--large-only", action="store_true",
                    help="only the Large on-the-fly forward and adjoint (for counter runs)")
+    p.add_argument("--extras", default="all",
+                   help="comma-separated extra workloads after the Medium line (onthefly_large, "
+                        "stored_large, diff_csr, explicit_rays_medium, attenuated_medium, "
+                        "learned_warm_start) or 'all'")
     p.add_argument("--cpu-views", type=int, default=30,
                    help="views of the workload the CPU oracle traces (bounded sample)")
     return p.parse_args()
@@ -201,8 +205,8 @@ def extra_large_onthefly():
 
 def extra_large_csr(reps=5):
     """Large workload from stored segment lists: on one MI355X the ray-major
-    and voxel-major stores (about 8 bytes per segment each, 8.46e9 segments)
-    fit in HBM, the transpose built in passes that fit the rest; batch 4,
+    and voxel-major stores (about 5 bytes per segment each, 8.46e9 segments)
+    fit in HBM, the transpose sorted in passes that fit the rest; batch 4,
     deterministic adjoint."""
     import torch
 
@@ -463,18 +467,19 @@ def main():
     if not a.quick:
         del P
         torch.cuda.empty_cache()
-        _log("large on-the-fly")
-        line["onthefly_large"] = extra_large_onthefly()
-        _log("large from stored lists")
-        line["stored_large"] = extra_large_csr()
-        _log("differentiation workload")
-        line["diff_csr"] = extra_diff_csr()
-        _log("explicit rays")
-        line["explicit_rays_medium"] = extra_explicit_medium()
-        _log("attenuated model")
-        line["attenuated_medium"] = extra_atten_medium()
-        _log("learned warm start")
-        line["learned_warm_start"] = extra_learned()
+        extras = [("onthefly_large", "large on-the-fly", extra_large_onthefly),
+                  ("stored_large", "large from stored lists", extra_large_csr),
+                  ("diff_csr", "differentiation workload", extra_diff_csr),
+                  ("explicit_rays_medium", "explicit rays", extra_explicit_medium),
+                  ("attenuated_medium", "attenuated model", extra_atten_medium),
+                  ("learned_warm_start", "learned warm start", extra_learned)]
+        want = None if a.extras == "all" else set(a.extras.split(","))
+        if want is not None and not want <= {k for k, _, _ in extras}:
+            raise SystemExit(f"unknown extras: {sorted(want - {k for k, _, _ in extras})}")
+        for key, what, fn in extras:
+            if want is None or key in want:
+                _log(what)
+                line[key] = fn()
     if not a.no_cpu_baseline:
         _log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_views)

@@ -572,15 +572,16 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
         return s;
     }
 
-    // entries per pass that the free memory (and the caps) allow
-    auto pass_cap = [&]() -> int64_t {
+    // entries per pass that the free memory (and the caps) allow, keeping
+    // `reserve` bytes aside
+    auto pass_cap = [&](int64_t reserve) -> int64_t {
         int64_t cap = S;
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
             const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
-            int64_t avail = (int64_t)fr - margin - 4096;
+            int64_t avail = (int64_t)fr - margin - 4096 - reserve;
             const int64_t dcap = device_cap();
-            if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - 4096);
+            if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - 4096 - reserve);
             cap = std::min<int64_t>(cap, avail / 25);
         } else {
             (void)hipGetLastError();
@@ -592,13 +593,14 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
         return cap;
     };
     // key ranges [cuts[p], cuts[p+1]) of at most cap entries each, from a
-    // coarse key histogram taken once
+    // coarse key histogram taken once; TSP_E_NOMEM (not reported) when one
+    // bucket of the histogram holds more than cap entries
     const int shift = std::max(0, bits_for(FV) - 12);
     const int nbk = (int)((FV - 1) >> shift) + 1;
     std::vector<unsigned long long> h;
     auto plan = [&](int64_t cap, std::vector<int64_t> &cuts) -> tsp_status {
         cuts.assign(1, 0);
-        if (cap < 1 && S > 0) return fail(TSP_E_NOMEM, "no device memory left for the transpose");
+        if (cap < 1 && S > 0) return TSP_E_NOMEM;
         if (cap < S) {
             if (h.empty()) {
                 unsigned long long *hist = nullptr;
@@ -621,9 +623,7 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
             }
             int64_t acc = 0;
             for (int b = 0; b < nbk; b++) {
-                if ((int64_t)h[b] > cap)
-                    return fail(TSP_E_NOMEM,
-                                "transpose: one key bucket exceeds the memory for a pass");
+                if ((int64_t)h[b] > cap) return TSP_E_NOMEM;
                 if (acc + (int64_t)h[b] > cap && acc > 0) {
                     cuts.push_back((int64_t)b << shift);
                     acc = 0;
@@ -677,16 +677,31 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
         vals = in_second ? v2 : v1;
         return TSP_OK;
     };
-    auto pass_entries = [&](const std::vector<int64_t> &cuts) {
-        return cuts.size() == 2 ? S : std::min<int64_t>(S, pass_cap());
+    // plan the passes and allocate their buffers, keeping `reserve` bytes free
+    std::vector<int64_t> cuts;
+    auto plan_passes = [&](int64_t reserve) -> tsp_status {
+        const int64_t cap = pass_cap(reserve);
+        tsp_status t = plan(cap, cuts);
+        if (t != TSP_OK) return t;
+        return alloc_pass_bufs(cuts.size() == 2 ? S : std::min<int64_t>(S, cap));
     };
 
-    // sweep 1: the rows every key takes, then the block offsets
-    std::vector<int64_t> cuts;
-    if ((s = plan(pass_cap(), cuts)) != TSP_OK ||
-        (s = alloc_pass_bufs(pass_entries(cuts))) != TSP_OK) {
+    // sweep 1: the rows every key takes, then the block offsets.  The passes
+    // leave room for the largest store the lists can need (each key's rows
+    // hold at most twice its entries plus 63 of padding), so that a second
+    // sweep can reuse them; without that room, plan for the sort alone.
+    const int64_t store_bound = 5 * (2 * S + 63 * FV);
+    s = plan_passes(store_bound);
+    if (s == TSP_E_NOMEM) {
+        free_pass_bufs();
+        g_err.clear();
+        s = plan_passes(0);
+    }
+    if (s != TSP_OK) {
         free_all();
-        return s;
+        return s == TSP_E_NOMEM && g_err.empty()
+                   ? fail(TSP_E_NOMEM, "transpose: one key bucket exceeds the memory for a pass")
+                   : s;
     }
     bool whole = cuts.size() == 2;
     int64_t total = 0, np = 0;
@@ -712,37 +727,43 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail("store offsets");
 
-    // the packed store (5 bytes per entry); a single pass keeps its sorted
-    // buffers when the store fits beside them
-    bool keep = false;
-    if (whole) {
+    // the packed store (5 bytes per entry), beside the pass buffers when it
+    // fits there
+    bool fits = false;
+    {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
             const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
             const int64_t dcap = device_cap();
-            keep = (int64_t)fr - margin >= 5 * P + 4096 &&
+            fits = (int64_t)fr - margin >= 5 * P + 4096 &&
                    (dcap <= 0 || g->bytes + 5 * P + 4096 <= dcap);
         } else {
             (void)hipGetLastError();
         }
     }
-    if (!keep) free_pass_bufs();
+    if (!fits) free_pass_bufs();
     if ((s = dalloc_n(g, &g->d_col_code, P, "voxel-major codes")) != TSP_OK ||
         (s = dalloc_n(g, &g->d_col_len, P, "voxel-major lengths")) != TSP_OK) {
         free_all();
         return s;
     }
-    if (keep) {
+    if (whole && fits) {
+        // the single pass's sorted lists are still there
         e = launch_pack_fill(cptr, vals, FV, g->d_col_ptr, g->d_col_code, g->d_col_len, st);
         if (e != hipSuccess) return hip_fail("pack");
     } else {
-        // sweep 2: sort again, in passes that fit beside the store, and pack
-        if ((s = plan(pass_cap(), cuts)) != TSP_OK ||
-            (s = alloc_pass_bufs(pass_entries(cuts))) != TSP_OK) {
-            free_all();
-            return s;
+        // sweep 2: sort again and pack, in the same passes or, when the
+        // buffers had to go, in passes that fit beside the store
+        if (!fits) {
+            if ((s = plan_passes(0)) != TSP_OK) {
+                free_all();
+                return s == TSP_E_NOMEM && g_err.empty()
+                           ? fail(TSP_E_NOMEM,
+                                  "transpose: one key bucket exceeds the memory for a pass")
+                           : s;
+            }
+            whole = cuts.size() == 2;
         }
-        whole = cuts.size() == 2;
         for (size_t p = 0; p + 1 < cuts.size(); p++) {
             const int32_t lo = (int32_t)cuts[p], hi = (int32_t)cuts[p + 1];
             if ((s = run_pass(lo, hi, whole, np, vals)) != TSP_OK) {
