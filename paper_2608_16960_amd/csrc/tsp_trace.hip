@@ -247,6 +247,25 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
         if (b < nb) y[b * rd.R + ray] = vis.acc[b];
 }
 
+// Lanes l and l + K (bit K of l clear, K <= 8: both in one row of 16) that
+// hold the same voxel (v >= 0) add their values in lane l; lane l + K drops
+// out (v = -1).  Every lane of the wavefront must be active.
+template <int K, int NB>
+__device__ __forceinline__ void merge_pairs(int &v, float *val, int lane) {
+    const int up = __builtin_amdgcn_update_dpp(-1, v, 0x100 + K, 0xf, 0xf, false);  // row_shl:K
+    const int dn = __builtin_amdgcn_update_dpp(-1, v, 0x110 + K, 0xf, 0xf, false);  // row_shr:K
+    const bool low = (lane & K) == 0;
+    const bool take = low && v >= 0 && up == v;
+    const bool give = !low && v >= 0 && dn == v;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const float t = __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(val[b]), 0x100 + K, 0xf, 0xf, false));
+        if (take) val[b] += t;
+    }
+    if (give) v = -1;
+}
+
 // On-the-fly adjoint into x ([V] for one object, voxel-major [V][4] for a
 // batch).  The 256 rays of a window cross largely the same voxels, so the
 // workgroup first adds its contributions in a hash table in LDS (open
@@ -255,7 +274,12 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
 // flush issues global atomics, one per distinct voxel and object.  The rays
 // advance kOtfEvents boundary events between workgroup barriers; at a barrier
 // the table is flushed once it is more than half full, and after the last ray
-// ends.  An insertion that finds no slot within kOtfProbes probes goes
+// ends.  Before inserting, the lanes of neighbouring rays that reached the
+// same voxel in the same event add their values in registers (pairs at lane
+// distance 1, 2, 4, 8 through DPP row shifts), which removes about half of
+// the LDS atomics and most of their same-address serialisation; a slot is
+// first looked up with a plain LDS read and claimed with a CAS only when
+// empty.  An insertion that finds no slot within kOtfProbes probes goes
 // straight to a global atomic, so a crowded table costs speed, never
 // correctness.
 constexpr int kOtfEvents = 16;
@@ -305,23 +329,41 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                                  (int64_t)D.nr * D.ne * D.na);
     }
     __syncthreads();
+    const int lane = threadIdx.x & 63;
     for (;;) {
-        for (int k = 0; k < kOtfEvents && alive; k++) {
-            int v;
-            double l;
-            const bool seg = w.step(T, v, l);
-            alive = !w.done();
-            if (!seg) continue;
-            v += fb;
-            const float lf = (float)l;
+        for (int k = 0; k < kOtfEvents; k++) {
+            if (__ballot(alive) == 0) break;  // uniform over the wavefront
+            int v = -1;
+            float lf = 0.0f;
+            if (alive) {
+                int vv;
+                double l;
+                const bool seg = w.step(T, vv, l);
+                alive = !w.done();
+                if (seg) {
+                    v = vv + fb;
+                    lf = (float)l;
+                }
+            }
+            float val[NB];
+#pragma unroll
+            for (int b = 0; b < NB; b++) val[b] = lf * yv[b];
+            merge_pairs<1, NB>(v, val, lane);
+            merge_pairs<2, NB>(v, val, lane);
+            merge_pairs<4, NB>(v, val, lane);
+            merge_pairs<8, NB>(v, val, lane);
+            if (v < 0) continue;
             unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
             bool done = false;
             for (int p = 0; p < kOtfProbes; p++) {
-                const int key = atomicCAS(hkey + h, -1, v);
-                if (key == -1) atomicAdd(&fill, 1);
+                int key = __hip_atomic_load(hkey + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (key == -1) {
+                    key = atomicCAS(hkey + h, -1, v);
+                    if (key == -1) atomicAdd(&fill, 1);
+                }
                 if (key == -1 || key == v) {
 #pragma unroll
-                    for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, lf * yv[b]);
+                    for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, val[b]);
                     done = true;
                     break;
                 }
@@ -330,7 +372,7 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
             if (!done) {
 #pragma unroll
                 for (int b = 0; b < NB; b++)
-                    if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, lf * yv[b]);
+                    if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, val[b]);
             }
         }
         __syncthreads();  // every insertion of this round has landed
