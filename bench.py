@@ -467,12 +467,15 @@ def main():
     if not a.quick:
         del P
         torch.cuda.empty_cache()
-        extras = [("onthefly_large", "large on-the-fly", extra_large_onthefly),
-                  ("stored_large", "large from stored lists", extra_large_csr),
-                  ("diff_csr", "differentiation workload", extra_diff_csr),
+        # the Large workloads last: device memory that a process has just
+        # released takes the driver noticeably longer to hand out again, which
+        # would show in the trace times of whatever follows them
+        extras = [("diff_csr", "differentiation workload", extra_diff_csr),
                   ("explicit_rays_medium", "explicit rays", extra_explicit_medium),
                   ("attenuated_medium", "attenuated model", extra_atten_medium),
-                  ("learned_warm_start", "learned warm start", extra_learned)]
+                  ("learned_warm_start", "learned warm start", extra_learned),
+                  ("onthefly_large", "large on-the-fly", extra_large_onthefly),
+                  ("stored_large", "large from stored lists", extra_large_csr)]
         want = None if a.extras == "all" else set(a.extras.split(","))
         if want is not None and not want <= {k for k, _, _ in extras}:
             raise SystemExit(f"unknown extras: {sorted(want - {k for k, _, _ in extras})}")
