@@ -2,6 +2,7 @@
 
     python -m paper_2608_16960_amd.profiling FETCH_DIR WRITE_DIR BYTES_JSON OUT_TXT
     python -m paper_2608_16960_amd.profiling valu PMC_DIR STATS_DIR OUT_TXT
+    python -m paper_2608_16960_amd.profiling occupancy PMC_DIR OUT_TXT KERNEL...
 
 FETCH_DIR / WRITE_DIR hold the counter_collection CSV of a `rocprofv3 --pmc
 FETCH_SIZE` and a `--pmc WRITE_SIZE` run of `bench.py --calib-copy`; each
@@ -145,9 +146,53 @@ def main_valu(argv):
             f.write(f"# {k}: {v['ns'] / 1e6:.2f} ms, {v['tflops']:.2f} TFLOP/s FP64; {cs}\n")
 
 
+def _kernel_resources(pmc_dir, kernel):
+    """(VGPRs, AGPRs, LDS bytes, workgroup size) of `kernel` from a counter_collection CSV."""
+    path = glob.glob(os.path.join(pmc_dir, "*counter_collection.csv"))[0]
+    for r in csv.DictReader(open(path)):
+        if _match(r["Kernel_Name"], kernel):
+            return (int(r["VGPR_Count"]), int(r.get("Accum_VGPR_Count") or 0),
+                    int(r["LDS_Block_Size"]), int(r["Workgroup_Size"]))
+    return None
+
+
+def theoretical_waves_per_cu(vgpr, agpr, lds, wg):
+    """Resident wavefronts per CU that registers and static LDS allow.  The
+    counter CSV gives VGPRs in units of two (half of the allocation in the
+    code object), so a SIMD holds 256 // (VGPRs + AGPRs) of them, at most 8;
+    a CU has 4 SIMDs and 160 KiB of LDS (dynamic LDS is not in the CSV)."""
+    regs = max(1, vgpr + agpr)
+    per_simd = min(8, 256 // regs)
+    waves_wg = max(1, wg // 64)
+    by_regs = 4 * per_simd
+    if lds <= 0:
+        return by_regs
+    by_lds = (160 * 1024 // lds) * waves_wg
+    return min(by_regs, by_lds)
+
+
+def main_occupancy(argv):
+    pmc_dir, out_txt, *kernels = argv
+    with open(out_txt, "a") as f:
+        f.write("\n| kernel | VGPRs (CSV units) | AGPRs | static LDS bytes / workgroup | workgroup | "
+                "resident waves per CU allowed (registers, static LDS) | MeanOccupancyPerCU (waves) "
+                "| OccupancyPercent (of 32 waves) |\n|---|---|---|---|---|---|---|---|\n")
+        for k in kernels:
+            c = _per_dispatch(pmc_dir, k)
+            res = _kernel_resources(pmc_dir, k)
+            if not c or res is None:
+                continue
+            th = theoretical_waves_per_cu(*res)
+            f.write(f"| `{k}` | {res[0]} | {res[1]} | {res[2]} | {res[3]} | {th} | "
+                    f"{c.get('MeanOccupancyPerCU', float('nan')):.1f} | "
+                    f"{c.get('OccupancyPercent', float('nan')):.1f}% |\n")
+
+
 def main(argv):
     if argv and argv[0] == "valu":
         return main_valu(argv[1:])
+    if argv and argv[0] == "occupancy":
+        return main_occupancy(argv[1:])
     fetch_dir, write_dir, bench_json, out_txt = argv
     s = summarise(fetch_dir, write_dir)
     algo = {}
