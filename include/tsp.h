@@ -73,7 +73,7 @@ typedef enum tsp_status {
     TSP_E_NOMEM = 2,       /* device allocation failed or exceeds TSP_MAX_DEVICE_BYTES */
     TSP_E_HIP = 3,         /* a HIP runtime call failed (message carries the HIP error) */
     TSP_E_STATE = 4,       /* call not valid in the geometry's state (e.g. forward before trace) */
-    TSP_E_UNSUPPORTED = 5  /* combination not implemented (e.g. deterministic adjoint on the fly) */
+    TSP_E_UNSUPPORTED = 5  /* combination not implemented (e.g. object frames on explicit rays) */
 } tsp_status;
 
 /* tsp_trace modes */
@@ -226,9 +226,19 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
  * Adjoint: x[b][f][v] = sum over all segments in voxel v of rays of views in
  * object frame f of len * y[b][ray].
  * y: device float32 [batch][R]; x: device float32 [batch][F][V], overwritten.
- * method TSP_ADJ_DETERMINISTIC (CSR mode with the transposed store:
- * bitwise reproducible) or TSP_ADJ_ATOMIC (CSR or on-the-fly mode).
- * TSP_E_UNSUPPORTED for a deterministic adjoint without a transposed store.
+ * method TSP_ADJ_DETERMINISTIC (bitwise reproducible) or TSP_ADJ_ATOMIC.
+ * The deterministic adjoint reads the transposed store when the geometry was
+ * traced in CSR mode with it.  Otherwise (on the fly, or TSP_TRACE_NO_CSC) it
+ * is traced within the call: the views (explicit rays: runs of whole 256-ray
+ * windows) are cut into ceil(S / C) equal chunks, C = 2^30 segments or the
+ * environment variable TSP_CHUNK_SEGMENTS; each chunk is traced into stores
+ * of its own, transposed, and its adjoint added into x in chunk order.  That
+ * costs about a full CSR trace per call and synchronises `stream`.  The
+ * first such call allocates the chunks' working memory (about 37 bytes per
+ * segment of the largest chunk expected, 1.5 times the mean; TSP_E_NOMEM if
+ * it does not fit), which the geometry keeps for later calls until tsp_trace
+ * or tsp_geometry_destroy.  Bitwise reproducible for a given geometry and C;
+ * with one chunk it equals the stored deterministic adjoint bit for bit.
  */
 tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
                            int32_t method, void *stream);

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "tsp.h"
@@ -79,6 +80,18 @@ struct tsp_geometry {
     int64_t FV() const { return V * rd.n_obj_frames; }
     int64_t bytes = 0;
     std::vector<std::pair<void *, int64_t>> allocs;
+    // Allocations come from an arena when `arena` is set: a stack of
+    // 256-byte aligned blocks (offset, size, live) in [arena, arena +
+    // arena_size); a block freed on top pops, with any dead blocks below it.
+    // The chunk geometries of a deterministic adjoint without a stored
+    // transposed list work in the arena their parent keeps in chunk_arena, so
+    // that chunks and later calls reuse one allocation: mapping and unmapping
+    // tens of GB per chunk would cost seconds.
+    char *arena = nullptr;
+    int64_t arena_size = 0;
+    std::vector<std::array<int64_t, 3>> arena_blocks;
+    mutable char *chunk_arena = nullptr;
+    mutable int64_t chunk_arena_size = 0;
 };
 
 namespace {
@@ -92,6 +105,23 @@ tsp_status dalloc(tsp_geometry *g, void **p, int64_t bytes, const char *what) {
         std::snprintf(buf, sizeof buf, "%s: %lld bytes would exceed TSP_MAX_DEVICE_BYTES=%lld",
                       what, (long long)bytes, (long long)cap);
         return fail(TSP_E_NOMEM, buf);
+    }
+    if (g->arena) {
+        const int64_t off = g->arena_blocks.empty()
+                                ? 0
+                                : g->arena_blocks.back()[0] + g->arena_blocks.back()[1];
+        const int64_t sz = (bytes + 255) / 256 * 256;
+        if (off + sz > g->arena_size) {
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "%s: %lld bytes exceed the chunk memory (%lld free)",
+                          what, (long long)bytes, (long long)(g->arena_size - off));
+            return fail(TSP_E_NOMEM, buf);
+        }
+        *p = g->arena + off;
+        g->arena_blocks.push_back({off, sz, 1});
+        g->bytes += bytes;
+        g->allocs.push_back({*p, bytes});
+        return TSP_OK;
     }
     hipError_t e = hipMalloc(p, (size_t)bytes);
     if (e != hipSuccess) {
@@ -124,7 +154,41 @@ void dfree(tsp_geometry *g, void *p) {
             break;
         }
     }
+    if (g->arena) {
+        const int64_t off = (char *)p - g->arena;
+        for (auto &b : g->arena_blocks)
+            if (b[0] == off) b[2] = 0;
+        while (!g->arena_blocks.empty() && g->arena_blocks.back()[2] == 0)
+            g->arena_blocks.pop_back();
+        return;
+    }
     (void)hipFree(p);
+}
+
+// Bytes that new allocations of g may take: the arena's free top, or the
+// driver's free memory less a margin (5% of the device, at least 2 GiB).
+// -1 when the driver cannot say.
+int64_t usable_bytes(const tsp_geometry *g) {
+    if (g->arena) {
+        const int64_t off = g->arena_blocks.empty()
+                                ? 0
+                                : g->arena_blocks.back()[0] + g->arena_blocks.back()[1];
+        return g->arena_size - off;
+    }
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
+    return (int64_t)fr - margin;
+}
+
+void release_chunk_arena(const tsp_geometry *g) {
+    if (!g->chunk_arena) return;
+    (void)hipFree(g->chunk_arena);
+    g->chunk_arena = nullptr;
+    g->chunk_arena_size = 0;
 }
 
 template <class T>
@@ -144,6 +208,7 @@ void release_stores(tsp_geometry *g) {
     dfree_p(g, g->d_col_ptr);
     dfree_p(g, g->d_col_code);
     dfree_p(g, g->d_col_len);
+    release_chunk_arena(g);
     g->mode = 0;
     g->S = g->max_per_ray = g->n_stored = 0;
 }
@@ -576,15 +641,12 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
     // `reserve` bytes aside
     auto pass_cap = [&](int64_t reserve) -> int64_t {
         int64_t cap = S;
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-            const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
-            int64_t avail = (int64_t)fr - margin - 4096 - reserve;
+        const int64_t usable = usable_bytes(g);
+        if (usable >= 0) {
+            int64_t avail = usable - 4096 - reserve;
             const int64_t dcap = device_cap();
             if (dcap > 0) avail = std::min<int64_t>(avail, dcap - g->bytes - 4096 - reserve);
             cap = std::min<int64_t>(cap, avail / 25);
-        } else {
-            (void)hipGetLastError();
         }
         if (const char *ev = std::getenv("TSP_TRANSPOSE_MAX_ENTRIES")) {
             const long long v = std::atoll(ev);
@@ -731,14 +793,10 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
     // fits there
     bool fits = false;
     {
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
-            const int64_t margin = std::max<int64_t>((int64_t)1 << 31, (int64_t)(tot / 20));
+        const int64_t usable = usable_bytes(g);
+        if (usable >= 0) {
             const int64_t dcap = device_cap();
-            fits = (int64_t)fr - margin >= 5 * P + 4096 &&
-                   (dcap <= 0 || g->bytes + 5 * P + 4096 <= dcap);
-        } else {
-            (void)hipGetLastError();
+            fits = usable >= 5 * P + 4096 && (dcap <= 0 || g->bytes + 5 * P + 4096 <= dcap);
         }
     }
     if (!fits) free_pass_bufs();
@@ -781,65 +839,8 @@ tsp_status build_transpose(tsp_geometry *g, const int64_t *srow, hipStream_t st)
     return TSP_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-void tsp_geometry_destroy(tsp_geometry *g) {
-    if (!g) return;
-    DeviceGuard dg(g->device);
-    (void)hipDeviceSynchronize();
-    for (auto &a : g->allocs) (void)hipFree(a.first);
-    g->allocs.clear();
-    delete g;
-}
-
-tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
-                                 int32_t n_frames) {
-    g_err.clear();
-    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
-    if (g->mode != 0) return fail(TSP_E_STATE, "object frames must be set before tsp_trace");
-    if (g->rd.explicit_rays)
-        return fail(TSP_E_UNSUPPORTED, "object frames need cone views (explicit rays given)");
-    if (!frame_of_view) return fail(TSP_E_INVALID, "frame_of_view is NULL");
-    if (n_frames < 1) return fail(TSP_E_INVALID, "n_frames < 1");
-    if (g->V * (int64_t)n_frames >= ((int64_t)1 << 31))
-        return fail(TSP_E_INVALID, "n_frames * voxels >= 2^31");
-    const int nv = g->rd.n_views;
-    for (int v = 0; v < nv; v++)
-        if (frame_of_view[v] < 0 || frame_of_view[v] >= n_frames) {
-            char buf[128];
-            std::snprintf(buf, sizeof buf, "frame_of_view[%d] = %d outside [0, %d)", v,
-                          (int)frame_of_view[v], (int)n_frames);
-            return fail(TSP_E_INVALID, buf);
-        }
-    DeviceGuard dg(g->device);
-    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
-    if (g->d_obj_frame) dfree_p(g, g->d_obj_frame);
-    g->rd.obj_frame = nullptr;
-    g->rd.n_obj_frames = 1;
-    tsp_status s;
-    if ((s = dalloc_n(g, &g->d_obj_frame, nv, "object frames")) != TSP_OK) return s;
-    if (hipMemcpy(g->d_obj_frame, frame_of_view, sizeof(int32_t) * nv, hipMemcpyHostToDevice) !=
-        hipSuccess) {
-        dfree_p(g, g->d_obj_frame);
-        return fail(TSP_E_HIP, "hipMemcpy of object frames failed");
-    }
-    g->rd.obj_frame = g->d_obj_frame;
-    g->rd.n_obj_frames = n_frames;
-    return TSP_OK;
-}
-
-tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
-    g_err.clear();
-    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
-    const int base_mode = mode & 0x0f;
-    const bool want_csc = (mode & TSP_TRACE_NO_CSC) == 0;
-    if (base_mode != TSP_MODE_CSR && base_mode != TSP_MODE_ONTHEFLY)
-        return fail(TSP_E_INVALID, "mode must be TSP_MODE_CSR or TSP_MODE_ONTHEFLY");
-    DeviceGuard dg(g->device);
-    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
-    hipStream_t st = (hipStream_t)stream;
+// The work of tsp_trace on a validated geometry (the device already current).
+tsp_status trace_impl(tsp_geometry *g, int base_mode, bool want_csc, hipStream_t st) {
     TSP_HIP(hipStreamSynchronize(st));
     release_stores(g);
     const RayDesc &rd = g->rd;
@@ -969,6 +970,199 @@ tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
     return TSP_OK;
 }
 
+// Segments per chunk of the deterministic adjoint without a stored
+// transposed list; the environment variable TSP_CHUNK_SEGMENTS overrides it.
+constexpr int64_t kChunkSegments = (int64_t)1 << 30;
+
+int64_t chunk_segments() {
+    if (const char *e = std::getenv("TSP_CHUNK_SEGMENTS")) {
+        const long long v = std::atoll(e);
+        if (v > 0) return v;
+    }
+    return kChunkSegments;
+}
+
+// Deterministic adjoint of a geometry without a stored transposed list (on
+// the fly, or stored lists traced without it).  The views (explicit rays: runs
+// of whole windows of 256 rays) are cut into ceil(S / chunk_segments())
+// chunks of equal size, a rule that depends on the geometry alone.  Each
+// chunk is traced into stores of its own (ray-major, then voxel-major,
+// packed), its deterministic adjoint computed, and the chunks' results added
+// into x in chunk order.  So x is bitwise reproducible for a given geometry
+// and setting, and with one chunk it equals the stored deterministic adjoint.
+// Memory: the stores of one chunk at a time.  Synchronises the stream.
+tsp_status chunked_adjoint(const tsp_geometry *g, const float *y, int B, float *x,
+                           hipStream_t st) {
+    const RayDesc &rd = g->rd;
+    const int64_t FV = g->FV(), R = g->R, S = g->S;
+    const int64_t lim = chunk_segments();
+    const int64_t nch = S > lim ? (S + lim - 1) / lim : 1;
+    std::vector<int64_t> cut{0};  // chunk boundaries in rays
+    if (!rd.explicit_rays) {
+        const int64_t hw = (int64_t)rd.H * rd.W, nv = rd.n_views;
+        const int64_t per = (nv + nch - 1) / nch;
+        for (int64_t v = per; v < nv; v += per) cut.push_back(v * hw);
+    } else {
+        const int64_t nwin = (R + kWindow - 1) / kWindow;
+        const int64_t per = (nwin + nch - 1) / nch * kWindow;
+        for (int64_t r = per; r < R; r += per) cut.push_back(r);
+    }
+    cut.push_back(R);
+    int64_t rmax = 0;
+    for (size_t c = 0; c + 1 < cut.size(); c++) rmax = std::max(rmax, cut[c + 1] - cut[c]);
+
+    // the chunks' working memory, allocated once and kept for later calls:
+    // both stores (about 10.5 bytes per segment), one transpose pass over the
+    // whole chunk (25), the trace's per-slot arrays and the block offsets; the
+    // segment count of a chunk is taken as 1.5 times the mean, and a larger
+    // chunk is transposed in passes within the same memory
+    if (!g->chunk_arena) {
+        int64_t ns_max = 0;
+        for (size_t c = 0; c + 1 < cut.size(); c++) {
+            const int64_t rc = cut[c + 1] - cut[c];
+            ns_max = std::max<int64_t>(ns_max, rd.explicit_rays
+                                                   ? (rc + kWindow - 1) / kWindow * kWindow
+                                                   : rc / ((int64_t)rd.H * rd.W) * rd.tiles_h *
+                                                         rd.tiles_w * kWindow);
+        }
+        const int64_t sc = (S / (int64_t)(cut.size() - 1)) * 3 / 2 + 4096;
+        int64_t want = sc * 37 + ns_max * 48 + FV * 40 + ((int64_t)64 << 20);
+        const int64_t dcap = device_cap();
+        if (dcap > 0) want = std::min<int64_t>(want, dcap - g->bytes);
+        void *mem = nullptr;
+        if (want <= 0 || hipMalloc(&mem, (size_t)want) != hipSuccess) {
+            (void)hipGetLastError();
+            char buf[160];
+            std::snprintf(buf, sizeof buf, "chunked adjoint: %lld bytes of working memory",
+                          (long long)want);
+            return fail(TSP_E_NOMEM, buf);
+        }
+        g->chunk_arena = (char *)mem;
+        g->chunk_arena_size = want;
+    }
+    float *ybuf = nullptr, *xbuf = nullptr;
+    hipError_t e = hipMallocAsync((void **)&ybuf, (size_t)std::max<int64_t>(1, B * rmax) * 4, st);
+    if (e == hipSuccess && cut.size() > 2)
+        e = hipMallocAsync((void **)&xbuf, (size_t)B * FV * 4, st);
+    auto free_bufs = [&]() {
+        if (ybuf) (void)hipFreeAsync(ybuf, st);
+        if (xbuf) (void)hipFreeAsync(xbuf, st);
+        (void)hipStreamSynchronize(st);
+    };
+    if (e != hipSuccess) {
+        free_bufs();
+        return fail(TSP_E_NOMEM, std::string("chunked adjoint buffers: ") + hipGetErrorString(e));
+    }
+    for (size_t c = 0; c + 1 < cut.size(); c++) {
+        const int64_t r0 = cut[c], rc = cut[c + 1] - r0;
+        // a geometry of the chunk's rays that shares g's tables and frames
+        tsp_geometry *gc = new tsp_geometry();
+        gc->device = g->device;
+        gc->T = g->T;
+        gc->d_tab = g->d_tab;
+        gc->V = g->V;
+        gc->R = rc;
+        gc->rd = rd;
+        gc->rd.R = rc;
+        gc->bytes = g->bytes;  // the device cap counts the parent's memory too
+        gc->arena = g->chunk_arena;
+        gc->arena_size = g->chunk_arena_size;
+        if (!rd.explicit_rays) {
+            const int64_t v0 = r0 / ((int64_t)rd.H * rd.W);
+            const int nvc = (int)(rc / ((int64_t)rd.H * rd.W));
+            gc->rd.n_views = nvc;
+            gc->rd.frames = rd.frames + 16 * v0;
+            gc->rd.obj_frame = rd.obj_frame ? rd.obj_frame + v0 : nullptr;
+            gc->rd.n_slots = (int64_t)nvc * rd.tiles_h * rd.tiles_w * kWindow;
+        } else {
+            gc->rd.starts = rd.starts + 3 * r0;
+            gc->rd.dirs = rd.dirs + 3 * r0;
+            gc->rd.n_slots = (rc + kWindow - 1) / kWindow * kWindow;
+        }
+        tsp_status s = trace_impl(gc, TSP_MODE_CSR, true, st);
+        if (s == TSP_OK) {
+            float *xo = (c == 0) ? x : xbuf;
+            e = launch_copy_rows(y + r0, R, ybuf, rc, B, st);
+            if (e == hipSuccess) e = adjoint_dispatch(gc, ybuf, B, xo, TSP_ADJ_DETERMINISTIC, st);
+            if (e == hipSuccess && c > 0) e = launch_add_f32(xbuf, x, (int64_t)B * FV, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess)
+                s = fail(TSP_E_HIP, std::string("chunked adjoint: ") + hipGetErrorString(e));
+        }
+        (void)hipStreamSynchronize(st);  // the chunk's work is done before its memory is reused
+        delete gc;
+        if (s != TSP_OK) {
+            free_bufs();
+            return s;
+        }
+    }
+    free_bufs();
+    return TSP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void tsp_geometry_destroy(tsp_geometry *g) {
+    if (!g) return;
+    DeviceGuard dg(g->device);
+    (void)hipDeviceSynchronize();
+    for (auto &a : g->allocs) (void)hipFree(a.first);
+    g->allocs.clear();
+    release_chunk_arena(g);
+    delete g;
+}
+
+tsp_status tsp_set_object_frames(tsp_geometry *g, const int32_t *frame_of_view,
+                                 int32_t n_frames) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (g->mode != 0) return fail(TSP_E_STATE, "object frames must be set before tsp_trace");
+    if (g->rd.explicit_rays)
+        return fail(TSP_E_UNSUPPORTED, "object frames need cone views (explicit rays given)");
+    if (!frame_of_view) return fail(TSP_E_INVALID, "frame_of_view is NULL");
+    if (n_frames < 1) return fail(TSP_E_INVALID, "n_frames < 1");
+    if (g->V * (int64_t)n_frames >= ((int64_t)1 << 31))
+        return fail(TSP_E_INVALID, "n_frames * voxels >= 2^31");
+    const int nv = g->rd.n_views;
+    for (int v = 0; v < nv; v++)
+        if (frame_of_view[v] < 0 || frame_of_view[v] >= n_frames) {
+            char buf[128];
+            std::snprintf(buf, sizeof buf, "frame_of_view[%d] = %d outside [0, %d)", v,
+                          (int)frame_of_view[v], (int)n_frames);
+            return fail(TSP_E_INVALID, buf);
+        }
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
+    if (g->d_obj_frame) dfree_p(g, g->d_obj_frame);
+    g->rd.obj_frame = nullptr;
+    g->rd.n_obj_frames = 1;
+    tsp_status s;
+    if ((s = dalloc_n(g, &g->d_obj_frame, nv, "object frames")) != TSP_OK) return s;
+    if (hipMemcpy(g->d_obj_frame, frame_of_view, sizeof(int32_t) * nv, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+        dfree_p(g, g->d_obj_frame);
+        return fail(TSP_E_HIP, "hipMemcpy of object frames failed");
+    }
+    g->rd.obj_frame = g->d_obj_frame;
+    g->rd.n_obj_frames = n_frames;
+    return TSP_OK;
+}
+
+tsp_status tsp_trace(tsp_geometry *g, int32_t mode, void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    const int base_mode = mode & 0x0f;
+    const bool want_csc = (mode & TSP_TRACE_NO_CSC) == 0;
+    if (base_mode != TSP_MODE_CSR && base_mode != TSP_MODE_ONTHEFLY)
+        return fail(TSP_E_INVALID, "mode must be TSP_MODE_CSR or TSP_MODE_ONTHEFLY");
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
+    hipStream_t st = (hipStream_t)stream;
+    return trace_impl(g, base_mode, want_csc, st);
+}
+
 tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, float *y,
                        void *stream) {
     g_err.clear();
@@ -991,10 +1185,9 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
     if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC)
         return fail(TSP_E_INVALID, "method must be TSP_ADJ_DETERMINISTIC or TSP_ADJ_ATOMIC");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject before tsp_trace");
-    if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
-        return fail(TSP_E_UNSUPPORTED,
-                    "deterministic adjoint needs TSP_MODE_CSR with the transposed store");
     DeviceGuard dg(g->device);
+    if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
+        return chunked_adjoint(g, y, batch, x, (hipStream_t)stream);
     const hipError_t e = adjoint_dispatch(g, y, batch, x, method, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
     return TSP_OK;

@@ -228,6 +228,11 @@ hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int
 hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
                                 int64_t base, int64_t *col_ptr, hipStream_t st);
 hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st);
+// x[i] += a[i], i < n
+hipError_t launch_add_f32(const float *a, float *x, int64_t n, hipStream_t st);
+// dst[b][i] = src[b * stride + i] for i < n, b < B (dst contiguous [B][n])
+hipError_t launch_copy_rows(const float *src, int64_t stride, float *dst, int64_t n, int B,
+                            hipStream_t st);
 // Packing of the sorted voxel-major entries (col_ptr [nkeys + 1], ent =
 // slot | length bits << 32): per key the rows of 64 entries its packed list
 // takes, then the packed lists at base[key] (base = exclusive scan of 64 rows).

@@ -360,6 +360,20 @@ __global__ __launch_bounds__(256) void k_pack_fill(const int64_t *col_ptr, const
     }
 }
 
+// x += a
+__global__ void k_add(const float *a, float *x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += a[i];
+}
+
+// dst[b][i] = src[b * stride + i], i < n, b < B
+__global__ void k_copy_rows(const float *src, int64_t stride, float *dst, int64_t n, int B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * B) return;
+    const int64_t b = i / n, k = i - b * n;
+    dst[i] = src[b * stride + k];
+}
+
 __global__ void k_copy_u64(const uint64_t *s, uint64_t *d, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = s[i];
@@ -582,6 +596,20 @@ hipError_t launch_pack_fill(const int64_t *col_ptr, const uint64_t *ent, int64_t
     if (nkeys <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_fill, dim3(blocks_for(nkeys * kWave, 256)), dim3(256), 0, st,
                        col_ptr, ent, nkeys, base, code, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_f32(const float *a, float *x, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_rows(const float *src, int64_t stride, float *dst, int64_t n, int B,
+                            hipStream_t st) {
+    if (n <= 0 || B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(n * B, 256)), dim3(256), 0, st, src, stride,
+                       dst, n, B);
     return hipGetLastError();
 }
 

@@ -118,6 +118,7 @@ class Projector:
         with torch.cuda.device(self.device):
             N.check(N.lib.tsp_trace(self._h, m, N.stream_handle()))
         self.mode = mode
+        self.csc = mode == "csr" and bool(csc)
 
     def info(self):
         inf = N.tsp_info()
@@ -168,8 +169,13 @@ class Projector:
             N.check(N.lib.tsp_forward(self._h, N.ptr(rho), B, N.ptr(y), N.stream_handle()))
         return y
 
-    def backproject(self, y, method="deterministic", out=None):
-        """x = F^T y.  y: (..., *out_shape) float32.  method: deterministic | atomic."""
+    def backproject(self, y, method=None, out=None):
+        """x = F^T y.  y: (..., *out_shape) float32.
+
+        method: "deterministic" (bitwise reproducible; from the voxel-major
+        store when the lists are stored with it, else traced chunk by chunk
+        within the call, which costs a full trace), "atomic", or None: the
+        stored deterministic adjoint when there is one, else the atomic one."""
         y = self._dev_f32(y, "y")
         k = len(self.out_shape)
         if tuple(y.shape[y.dim() - k:]) != self.out_shape:
@@ -178,8 +184,8 @@ class Projector:
         B = int(np.prod(lead)) if lead else 1
         x = out if out is not None else torch.empty((*lead, *self.obj_shape),
                                                     dtype=torch.float32, device=self.device)
-        if self.mode == "onthefly":
-            method = "atomic"
+        if method is None:
+            method = "deterministic" if self.csc else "atomic"
         if B:
             N.check(N.lib.tsp_backproject(self._h, N.ptr(y), B, N.ptr(x), ADJ[method],
                                           N.stream_handle()))
@@ -212,7 +218,7 @@ class ProjectorFn(torch.autograd.Function):
     never sees the ray tracer."""
 
     @staticmethod
-    def forward(ctx, rho, proj, method="deterministic"):
+    def forward(ctx, rho, proj, method=None):
         ctx.proj = proj
         ctx.method = method
         return proj.forward(rho)

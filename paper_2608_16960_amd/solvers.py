@@ -20,7 +20,7 @@ from .projector import ProjectorFn
 class CountingOperator:
     """F and F^T of a Projector with a per-object call counter."""
 
-    def __init__(self, P, method="deterministic"):
+    def __init__(self, P, method=None):
         self.P = P
         self.method = method
         self.calls = None

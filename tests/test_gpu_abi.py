@@ -53,26 +53,31 @@ def test_state_and_capacity_errors():
         finally:
             del os.environ["TSP_MAX_DEVICE_BYTES"]
         assert N.lib.tsp_forward(h, N.ptr(rho), 1, N.ptr(y), s) == N.TSP_OK
+        # on the fly, the deterministic adjoint is traced chunk by chunk in the call
         assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_DETERMINISTIC, s) == \
-            N.TSP_E_UNSUPPORTED
+            N.TSP_OK
+        xd = x.clone()
         assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_ATOMIC, s) == N.TSP_OK
+        assert torch.allclose(x, xd, rtol=1e-5, atol=1e-5)
         rp = torch.empty(w.views.n_rays + 1, dtype=torch.int64, device="cuda")
         assert N.lib.tsp_segments(h, N.ptr(rp), None, None, s) == N.TSP_E_STATE
         assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), 7, s) == N.TSP_E_INVALID
         info = N.tsp_info()
         assert N.lib.tsp_query(h, ctypes.byref(info)) == N.TSP_OK
         assert info.mode == N.TSP_MODE_ONTHEFLY and info.n_segments > 0 and info.has_csc == 0
-        # switch back to stored lists without the transposed store
+        # switch back to stored lists without the transposed store: the
+        # deterministic adjoint is then traced in the call as well
         assert N.lib.tsp_trace(h, N.TSP_MODE_CSR | N.TSP_TRACE_NO_CSC, s) == N.TSP_OK
         assert N.lib.tsp_backproject(h, N.ptr(y), 1, N.ptr(x), N.TSP_ADJ_DETERMINISTIC, s) == \
-            N.TSP_E_UNSUPPORTED
+            N.TSP_OK
+        assert torch.equal(x, xd)
         torch.cuda.synchronize()
     finally:
         N.lib.tsp_geometry_destroy(h)
 
 
 def test_projector_falls_back_to_onthefly_adjoint():
-    """The Python layer uses the atomic adjoint in on-the-fly mode."""
+    """By default the Python layer uses the atomic adjoint in on-the-fly mode."""
     from paper_2608_16960_amd.projector import Projector
     w = W.tiny()
     P = Projector(w.grid, views=w.views, mode="onthefly")
