@@ -49,6 +49,36 @@ typedef enum tspnn_status {
     TSPNN_E_UNSUPPORTED = 5  /* shape the kernels do not handle (e.g. D2 % 16 != 0) */
 } tspnn_status;
 
+/* ------------------------------------------------------------------ vectors */
+/*
+ * Per-object vector steps of the solvers (gradient descent, power iteration,
+ * the data term and the training loss).  Objects are B rows of n float32 on
+ * the device.  Reductions run in a fixed order (blocks of 8192 elements,
+ * then the blocks of each row in increasing order): the same inputs give the
+ * same bits.  work: tspnn_vec_workspace(B, n) bytes of device memory.
+ */
+size_t tspnn_vec_workspace(int32_t B, int64_t n);
+
+/*
+ * Residual of the data term: diff[o][i] = f[o][i] - y[o][i] (diff may be NULL,
+ * or alias f) and res[o] = sum_i diff[o][i]^2, written only for objects with
+ * active[o] != 0 (every object when active is NULL; active: device int32 [B]).
+ * 1 <= B <= 65535.
+ */
+tspnn_status tspnn_residual(const float *y, const float *f, int32_t B, int64_t n, float *diff,
+                            float *res, const int32_t *active, void *work, void *stream);
+
+/* out[o] = sum_i a[o][i] * b[o][i]  (1 <= B <= 65535) */
+tspnn_status tspnn_dot(const float *a, const float *b, int32_t B, int64_t n, float *out,
+                       void *work, void *stream);
+
+/* x[o][i] += alpha * a[o][i] for objects with active[o] != 0 (all when NULL) */
+tspnn_status tspnn_axpy(float *x, const float *a, float alpha, int32_t B, int64_t n,
+                        const int32_t *active, void *stream);
+
+/* dst[i] = alpha * src[i], i < n (dst may alias src) */
+tspnn_status tspnn_scale(const float *src, float alpha, int64_t n, float *dst, void *stream);
+
 /* ------------------------------------------------------------------ TV + Adam */
 
 /* Workspace (bytes) that tspnn_tv needs for a batch of B volumes of V voxels. */

@@ -16,6 +16,7 @@ FP32 master weights, BF16 MFMA kernels for the hidden layers.
 import numpy as np
 import torch
 
+from . import nn as NN
 from . import solvers
 from .nn import CNN, Adam
 
@@ -57,20 +58,21 @@ class WarmStart:
             tot = 0.0
             for b0 in range(0, n - batch + 1, batch):
                 idx = perm[b0:b0 + batch].to(x_in.device)
-                xb = x_in[idx] * self.scale
+                xb = x_in[idx]
+                NN.scale(xb, self.scale, out=xb)
                 tb = truth[idx]
                 out = self.net.forward(xb)
-                diff = out - tb
-                grads = self.net.backward((2.0 / (batch * nvox)) * diff)
+                res = NN.residual(tb, out, diff=out)  # out now holds out - tb
+                grads = self.net.backward(NN.scale(out, 2.0 / (batch * nvox), out=out))
                 opt.step(grads, bf16_copies=self.net.bf16_targets())
-                tot += float((diff * diff).mean()) * batch
+                tot += float(res.cpu().double().sum()) / nvox
             hist.append(tot / (n - n % batch))
             if log:
                 log(f"epoch {ep}: mse {hist[-1]:.4e}")
         return hist
 
     def predict(self, x_in):
-        return self.net.forward(x_in * self.scale, keep=False)
+        return self.net.forward(NN.scale(x_in, self.scale), keep=False)
 
     # ------------------------------------------------------------ evaluation
     def evaluate(self, truth, batch=8):

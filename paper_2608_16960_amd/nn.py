@@ -1,5 +1,6 @@
 """ctypes binding of libtspnn.so (include/tspnn.h) and the layers built on it.
 
+- residual, dot, axpy, scale: the per-object vector steps of the solvers;
 - tv(rho, eps): smoothed anisotropic total variation and its gradient;
 - TV: torch.autograd.Function around it (for lambda * TV(rho) in a loss);
 - Adam: optimiser state in device memory, one fused update kernel per step;
@@ -42,6 +43,11 @@ SIGNATURES = {
     "tspnn_conv_flip_weights": (_st, [_vp, _vp, _vp]),
     "tspnn_to_bf16": (_st, [_vp, _vp, _i64, _vp]),
     "tspnn_from_bf16": (_st, [_vp, _vp, _i64, _vp]),
+    "tspnn_vec_workspace": (ctypes.c_size_t, [_i32, _i64]),
+    "tspnn_residual": (_st, [_vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp, _vp]),
+    "tspnn_dot": (_st, [_vp, _vp, _i32, _i64, _vp, _vp, _vp]),
+    "tspnn_axpy": (_st, [_vp, _vp, _f, _i32, _i64, _vp, _vp]),
+    "tspnn_scale": (_st, [_vp, _f, _i64, _vp, _vp]),
     "tspnn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -103,6 +109,67 @@ def from_bf16(x):
     return y
 
 
+# ------------------------------------------------------------------ vectors
+
+def _rows(t, name):
+    t = _req(t, torch.float32, name)
+    B = t.shape[0] if t.dim() > 1 else 1
+    return t, B, t.numel() // B
+
+
+def _vec_work(B, n, dev):
+    return torch.empty(int(lib.tspnn_vec_workspace(B, n)) // 4 + 1, dtype=torch.float32,
+                       device=dev)
+
+
+def residual(y, f, diff=None, out=None, active=None):
+    """Per object (rows over the leading dimension): res[b] = sum (f - y)^2,
+    float32 [B]; diff (like f, may be f itself) receives f - y.  With active
+    (bool or int [B] on the device) only the active entries of `out` are
+    written, the others keep their values."""
+    y, B, n = _rows(y, "y")
+    f, B2, n2 = _rows(f, "f")
+    if (B, n) != (B2, n2):
+        raise ValueError("y and f must have the same shape")
+    if diff is not None:
+        _req(diff, torch.float32, "diff")
+    res = out if out is not None else torch.empty(B, dtype=torch.float32, device=y.device)
+    act = None if active is None else active.to(torch.int32).contiguous()
+    check(lib.tspnn_residual(_p(y), _p(f), B, n, _p(diff), _p(res), _p(act),
+                             _p(_vec_work(B, n, y.device)), _s()))
+    return res
+
+
+def dot(a, b):
+    """out[b] = sum a[b] * b[b] per object (float32 [B])."""
+    a, B, n = _rows(a, "a")
+    b, B2, n2 = _rows(b, "b")
+    if (B, n) != (B2, n2):
+        raise ValueError("a and b must have the same shape")
+    out = torch.empty(B, dtype=torch.float32, device=a.device)
+    check(lib.tspnn_dot(_p(a), _p(b), B, n, _p(out), _p(_vec_work(B, n, a.device)), _s()))
+    return out
+
+
+def axpy(x, a, alpha, active=None):
+    """x[b] += alpha * a[b] in place, for active objects (all when None)."""
+    x, B, n = _rows(x, "x")
+    a, B2, n2 = _rows(a, "a")
+    if (B, n) != (B2, n2):
+        raise ValueError("x and a must have the same shape")
+    act = None if active is None else active.to(torch.int32).contiguous()
+    check(lib.tspnn_axpy(_p(x), _p(a), float(alpha), B, n, _p(act), _s()))
+    return x
+
+
+def scale(src, alpha, out=None):
+    """alpha * src (out may be src itself)."""
+    src = _req(src.contiguous(), torch.float32, "src")
+    dst = out if out is not None else torch.empty_like(src)
+    check(lib.tspnn_scale(_p(src), float(alpha), src.numel(), _p(dst), _s()))
+    return dst
+
+
 # ------------------------------------------------------------------ TV
 
 def tv(rho, eps=1e-6, with_grad=True):
@@ -132,7 +199,7 @@ class TV(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
-        return grad * g, None
+        return scale(grad, float(g)), None
 
 
 # ------------------------------------------------------------------ Adam

@@ -6,15 +6,19 @@
   eta = 1 / (2 lambda_max), rho <- rho - eta * 2 F^T (F rho - y), stopping
   per object when its residual reaches a target;
 - adam_tv: ||y - F rho||^2 + lambda TV(rho) minimised with Adam (Listing 7),
-  gradients from ProjectorFn / TV (hand-written kernels, no autograd tracing
+  gradients from DataTerm / TV (hand-written kernels, no autograd tracing
   of the ray tracer).
+The vector arithmetic (residuals, dot products, updates) runs in the
+library's kernels too (nn.residual / dot / axpy / scale).
 Batched: every function works on a batch of objects at once (the projector
 kernels take batches natively).
 """
+import math
+
 import torch
 
+from . import nn as NN
 from .nn import TV, Adam
-from .projector import ProjectorFn
 
 
 class CountingOperator:
@@ -52,14 +56,14 @@ def power_iteration(P, iters=20, seed=0):
     lam = 0.0
     for _ in range(iters):
         w = P.backproject(P.forward(v))
-        lam = float((w * v).sum() / (v * v).sum())
-        v = w / w.norm()
+        lam = float(NN.dot(w, v)[0]) / float(NN.dot(v, v)[0])
+        v = NN.scale(w, 1.0 / math.sqrt(float(NN.dot(w, w)[0])))
     return lam
 
 
 def residual(y, Fr):
     """||y - F rho||^2 per object."""
-    return ((y - Fr) ** 2).flatten(1).sum(1)
+    return NN.residual(y, Fr)
 
 
 def gd(op, y, rho0, lam_max, iters=None, target=None, max_iters=10000, Fr0=None):
@@ -74,7 +78,8 @@ def gd(op, y, rho0, lam_max, iters=None, target=None, max_iters=10000, Fr0=None)
     rho = rho0.clone()
     B = rho.shape[0]
     Fr = op.F(rho) if Fr0 is None else Fr0
-    res = residual(y, Fr)
+    diff = torch.empty_like(Fr)  # F rho - y, the adjoint's input
+    res = NN.residual(y, Fr, diff=diff)
     hist = [res.clone()]
     done = torch.zeros(B, dtype=torch.bool, device=rho.device)
     if target is not None:
@@ -87,17 +92,35 @@ def gd(op, y, rho0, lam_max, iters=None, target=None, max_iters=10000, Fr0=None)
         if iters is None and (bool(done.all()) or k >= max_iters):
             break
         active = ~done
-        g = op.FT(Fr - y, active)
-        step = (g / lam_max) * active.float().reshape(B, *([1] * (rho.dim() - 1)))
-        rho = rho - step
+        g = op.FT(diff, active)
+        NN.axpy(rho, g, -1.0 / lam_max, active=active)
         Fr = op.F(rho, active)
-        res = torch.where(active, residual(y, Fr), res)
+        NN.residual(y, Fr, diff=diff, out=res, active=active)
         hist.append(res.clone())
         n_it += active.cpu().long()
         if target is not None:
             done |= res <= target
         k += 1
     return rho, hist, n_it, Fr
+
+
+class DataTerm(torch.autograd.Function):
+    """||F rho - y||^2 summed over objects; the gradient 2 F^T (F rho - y).
+    Both run in the library's kernels (projector, residual, scaling)."""
+
+    @staticmethod
+    def forward(ctx, rho, proj, y):
+        Fr = proj.forward(rho)
+        res = NN.residual(y.reshape(1, -1), Fr.reshape(1, -1), diff=Fr.reshape(1, -1))
+        ctx.proj = proj
+        ctx.save_for_backward(Fr)  # now F rho - y
+        return res[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (d,) = ctx.saved_tensors
+        x = ctx.proj.backproject(d)
+        return NN.scale(x, 2.0 * float(g), out=x), None, None
 
 
 def adam_tv(P, y, rho0, lam_tv=1e-3, lr=1e-2, steps=200, eps_tv=1e-6):
@@ -107,7 +130,7 @@ def adam_tv(P, y, rho0, lam_tv=1e-3, lr=1e-2, steps=200, eps_tv=1e-6):
     losses = []
     for _ in range(steps):
         r = rho.detach().requires_grad_(True)
-        loss = ((ProjectorFn.apply(r, P) - y) ** 2).sum() + lam_tv * TV.apply(r, eps_tv)
+        loss = DataTerm.apply(r, P, y) + lam_tv * TV.apply(r, eps_tv)
         loss.backward()
         opt.step([r.grad])
         losses.append(float(loss))

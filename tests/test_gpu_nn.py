@@ -217,3 +217,45 @@ def test_cnn_end_to_end_gradient(nn):
         gc, gr = gg.cpu().double().reshape(-1), p.grad.reshape(-1)
         cos = float(gc @ gr / (gc.norm() * gr.norm() + 1e-30))
         assert cos > 0.995, (k, cos)
+
+
+def test_vector_steps(nn):
+    """Per-object residual (with the difference written, optionally in place
+    and masked), dot product, masked axpy and scaling against FP64 numpy on
+    3 objects of 20001 floats (ragged against the 8192-element blocks);
+    reductions bitwise repeatable."""
+    rng = np.random.default_rng(80)
+    B, n = 3, 20001
+    y = rng.normal(size=(B, n)).astype(np.float32)
+    f = rng.normal(size=(B, n)).astype(np.float32)
+    yt, ft = torch.from_numpy(y).cuda(), torch.from_numpy(f).cuda()
+    d64 = f.astype(np.float64) - y.astype(np.float64)
+    ref = np.sum(d64 ** 2, axis=1)
+    diff = torch.empty_like(ft)
+    res = nn.residual(yt, ft, diff=diff)
+    assert np.allclose(res.cpu().numpy(), ref, rtol=1e-5)
+    assert torch.equal(diff, ft - yt)
+    assert torch.equal(res, nn.residual(yt, ft))
+    # masked: only active objects' entries are written; diff may alias f
+    out = torch.full((B,), -7.0, device="cuda")
+    active = torch.tensor([True, False, True], device="cuda")
+    f2 = ft.clone()
+    nn.residual(yt, f2, diff=f2, out=out, active=active)
+    o = out.cpu().numpy()
+    assert o[1] == -7.0 and np.allclose(o[[0, 2]], ref[[0, 2]], rtol=1e-5)
+    assert torch.equal(f2, ft - yt)
+    # dot
+    dt = nn.dot(yt, ft).cpu().numpy()
+    assert np.allclose(dt, np.sum(y.astype(np.float64) * f, axis=1), rtol=1e-4, atol=1e-3)
+    # axpy (masked) and scale
+    x = ft.clone()
+    nn.axpy(x, yt, -0.25, active=active)
+    xs = x.cpu().numpy()
+    assert np.array_equal(xs[1], f[1])
+    assert np.allclose(xs[[0, 2]], f[[0, 2]] - 0.25 * y[[0, 2]], rtol=1e-6, atol=1e-6)
+    s = nn.scale(yt, 3.5).cpu().numpy()
+    assert np.array_equal(s, np.float32(3.5) * y)
+    from paper_2608_16960_amd.nn import TspnnError
+    with pytest.raises(TspnnError):
+        nn.check(nn.lib.tspnn_residual(nn._p(yt), nn._p(ft), 0, n, None, nn._p(out), None,
+                                       nn._p(out), nn._s()))
