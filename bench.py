@@ -442,6 +442,14 @@ def main():
                     "median_ms": adj_t[K // 2], "bytes": adj_bytes,
                     "GBps": adj_bytes / adj_ms / 1e6},
     }
+    # the measured alternative: the atomic adjoint from the ray-major store
+    # (outside the timed step; its sums depend on the order atomics land in)
+    xa = torch.empty_like(x)
+    atomic_ms = _time_ms(lambda: P.backproject(y, "atomic", out=xa), 20)
+    atomic = {"kernel": "k_adj_atomic<1>", "ms": atomic_ms,
+              "GBps_algorithmic": adj_bytes / atomic_ms / 1e6,
+              "max_rel_diff_vs_deterministic":
+                  float((xa - x).abs().max() / x.abs().max().clamp_min(1e-30))}
     copy_gbps = measured_copy_gbps(dev)
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
@@ -463,6 +471,7 @@ def main():
                      "copy_GBps": copy_gbps, "frac_of_copy": d["GBps"] / copy_gbps},
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kern.items()},
+        "atomic_adjoint": atomic,
         "trace_s": trace_s,
         "stored_slots": info["n_stored"], "pad_frac": info["n_stored"] / max(S, 1) - 1,
     }
