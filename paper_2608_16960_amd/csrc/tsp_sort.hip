@@ -399,7 +399,12 @@ __global__ __launch_bounds__(256) void k_rs_hist(const int32_t *keys, int64_t n,
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = (int32_t)cnt[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin, const uint64_t *vin,
+// One digit pass of the stable LSD sort over a tile of kRsTile items, written
+// straight to global memory: each wavefront ranks its items among equal
+// digits (ballots over the 8 digit bits) and writes each item at its place.
+// Used once the low digit is sorted: the higher digits of these keys are
+// spatially coherent, so neighbouring items land close together anyway.
+__global__ __launch_bounds__(256) void k_rs_scatter_direct(const int32_t *kin, const uint64_t *vin,
                                                      int32_t *kout, uint64_t *vout, int64_t n,
                                                      int shift, const int64_t *offs,
                                                      int64_t nblk) {
@@ -452,6 +457,89 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin, const ui
         __builtin_amdgcn_wave_barrier();
         if (leader) run[w][d] = before + (unsigned)__popcll(match);
         __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// The same pass with the tile reordered by digit in LDS first, so that each
+// digit's run goes out contiguously at its place (goff, from the histogram
+// scan) and global writes coalesce instead of scattering over 256 buckets:
+// used for the lowest digit, which is spread at random over the input.
+__global__ __launch_bounds__(256) void k_rs_scatter_tiled(const int32_t *kin, const uint64_t *vin,
+                                                     int32_t *kout, uint64_t *vout, int64_t n,
+                                                     int shift, const int64_t *offs,
+                                                     int64_t nblk) {
+    __shared__ unsigned run[4][256];
+    __shared__ unsigned wbase[4][256];
+    __shared__ unsigned loff[256];  // start of each digit within the tile
+    __shared__ unsigned wsum[4];
+    __shared__ int64_t goff[256];
+    __shared__ int32_t lk[kRsTile];
+    __shared__ uint64_t lv[kRsTile];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < 1024; i += 256) (&run[0][0])[i] = 0;
+    goff[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    __syncthreads();
+    const int64_t wb = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveItems;
+    for (int c = 0; c < kRsItems; c++) {
+        const int64_t idx = wb + c * 64 + lane;
+        if (idx < n) atomicAdd(&run[w][(kin[idx] >> shift) & 255], 1u);
+    }
+    __syncthreads();
+    unsigned tot = 0;  // items of digit tid in the tile
+#pragma unroll
+    for (int ww = 0; ww < 4; ww++) {
+        const unsigned cc = run[ww][tid];
+        wbase[ww][tid] = tot;
+        tot += cc;
+        run[ww][tid] = 0;
+    }
+    // exclusive scan of the digit counts over the tile
+    unsigned incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned t = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    unsigned wpre = 0;
+    for (int ww = 0; ww < w; ww++) wpre += wsum[ww];
+    loff[tid] = wpre + incl - tot;
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+    for (int c = 0; c < kRsItems; c++) {
+        const int64_t idx = wb + c * 64 + lane;
+        const bool valid = idx < n;
+        const int32_t k = valid ? kin[idx] : 0;
+        const uint64_t v = valid ? vin[idx] : 0ull;
+        const int d = (k >> shift) & 255;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int bbit = 0; bbit < 8; bbit++) {
+            const bool bitset = (d >> bbit) & 1;
+            const uint64_t m = __ballot(bitset);
+            match &= bitset ? m : ~m;
+        }
+        const unsigned rank = (unsigned)__popcll(match & below);
+        const unsigned before = run[w][d];
+        if (valid) {
+            const unsigned p = loff[d] + wbase[w][d] + before + rank;
+            lk[p] = k;
+            lv[p] = v;
+        }
+        const bool leader = valid && ((match >> lane) == 1ull);
+        __builtin_amdgcn_wave_barrier();
+        if (leader) run[w][d] = before + (unsigned)__popcll(match);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    const unsigned nvalid = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    for (unsigned i = tid; i < nvalid; i += 256) {
+        const int32_t k = lk[i];
+        const int d = (k >> shift) & 255;
+        const int64_t pos = goff[d] + (int64_t)(i - loff[d]);
+        kout[pos] = k;
+        vout[pos] = lv[i];
     }
 }
 
@@ -529,8 +617,12 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
                            nb);
         hipError_t e = launch_scan_i32(hist, h, 1, offs, tmp, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(256), 0, st, ka, va, kb, vb, n,
-                           shift, offs, nb);
+        if (shift == 0)
+            hipLaunchKernelGGL(k_rs_scatter_tiled, dim3((unsigned)nb), dim3(256), 0, st, ka, va, kb,
+                               vb, n, shift, offs, nb);
+        else
+            hipLaunchKernelGGL(k_rs_scatter_direct, dim3((unsigned)nb), dim3(256), 0, st, ka, va,
+                               kb, vb, n, shift, offs, nb);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         int32_t *tk = ka;
