@@ -208,11 +208,10 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
                              int64_t n, int key_bits, void *ws, int *in_second, hipStream_t st);
 size_t radix_ws_bytes(int64_t n);
 // Transpose in passes over key ranges [lo, hi) (bounded temporary memory):
-// coarse key histogram (bucket = key >> shift, nb <= key_hist_buckets()),
+// coarse key histogram (bucket = key >> shift, at most 4096 buckets),
 // counts in a range per natural slot (cnt_ray: [n_slots], zeroed first),
 // compacted expansion in natural slot order (crow: [n_slots + 1] offsets),
 // and the range's column offsets with a base.
-int key_hist_buckets();
 hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                            const int64_t *slice_ptr, const uint8_t *code, const float *len,
                            int nr, int ne, int na, int shift, int nb, unsigned long long *hist,
@@ -227,7 +226,6 @@ hipError_t launch_expand_range(const RayDesc &rd, const int32_t *perm, const int
                                int32_t hi, int32_t *keys, uint64_t *vals, hipStream_t st);
 hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t key0, int64_t nk,
                                 int64_t base, int64_t *col_ptr, hipStream_t st);
-hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st);
 // x[i] += a[i], i < n
 hipError_t launch_add_f32(const float *a, float *x, int64_t n, hipStream_t st);
 // dst[b][i] = src[b * stride + i] for i < n, b < B (dst contiguous [B][n])

@@ -374,11 +374,6 @@ __global__ void k_copy_rows(const float *src, int64_t stride, float *dst, int64_
     dst[i] = src[b * stride + k];
 }
 
-__global__ void k_copy_u64(const uint64_t *s, uint64_t *d, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) d[i] = s[i];
-}
-
 // ------------------------------------------------------------ radix sort
 
 constexpr int kRsItems = 16;                // items per thread
@@ -637,8 +632,6 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
     return hipSuccess;
 }
 
-int key_hist_buckets() { return kHistBuckets; }
-
 hipError_t launch_key_hist(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                            const int64_t *slice_ptr, const uint8_t *code, const float *len,
                            int nr, int ne, int na, int shift, int nb, unsigned long long *hist,
@@ -702,12 +695,6 @@ hipError_t launch_copy_rows(const float *src, int64_t stride, float *dst, int64_
     if (n <= 0 || B <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(n * B, 256)), dim3(256), 0, st, src, stride,
                        dst, n, B);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_u64(const uint64_t *s, uint64_t *d, int64_t n, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, s, d, n);
     return hipGetLastError();
 }
 
