@@ -242,7 +242,10 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
 // Segments with keys in [lo, hi), compacted in natural slot order (the ray
 // in natural slot s writes at crow[s] ...), as (key, natural slot | length
 // bits << 32) for the sort: every key's entries then come out of the stable
-// sort in increasing slot order.
+// sort in increasing slot order.  A lane reads its ray's entries four at a
+// time (one 4-byte code word, one 16-byte length load) and writes its items
+// four at a time once its output is 16-byte aligned (16 bytes of keys, 32 of
+// values per store group), single items at the head and tail of its run.
 __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const int32_t *perm,
                                                        const int32_t *cnt_sorted,
                                                        const int64_t *slice_ptr,
@@ -251,6 +254,9 @@ __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const in
                                                        int nr, int ne, int na, int32_t lo,
                                                        int32_t hi, int32_t *keys,
                                                        uint64_t *vals) {
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    typedef unsigned long long v2u __attribute__((ext_vector_type(2)));
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;
     const int32_t r = perm[slot];
@@ -260,19 +266,61 @@ __global__ __launch_bounds__(256) void k_expand_range(const RayDesc rd, const in
     const int lane = (int)(slot & 63);
     const int64_t nslot = natural_slot(rd, slot, r);
     const uint64_t ns = (uint64_t)(uint32_t)nslot;
+    const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+    const v4f *lp = (const v4f *)(len + base) + lane;
     int64_t dst = crow[nslot];
     int32_t v = 0;
-    for (int j = 0; j < c; j++) {
-        const int64_t i = sell_index(base, lane, j);
-        const int cd = code[i];
-        const float l = decode_entry(cd, len[i], v, na, ne * na);
-        if (cd == kCodeEsc) continue;
-        const int32_t k = seg_key(rd, r, v, nr, ne, na);
-        if (k >= lo && k < hi) {
-            keys[dst] = k;
-            vals[dst] = ns | ((uint64_t)__float_as_uint(l) << 32);
-            dst++;
+    int nbuf = 0;
+    int32_t k0 = 0, k1 = 0, k2 = 0, k3 = 0;
+    uint64_t u0 = 0, u1 = 0, u2 = 0, u3 = 0;
+    const int nq = (c + 3) >> 2;
+    for (int q = 0; q < nq; q++) {
+        const uint32_t cw = cp[(int64_t)q * kWave];
+        const v4f lq = lp[(int64_t)q * kWave];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (4 * q + e >= c) break;
+            const int cd = (cw >> (8 * e)) & 255;
+            const float l = decode_entry(cd, lq[e], v, na, ne * na);
+            if (cd == kCodeEsc) continue;
+            const int32_t k = seg_key(rd, r, v, nr, ne, na);
+            if (k < lo || k >= hi) continue;
+            const uint64_t u = ns | ((uint64_t)__float_as_uint(l) << 32);
+            if (nbuf == 0 && (dst & 3) != 0) {  // head of the run, before alignment
+                keys[dst] = k;
+                vals[dst] = u;
+                dst++;
+                continue;
+            }
+            k0 = nbuf == 0 ? k : k0;
+            k1 = nbuf == 1 ? k : k1;
+            k2 = nbuf == 2 ? k : k2;
+            k3 = nbuf == 3 ? k : k3;
+            u0 = nbuf == 0 ? u : u0;
+            u1 = nbuf == 1 ? u : u1;
+            u2 = nbuf == 2 ? u : u2;
+            u3 = nbuf == 3 ? u : u3;
+            if (++nbuf == 4) {
+                *reinterpret_cast<v4i *>(keys + dst) = v4i{k0, k1, k2, k3};
+                *reinterpret_cast<v2u *>(vals + dst) = v2u{u0, u1};
+                *reinterpret_cast<v2u *>(vals + dst + 2) = v2u{u2, u3};
+                dst += 4;
+                nbuf = 0;
+            }
         }
+    }
+    // the tail
+    if (nbuf > 0) {
+        keys[dst] = k0;
+        vals[dst] = u0;
+    }
+    if (nbuf > 1) {
+        keys[dst + 1] = k1;
+        vals[dst + 1] = u1;
+    }
+    if (nbuf > 2) {
+        keys[dst + 2] = k2;
+        vals[dst + 2] = u2;
     }
 }
 
