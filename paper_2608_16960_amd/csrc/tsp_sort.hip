@@ -194,13 +194,21 @@ __global__ __launch_bounds__(256) void k_key_hist(const RayDesc rd, const int32_
             const int c = cnt_sorted[slot];
             const int64_t base = slice_ptr[slot >> 6];
             const int lane = (int)(slot & 63);
+            const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+            const float4 *lp = (const float4 *)(len + base) + lane;
             int32_t v = 0;
-            for (int j = 0; j < c; j++) {
-                const int64_t i = sell_index(base, lane, j);
-                const int cd = code[i];
-                decode_entry(cd, len[i], v, na, ne * na);
-                if (cd == kCodeEsc) continue;
-                atomicAdd(&h[seg_key(rd, r, v, nr, ne, na) >> shift], 1u);
+            for (int q = 0; q < ((c + 3) >> 2); q++) {
+                const uint32_t cw = cp[(int64_t)q * kWave];
+                const float4 lq = lp[(int64_t)q * kWave];
+                const float la[4] = {lq.x, lq.y, lq.z, lq.w};
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    if (4 * q + e >= c) break;
+                    const int cd = (cw >> (8 * e)) & 255;
+                    decode_entry(cd, la[e], v, na, ne * na);
+                    if (cd == kCodeEsc) continue;
+                    atomicAdd(&h[seg_key(rd, r, v, nr, ne, na) >> shift], 1u);
+                }
             }
         }
     }
@@ -226,15 +234,23 @@ __global__ __launch_bounds__(256) void k_count_range(const RayDesc rd, const int
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
     const int64_t nslot = natural_slot(rd, slot, r);
+    const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+    const float4 *lp = (const float4 *)(len + base) + lane;
     int n = 0;
     int32_t v = 0;
-    for (int j = 0; j < c; j++) {
-        const int64_t i = sell_index(base, lane, j);
-        const int cd = code[i];
-        decode_entry(cd, len[i], v, na, ne * na);
-        if (cd == kCodeEsc) continue;
-        const int32_t k = seg_key(rd, r, v, nr, ne, na);
-        n += (k >= lo && k < hi);
+    for (int q = 0; q < ((c + 3) >> 2); q++) {
+        const uint32_t cw = cp[(int64_t)q * kWave];
+        const float4 lq = lp[(int64_t)q * kWave];
+        const float la[4] = {lq.x, lq.y, lq.z, lq.w};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (4 * q + e >= c) break;
+            const int cd = (cw >> (8 * e)) & 255;
+            decode_entry(cd, la[e], v, na, ne * na);
+            if (cd == kCodeEsc) continue;
+            const int32_t k = seg_key(rd, r, v, nr, ne, na);
+            n += (k >= lo && k < hi);
+        }
     }
     cnt_ray[nslot] = n;
 }
