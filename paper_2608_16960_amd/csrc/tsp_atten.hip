@@ -29,6 +29,8 @@ namespace {
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // s[b][v] = sigma[v] * rho[b][v]
 __global__ void k_atten_s(const float *sigma, const float *rho, int64_t V, int64_t n, float *s) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,15 +77,23 @@ __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ p
     const int c = cnt_sorted[slot];
     const int64_t base = slice_ptr[slot >> 6];
     const int lane = (int)(slot & 63);
+    const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+    const v4f *lp = (const v4f *)(len + base) + lane;
     float T = 0.0f, acc = 0.0f;
     int32_t v = 0;
-    for (int j = 0; j < c; j++) {
-        const int64_t i = sell_index(base, lane, j);
-        const int cd = __builtin_nontemporal_load(code + i);
-        const float l = decode_entry(cd, __builtin_nontemporal_load(len + i), v, na, nena);
-        if (cd == kCodeEsc) continue;
-        T = fmaf(s[v], l, T);
-        acc = fmaf(w[v] * expf(-T), l, acc);
+    for (int q = 0; q < ((c + 3) >> 2); q++) {
+        const uint32_t cw = __builtin_nontemporal_load(cp + (int64_t)q * kWave);
+        const v4f lq = __builtin_nontemporal_load(lp + (int64_t)q * kWave);
+        const float la[4] = {lq[0], lq[1], lq[2], lq[3]};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (4 * q + e >= c) break;
+            const int cd = (cw >> (8 * e)) & 255;
+            const float l = decode_entry(cd, la[e], v, na, nena);
+            if (cd == kCodeEsc) continue;
+            T = fmaf(s[v], l, T);
+            acc = fmaf(w[v] * expf(-T), l, acc);
+        }
     }
     y[ray] = acc;
 }
@@ -107,53 +117,65 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
     const int64_t base = slice_ptr[slot >> 6];
     const float g = (ray >= 0) ? gy[ray] : 0.0f;
     // pass 1: the ray's measurement (the total that the suffix sums start from)
+    const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+    const v4f *lp = (const v4f *)(len + base) + lane;
     float T = 0.0f, yr = 0.0f;
     int32_t vr = 0;
-    for (int j = 0; j < c; j++) {
-        const int64_t i = sell_index(base, lane, j);
-        const int cd = code[i];
-        const float l = decode_entry(cd, len[i], vr, na, nena);
-        if (cd == kCodeEsc) continue;
-        T = fmaf(s[vr], l, T);
-        yr = fmaf(w[vr] * expf(-T), l, yr);
+    for (int q = 0; q < ((c + 3) >> 2); q++) {
+        const uint32_t cw = cp[(int64_t)q * kWave];
+        const v4f lq = lp[(int64_t)q * kWave];
+        const float la[4] = {lq[0], lq[1], lq[2], lq[3]};
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            if (4 * q + e >= c) break;
+            const int cd = (cw >> (8 * e)) & 255;
+            const float l = decode_entry(cd, la[e], vr, na, nena);
+            if (cd == kCodeEsc) continue;
+            T = fmaf(s[vr], l, T);
+            yr = fmaf(w[vr] * expf(-T), l, yr);
+        }
     }
     // pass 2: both gradient terms of every segment, merged across the wavefront
     T = 0.0f;
     float prefix = 0.0f;
     vr = 0;
-    for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
-        int v = -1;
-        float a = 0.0f, bterm = 0.0f, l = 0.0f;
-        if (j < c) {
-            const int64_t i = sell_index(base, lane, j);
-            const int cd = code[i];
-            l = decode_entry(cd, len[i], vr, na, nena);
-            if (cd != kCodeEsc) v = vr;
-        }
-        if (v >= 0) {
-            T = fmaf(s[v], l, T);
-            const float E = expf(-T);
-            const float ck = w[v] * E * l;
-            a = g * E * l;
-            bterm = -g * l * (yr - prefix);
-            prefix += ck;
-        }
-        uint64_t pend = __ballot(v >= 0);
-        while (pend) {
-            const int leader = __ffsll((unsigned long long)pend) - 1;
-            const int v0 = __shfl(v, leader, kWave);
-            const bool mine = (v == v0);
-            float sa = mine ? a : 0.0f, sb = mine ? bterm : 0.0f;
+    for (int q = 0; q < (m >> 2); q++) {  // m is uniform over the wavefront, a multiple of 4
+        const uint32_t cw = cp[(int64_t)q * kWave];
+        const v4f lq = lp[(int64_t)q * kWave];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                sa += __shfl_xor(sa, o, kWave);
-                sb += __shfl_xor(sb, o, kWave);
+        for (int e = 0; e < 4; e++) {
+            int v = -1;
+            float a = 0.0f, bterm = 0.0f, l = 0.0f;
+            if (4 * q + e < c) {
+                const int cd = (cw >> (8 * e)) & 255;
+                l = decode_entry(cd, lq[e], vr, na, nena);
+                if (cd != kCodeEsc) v = vr;
             }
-            if (lane == leader) {
-                atomicAdd(gw + v0, sa);
-                atomicAdd(gs + v0, sb);
+            if (v >= 0) {
+                T = fmaf(s[v], l, T);
+                const float E = expf(-T);
+                const float ck = w[v] * E * l;
+                a = g * E * l;
+                bterm = -g * l * (yr - prefix);
+                prefix += ck;
             }
-            pend &= ~__ballot(mine);
+            uint64_t pend = __ballot(v >= 0);
+            while (pend) {
+                const int leader = __ffsll((unsigned long long)pend) - 1;
+                const int v0 = __shfl(v, leader, kWave);
+                const bool mine = (v == v0);
+                float sa = mine ? a : 0.0f, sb = mine ? bterm : 0.0f;
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) {
+                    sa += __shfl_xor(sa, o, kWave);
+                    sb += __shfl_xor(sb, o, kWave);
+                }
+                if (lane == leader) {
+                    atomicAdd(gw + v0, sa);
+                    atomicAdd(gs + v0, sb);
+                }
+                pend &= ~__ballot(mine);
+            }
         }
     }
 }
