@@ -289,31 +289,37 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
 #pragma unroll
     for (int b = 0; b < NB; b++) yv[b] = (ray >= 0 && b < nb) ? y[b * R + ray] : 0.0f;
     int32_t vraw = 0;
-    for (int j = 0; j < m; j++) {  // m is uniform over the wavefront
-        int v = -1;
-        float l = 0.0f;
-        if (j < c) {
-            const int64_t i = sell_index(base, lane, j);
-            const int cd = code[i];
-            l = decode_entry(cd, len[i], vraw, na, nena);
-            v = (cd == kCodeEsc) ? -1 : fb + vraw;
-        }
-        float cb[NB];
+    const uint32_t *cp = (const uint32_t *)(code + base) + lane;
+    const v4f *lp = (const v4f *)(len + base) + lane;
+    for (int q = 0; q < (m >> 2); q++) {  // m is uniform over the wavefront, a multiple of 4
+        const uint32_t cw = __builtin_nontemporal_load(cp + (int64_t)q * kWave);
+        const v4f lq = ld_nt(lp + (int64_t)q * kWave);
 #pragma unroll
-        for (int b = 0; b < NB; b++) cb[b] = (v >= 0) ? l * yv[b] : 0.0f;
-        uint64_t pend = __ballot(v >= 0);
-        while (pend) {
-            const int leader = __ffsll((unsigned long long)pend) - 1;
-            const int v0 = __shfl(v, leader, kWave);
-            const bool mine = (v == v0);
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                float sb = mine ? cb[b] : 0.0f;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) sb += __shfl_xor(sb, o, kWave);
-                if (lane == leader && b < nb) atomicAdd(x + b * V + v0, sb);
+        for (int e = 0; e < 4; e++) {
+            int v = -1;
+            float l = 0.0f;
+            if (4 * q + e < c) {
+                const int cd = (cw >> (8 * e)) & 255;
+                l = decode_entry(cd, lq[e], vraw, na, nena);
+                v = (cd == kCodeEsc) ? -1 : fb + vraw;
             }
-            pend &= ~__ballot(mine);
+            float cb[NB];
+#pragma unroll
+            for (int b = 0; b < NB; b++) cb[b] = (v >= 0) ? l * yv[b] : 0.0f;
+            uint64_t pend = __ballot(v >= 0);
+            while (pend) {
+                const int leader = __ffsll((unsigned long long)pend) - 1;
+                const int v0 = __shfl(v, leader, kWave);
+                const bool mine = (v == v0);
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    float sb = mine ? cb[b] : 0.0f;
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) sb += __shfl_xor(sb, o, kWave);
+                    if (lane == leader && b < nb) atomicAdd(x + b * V + v0, sb);
+                }
+                pend &= ~__ballot(mine);
+            }
         }
     }
 }
