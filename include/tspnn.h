@@ -46,7 +46,7 @@ typedef enum tspnn_status {
     TSPNN_OK = 0,
     TSPNN_E_INVALID = 1,     /* bad argument */
     TSPNN_E_HIP = 3,         /* HIP runtime failure */
-    TSPNN_E_UNSUPPORTED = 5  /* shape the kernels do not handle (e.g. D2 % 16 != 0) */
+    TSPNN_E_UNSUPPORTED = 5  /* shape the kernels do not handle (e.g. D2 % 32 != 0) */
 } tspnn_status;
 
 /* ------------------------------------------------------------------ vectors */
@@ -116,7 +116,7 @@ tspnn_status tspnn_conv_in_fwd(const float *x, int32_t N, int32_t D0, int32_t D1
                                const float *w, const float *b, uint16_t *y, void *stream);
 
 /* 32 -> 32 layer on MFMA: y = relu(conv(x) + b), x, y bfloat16 [..][32],
- * w bfloat16 [27][32][32] (out, in), b float32 [32].  D2 % 16 == 0. */
+ * w bfloat16 [27][32][32] (out, in), b float32 [32].  D2 % 32 == 0, D2 <= 128. */
 tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
                             const uint16_t *w, const float *b, uint16_t *y, void *stream);
 
@@ -131,7 +131,7 @@ tspnn_status tspnn_conv_out_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_
  * Backward of a 32 -> 32 layer with respect to its input, fused with the ReLU
  * of the layer below:  dz_in = (conv^T(dz_out; w)) * (act_in > 0),
  * where conv^T is the adjoint of the layer's convolution.  dz_out, act_in,
- * dz_in bfloat16 [..][32]; w as in tspnn_conv_fwd.  D2 % 16 == 0.
+ * dz_in bfloat16 [..][32]; w as in tspnn_conv_fwd.  D2 % 32 == 0, D2 <= 128.
  */
 tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, int32_t D1,
                                  int32_t D2, const uint16_t *w, const uint16_t *act_in,
@@ -139,7 +139,7 @@ tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, 
 
 /* Weight / bias gradients of a 32 -> 32 layer on MFMA:
  * dw[t][o][i] = sum_p dz[p][o] x[p + off(t)][i], db[o] = sum_p dz[p][o].
- * dw float32 [27][32][32]; db float32 [32] (may be NULL).  D2 % 16 == 0. */
+ * dw float32 [27][32][32]; db float32 [32] (may be NULL).  D2 % 32 == 0, D2 <= 128. */
 tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t D0,
                                    int32_t D1, int32_t D2, float *dw, float *db, void *work,
                                    void *stream);

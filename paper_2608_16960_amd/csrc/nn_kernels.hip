@@ -6,9 +6,10 @@
 //     channels, K = 32 input channels of one of the 27 taps; each lane loads
 //     8 consecutive channels of one voxel (16 bytes, channels last);
 //   weight gradient: M = 16 output channels, N = 16 input channels, K = 32
-//     voxels of one azimuth row; rows of dz and of the (shifted) neighbour
-//     rows of x are staged transposed in LDS so that each lane reads its 8
-//     consecutive voxels with one 16-byte LDS load.
+//     voxels of one azimuth row; rows of dz and the neighbour rows of x are
+//     staged transposed in LDS so that each lane reads its 8 consecutive
+//     voxels with one 16-byte LDS load (shifted by one azimuth: two 4-byte
+//     neighbours and funnel shifts).
 // MFMA lane layout used (16x16x32, wave64): lane l supplies A[l % 16][8 (l/16)
 // .. +7] and B[8 (l/16) .. +7][l % 16] and receives D[4 (l/16) + i][l % 16],
 // i = 0..3.
@@ -240,18 +241,28 @@ __global__ __launch_bounds__(256) void k_conv_out_fwd(const uint16_t *x, Dims d,
     if (p >= d.vox()) return;
     int n, i, j, k;
     unflatten(d, p, n, i, j, k);
-    float a = b[0] + (res ? res[p] : 0.0f);
+    // eight partial sums (one per channel of a 16-byte group) keep the
+    // multiply-adds independent; neighbours outside the grid read the voxel
+    // itself and count zero
+    float acc[8];
+#pragma unroll
+    for (int e = 0; e < 8; e++) acc[e] = 0.0f;
+#pragma unroll 3
     for (int t = 0; t < 27; t++) {
         const int64_t q = neighbour(d, n, i, j, k, t);
-        if (q < 0) continue;
-        const u16x8 *src = (const u16x8 *)(x + q * C);
+        const float on = q >= 0 ? 1.0f : 0.0f;
+        const u16x8 *src = (const u16x8 *)(x + (q >= 0 ? q : p) * C);
 #pragma unroll
         for (int c8 = 0; c8 < 4; c8++) {
             const u16x8 v = src[c8];
 #pragma unroll
-            for (int e = 0; e < 8; e++) a = fmaf(ws[t * C + c8 * 8 + e], bf2f(v[e]), a);
+            for (int e = 0; e < 8; e++)
+                acc[e] = fmaf(ws[t * C + c8 * 8 + e] * on, bf2f(v[e]), acc[e]);
         }
     }
+    float a = b[0] + (res ? res[p] : 0.0f);
+#pragma unroll
+    for (int e = 0; e < 8; e++) a += acc[e];
     out[p] = a;
 }
 
@@ -385,58 +396,80 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// EPI 0: y = relu(acc + b); EPI 1: y = acc * (mask > 0).  One wavefront per 64
-// voxels of an azimuth row (4 M tiles of 16), all 32 output channels (2 N tiles).
-template <int EPI>
-__global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ x, Dims d,
-                                                   const uint16_t *__restrict__ w,
-                                                   const float *__restrict__ bias,
-                                                   const uint16_t *__restrict__ mask,
-                                                   uint16_t *__restrict__ y) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
-    const int nchunk = (d.D2 + 63) / 64;
-    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
-    if (wave >= rows * nchunk) return;  // uniform per wave
-    const int64_t row = wave / nchunk;
-    const int a0 = (int)(wave % nchunk) * 64;
-    const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1), n = (int)(row / d.D1 / d.D0);
-    const int ntile = min(4, (d.D2 - a0) / 16);
+// The same layer with its inputs staged in LDS.  A workgroup of four
+// wavefronts takes four consecutive e-rows (j0 .. j0+3) of one (n, i) and up
+// to 64 azimuths a0 .. a0+63.  It stages the 3 x 6 neighbour rows those
+// outputs read, each with one azimuth of circular halo on both sides (66
+// voxels of 64 bytes; rows outside the grid as zeros), then wavefront w
+// computes e-row j0 + w: 27 taps of 8 MFMAs with no branch between them, the
+// voxel fragments read from LDS and the weight fragments (which every
+// workgroup shares, so they stay in cache) loaded one tap ahead.
+// A staged voxel r keeps its four 16-byte channel groups c at position
+// c ^ s(r), s(r) = ((r >> 1) ^ (r >> 3)) & 3: 8 (16) consecutive voxels then
+// cover all 32 (64) LDS banks.
+constexpr int kTileRows = 4;                    // e-rows per workgroup
+constexpr int kStageRows = 3 * (kTileRows + 2);  // (dr, de) rows staged
+constexpr int kStageVox = 66;                    // 64 azimuths + halo
+
+__device__ __forceinline__ int swz_off(int r, int c) {  // bf16 elements
+    return (r * 4 + (c ^ (((r >> 1) ^ (r >> 3)) & 3))) * 8;
+}
+
+template <int EPI, int NT>
+__device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const Dims &d,
+                                          const uint16_t *__restrict__ w,
+                                          const float *__restrict__ bias,
+                                          const uint16_t *__restrict__ mask,
+                                          uint16_t *__restrict__ y, uint16_t *xs, int n, int i,
+                                          int j0, int a0) {
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    f32x4 acc[4][2];
+    constexpr int nq = NT * 16 + 2;  // staged voxels per row
+    for (int e = tid; e < kStageRows * nq * 4; e += 256) {
+        const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
+        const int ii = i + row / (kTileRows + 2) - 1, jj = j0 - 1 + row % (kTileRows + 2);
+        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1) {
+            int a = a0 - 1 + q;
+            a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
+            const int64_t p = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + a;
+            v = *reinterpret_cast<const u16x8 *>(x + p * C + 8 * c);
+        }
+        *reinterpret_cast<u16x8 *>(&xs[swz_off(row * kStageVox + q, c)]) = v;
+    }
+    const int j = j0 + wv;
+    // weight fragments of tap 0 (output channels m and 16 + m)
+    const uint16_t *wl = w + m * C + 8 * kq;
+    bf16x8 b0[2], b1[2];
+    b0[0] = ld8(wl);
+    b1[0] = ld8(wl + 16 * C);
+    __syncthreads();
+    if (j >= d.D1) return;  // uniform per wave; no barrier follows
+    f32x4 acc[NT][2];
 #pragma unroll
-    for (int t = 0; t < 4; t++)
+    for (int t = 0; t < NT; t++)
 #pragma unroll
         for (int u = 0; u < 2; u++) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int dr = -1; dr <= 1; dr++) {
-        const int ii = i + dr;
-        if (ii < 0 || ii >= d.D0) continue;
-        for (int de = -1; de <= 1; de++) {
-            const int jj = j + de;
-            if (jj < 0 || jj >= d.D1) continue;
-            const int64_t rb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
 #pragma unroll
-            for (int da = -1; da <= 1; da++) {
-                const int tap = (dr + 1) * 9 + (de + 1) * 3 + (da + 1);
-                const bf16x8 b0 = ld8(w + ((int64_t)tap * C + m) * C + 8 * kq);
-                const bf16x8 b1 = ld8(w + ((int64_t)tap * C + 16 + m) * C + 8 * kq);
+    for (int tap = 0; tap < 27; tap++) {
+        const int cur = tap & 1;
+        if (tap + 1 < 27) {
+            b0[cur ^ 1] = ld8(wl + (tap + 1) * C * C);
+            b1[cur ^ 1] = ld8(wl + (tap + 1) * C * C + 16 * C);
+        }
+        const int dr = tap / 9, de = (tap / 3) % 3, da = tap % 3;  // offsets + 1
+        const int row = dr * (kTileRows + 2) + wv + de;
 #pragma unroll
-                for (int t = 0; t < 4; t++) {
-                    if (t < ntile) {
-                        int a = a0 + 16 * t + m + da;
-                        a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
-                        const bf16x8 av = ld8(x + (rb + a) * C + 8 * kq);
-                        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0, acc[t][0], 0, 0, 0);
-                        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1, acc[t][1], 0, 0, 0);
-                    }
-                }
-            }
+        for (int t = 0; t < NT; t++) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
+                &xs[swz_off(row * kStageVox + 16 * t + m + da, kq)]);
+            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0[cur], acc[t][0], 0, 0, 0);
+            acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1[cur], acc[t][1], 0, 0, 0);
         }
     }
-    const int64_t ob = row * d.D2;
+    const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2;
 #pragma unroll
-    for (int t = 0; t < 4; t++) {
-        if (t >= ntile) continue;
+    for (int t = 0; t < NT; t++) {
 #pragma unroll
         for (int u = 0; u < 2; u++) {
             const int o = 16 * u + m;
@@ -455,86 +488,131 @@ __global__ __launch_bounds__(256) void k_conv_mfma(const uint16_t *__restrict__ 
     }
 }
 
-// Weight gradient of a 32 -> 32 layer.  A workgroup walks rows r = blockIdx.x,
-// blockIdx.x + gridDim.x, ...; per row it stages dz transposed ([o][a]) and, for
-// each of the 9 (dr, de) neighbour rows, three azimuth-shifted transposed
-// copies of x ([da][i][a] = x[(a + da) mod D2][i]).  Wave w owns the taps
-// t = w, w + 4, ... (at most 7) and keeps their 32x32 sums in registers; at the
-// end every workgroup writes its partial sums (reduced later in fixed order).
-constexpr int kMaxD2 = 128;
-constexpr int kLdsStride = kMaxD2 + 8;  // padded row stride (bf16 elements)
+template <int EPI>
+__global__ __launch_bounds__(256) void k_conv_lds(const uint16_t *__restrict__ x, Dims d,
+                                                  const uint16_t *__restrict__ w,
+                                                  const float *__restrict__ bias,
+                                                  const uint16_t *__restrict__ mask,
+                                                  uint16_t *__restrict__ y) {
+    __shared__ __attribute__((aligned(16))) uint16_t xs[kStageRows * kStageVox * C];
+    const int nchunk = (d.D2 + 63) / 64, njb = (d.D1 + kTileRows - 1) / kTileRows;
+    int64_t b = blockIdx.x;
+    const int ac = (int)(b % nchunk);
+    b /= nchunk;
+    const int jb = (int)(b % njb);
+    b /= njb;
+    const int i = (int)(b % d.D0), n = (int)(b / d.D0);
+    const int a0 = ac * 64, j0 = jb * kTileRows;
+    if (d.D2 - a0 >= 64)  // uniform over the workgroup
+        conv_tile<EPI, 4>(x, d, w, bias, mask, y, xs, n, i, j0, a0);
+    else  // D2 % 32 == 0: the last chunk holds 32 azimuths
+        conv_tile<EPI, 2>(x, d, w, bias, mask, y, xs, n, i, j0, a0);
+}
 
-__global__ __launch_bounds__(256) void k_conv_wgrad_mfma(const uint16_t *__restrict__ x,
-                                                         const uint16_t *__restrict__ dz, Dims d,
-                                                         float *__restrict__ part) {
-    __shared__ __attribute__((aligned(16))) uint16_t dzT[C * kLdsStride];
-    __shared__ __attribute__((aligned(16))) uint16_t xT[3][C * kLdsStride];
+constexpr int kMaxD2 = 128;  // widest azimuth row of the MFMA layers
+
+// Weight gradient of a 32 -> 32 layer, tiled.  A tile is two e-rows (j0,
+// j0 + 1) of one (n, i); a workgroup takes tiles blockIdx.x, + gridDim.x, ...
+// and stages per tile, transposed to [channel][azimuth], the two rows of dz
+// and the 3 x 4 neighbour rows of x they meet (rows outside the grid as
+// zeros).  A staged x row keeps azimuth a at position a + 8, with a - 1 of
+// a = 0 at 7 and a + 1 of a = D2 - 1 at D2 + 8, so that the operand of shift
+// 0 is one aligned 16-byte read and those of shifts -1 and +1 follow from it
+// and two 4-byte neighbours by funnel shifts.  Staging stores pack two
+// azimuths of one channel into 4 bytes; channel rows have an odd number of
+// 16-byte units, so the 16 rows an MFMA reads fall in different banks.
+// Wavefront w owns output channels 16 (w >> 1) .. +15 and input channels
+// 16 (w & 1) .. +15 of all 27 taps; its sums stay in registers until the
+// workgroup's last tile, then go out as its partial sums.
+constexpr int kWRows = 2;                  // e-rows per tile
+constexpr int kWStage = 3 * (kWRows + 2);  // staged x rows per tile
+
+__device__ __forceinline__ uint32_t pack_bf16x2(uint16_t lo, uint16_t hi) {
+    return (uint32_t)lo | ((uint32_t)hi << 16);
+}
+
+__global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
+                                                          const uint16_t *__restrict__ dz, Dims d,
+                                                          float *__restrict__ part) {
+    extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
+    const int D2 = d.D2;
+    const int sx = D2 + 24, sz = D2 + 8;  // channel-row strides (bf16 elements)
+    uint16_t *xT = lds;                   // [kWStage][C][sx]
+    uint16_t *zT = lds + kWStage * C * sx;  // [kWRows][C][sz]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
-    const int D2 = d.D2;
-    const int nks = D2 / 32;
-    f32x4 acc[7][2][2];
+    const int ot = wv >> 1, ct = wv & 1;  // output / input channel tiles
+    const int njb = (d.D1 + kWRows - 1) / kWRows;
+    const int64_t ntiles = (int64_t)d.N * d.D0 * njb;
+    const int nkb = D2 / 32;
+    f32x4 acc[27];
 #pragma unroll
-    for (int s = 0; s < 7; s++)
-#pragma unroll
-        for (int a = 0; a < 2; a++)
-#pragma unroll
-            for (int b = 0; b < 2; b++) acc[s][a][b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    for (int64_t row = blockIdx.x; row < rows; row += gridDim.x) {
-        const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
-        const int n = (int)(row / d.D1 / d.D0);
-        __syncthreads();
-        for (int e = tid; e < D2 * 4; e += 256) {  // 8 channels of one voxel per item
-            const int a = e >> 2, c8 = (e & 3) * 8;
-            const u16x8 v = *reinterpret_cast<const u16x8 *>(dz + (row * D2 + a) * C + c8);
-#pragma unroll
-            for (int q = 0; q < 8; q++) dzT[(c8 + q) * kLdsStride + a] = v[q];
-        }
-        for (int dr = -1; dr <= 1; dr++) {
-            const int ii = i + dr;
-            const bool okr = ii >= 0 && ii < d.D0;
-            for (int de = -1; de <= 1; de++) {
-                const int jj = j + de;
-                if (!okr || jj < 0 || jj >= d.D1) continue;  // uniform over the block
+    for (int t = 0; t < 27; t++) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int j0 = (int)(tile % njb) * kWRows;
+        const int i = (int)((tile / njb) % d.D0), n = (int)(tile / njb / d.D0);
+        __syncthreads();  // the previous tile's reads are done
+        // x rows (i + s / 4 - 1, j0 - 1 + s % 4); pairs of azimuths at positions
+        // 6 + 2 pi, pi = 0 .. D2 / 2 + 1 (azimuths 2 pi - 2, 2 pi - 1 mod D2)
+        const int npx = D2 / 2 + 2;
+        for (int e = tid; e < kWStage * 4 * npx; e += 256) {
+            const int pi = e % npx, c8 = ((e / npx) & 3) * 8, s = e / npx / 4;
+            const int ii = i + s / (kWRows + 2) - 1, jj = j0 - 1 + s % (kWRows + 2);
+            u16x8 v0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, v1 = v0;
+            if (ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1) {
+                int a = 2 * pi - 2;
+                a = a < 0 ? a + D2 : (a >= D2 ? a - D2 : a);
+                const int a1 = a + 1 == D2 ? 0 : a + 1;
                 const int64_t rb = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * D2;
-                __syncthreads();
-                for (int e = tid; e < D2 * 4; e += 256) {
-                    const int a = e >> 2, c8 = (e & 3) * 8;
-                    const u16x8 v = *reinterpret_cast<const u16x8 *>(x + (rb + a) * C + c8);
+                v0 = *reinterpret_cast<const u16x8 *>(x + (rb + a) * C + c8);
+                v1 = *reinterpret_cast<const u16x8 *>(x + (rb + a1) * C + c8);
+            }
+            uint32_t *dst = reinterpret_cast<uint32_t *>(xT + (s * C + c8) * sx + 6 + 2 * pi);
 #pragma unroll
-                    for (int s = 0; s < 3; s++) {  // copy for shift da = s - 1
-                        int ap = a - (s - 1);
-                        ap = ap < 0 ? ap + D2 : (ap >= D2 ? ap - D2 : ap);
+            for (int q = 0; q < 8; q++) dst[q * (sx / 2)] = pack_bf16x2(v0[q], v1[q]);
+        }
+        // dz rows j0, j0 + 1 at positions 0 .. D2 - 1
+        const int npz = D2 / 2;
+        for (int e = tid; e < kWRows * 4 * npz; e += 256) {
+            const int pi = e % npz, c8 = ((e / npz) & 3) * 8, r = e / npz / 4;
+            u16x8 v0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, v1 = v0;
+            if (j0 + r < d.D1) {
+                const int64_t rb = (((int64_t)n * d.D0 + i) * d.D1 + j0 + r) * D2;
+                v0 = *reinterpret_cast<const u16x8 *>(dz + (rb + 2 * pi) * C + c8);
+                v1 = *reinterpret_cast<const u16x8 *>(dz + (rb + 2 * pi + 1) * C + c8);
+            }
+            uint32_t *dst = reinterpret_cast<uint32_t *>(zT + (r * C + c8) * sz + 2 * pi);
 #pragma unroll
-                        for (int q = 0; q < 8; q++) xT[s][(c8 + q) * kLdsStride + ap] = v[q];
-                    }
-                }
-                __syncthreads();
+            for (int q = 0; q < 8; q++) dst[q * (sz / 2)] = pack_bf16x2(v0[q], v1[q]);
+        }
+        __syncthreads();
+        for (int r = 0; r < kWRows; r++) {
+            if (j0 + r >= d.D1) break;  // uniform over the workgroup; zeros otherwise
+            for (int kb = 0; kb < nkb; kb++) {
+                const int a = 32 * kb + 8 * kq;
+                const bf16x8 A = *reinterpret_cast<const bf16x8 *>(
+                    zT + (r * C + 16 * ot + m) * sz + a);
 #pragma unroll
-                for (int s = 0; s < 3; s++) {
-                    const int tap = (dr + 1) * 9 + (de + 1) * 3 + s;
-                    if ((tap & 3) != wv) continue;  // uniform per wave
-                    const int slot = tap >> 2;
-                    for (int ks = 0; ks < nks; ks++) {
-                        const int a = 32 * ks + 8 * kq;
-                        bf16x8 A[2], Bv[2];
-#pragma unroll
-                        for (int u = 0; u < 2; u++) {
-                            A[u] = *reinterpret_cast<const bf16x8 *>(&dzT[(16 * u + m) * kLdsStride + a]);
-                            Bv[u] = *reinterpret_cast<const bf16x8 *>(&xT[s][(16 * u + m) * kLdsStride + a]);
-                        }
-#pragma unroll
-                        for (int sl = 0; sl < 7; sl++) {
-                            if (sl != slot) continue;
-#pragma unroll
-                            for (int mu = 0; mu < 2; mu++)
-#pragma unroll
-                                for (int nu = 0; nu < 2; nu++)
-                                    acc[sl][mu][nu] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                        A[mu], Bv[nu], acc[sl][mu][nu], 0, 0, 0);
-                        }
-                    }
+                for (int dd = 0; dd < 9; dd++) {  // (dr, de) offsets + 1
+                    const int row = (dd / 3) * (kWRows + 2) + r + dd % 3;
+                    const uint16_t *bp = xT + (row * C + 16 * ct + m) * sx + a + 8;
+                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                    const u32x4 c = *reinterpret_cast<const u32x4 *>(bp);
+                    const uint32_t lo = *reinterpret_cast<const uint32_t *>(bp - 2);
+                    const uint32_t hi = *reinterpret_cast<const uint32_t *>(bp + 8);
+                    const uint32_t f0 = __builtin_amdgcn_alignbit(c[0], lo, 16);
+                    const uint32_t f1 = __builtin_amdgcn_alignbit(c[1], c[0], 16);
+                    const uint32_t f2 = __builtin_amdgcn_alignbit(c[2], c[1], 16);
+                    const uint32_t f3 = __builtin_amdgcn_alignbit(c[3], c[2], 16);
+                    const uint32_t f4 = __builtin_amdgcn_alignbit(hi, c[3], 16);
+                    const u32x4 bm = u32x4{f0, f1, f2, f3}, bpl = u32x4{f1, f2, f3, f4};
+                    const int t0 = dd * 3;
+                    acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        A, __builtin_bit_cast(bf16x8, bm), acc[t0], 0, 0, 0);
+                    acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        A, __builtin_bit_cast(bf16x8, c), acc[t0 + 1], 0, 0, 0);
+                    acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        A, __builtin_bit_cast(bf16x8, bpl), acc[t0 + 2], 0, 0, 0);
                 }
             }
         }
@@ -542,19 +620,16 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_mfma(const uint16_t *__restr
     // partial sums: part[blk][tap][o][i]
     float *pb = part + (int64_t)blockIdx.x * 27 * C * C;
 #pragma unroll
-    for (int sl = 0; sl < 7; sl++) {
-        const int tap = sl * 4 + wv;
-        if (tap >= 27) continue;
+    for (int t = 0; t < 27; t++)
 #pragma unroll
-        for (int mu = 0; mu < 2; mu++)
-#pragma unroll
-            for (int nu = 0; nu < 2; nu++)
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const int o = 16 * mu + 4 * kq + e, ci = 16 * nu + m;
-                    pb[((int64_t)tap * C + o) * C + ci] = acc[sl][mu][nu][e];
-                }
-    }
+        for (int e = 0; e < 4; e++) {
+            const int o = 16 * ot + 4 * kq + e, ci = 16 * ct + m;
+            pb[((int64_t)t * C + o) * C + ci] = acc[t][e];
+        }
+}
+
+size_t wgrad_lds_bytes(int D2) {
+    return sizeof(uint16_t) * ((size_t)kWStage * C * (D2 + 24) + (size_t)kWRows * C * (D2 + 8));
 }
 
 __global__ void k_flip(const uint16_t *w, uint16_t *wt) {
@@ -653,6 +728,12 @@ tspnn_status hipret(hipError_t e, const char *what) {
     return TSPNN_OK;
 }
 
+// workgroups of k_conv_lds: (n, i, block of e-rows, 64-azimuth chunk)
+unsigned conv_blocks(const Dims &d) {
+    return (unsigned)((int64_t)d.N * d.D0 * ((d.D1 + kTileRows - 1) / kTileRows) *
+                      ((d.D2 + 63) / 64));
+}
+
 tspnn_status mfma_dims(int N, int D0, int D1, int D2) {
     if (!dims_ok(N, D0, D1, D2)) return fail(TSPNN_E_INVALID, "dimensions must be positive");
     if (D2 % 32 != 0 || D2 > kMaxD2)
@@ -747,9 +828,8 @@ tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    const int64_t waves = (int64_t)N * D0 * D1 * ((D2 + 63) / 64);
-    hipLaunchKernelGGL(k_conv_mfma<0>, dim3(nblk(waves * 64, 256)), dim3(256), 0,
-                       (hipStream_t)stream, x, d, w, b, (const uint16_t *)nullptr, y);
+    hipLaunchKernelGGL(k_conv_lds<0>, dim3(conv_blocks(d)), dim3(256), 0, (hipStream_t)stream,
+                       x, d, w, b, (const uint16_t *)nullptr, y);
     return hipret(hipGetLastError(), "tspnn_conv_fwd");
 }
 
@@ -762,9 +842,8 @@ tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, 
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    const int64_t waves = (int64_t)N * D0 * D1 * ((D2 + 63) / 64);
-    hipLaunchKernelGGL(k_conv_mfma<1>, dim3(nblk(waves * 64, 256)), dim3(256), 0,
-                       (hipStream_t)stream, dz_out, d, w, (const float *)nullptr, act_in, dz_in);
+    hipLaunchKernelGGL(k_conv_lds<1>, dim3(conv_blocks(d)), dim3(256), 0, (hipStream_t)stream,
+                       dz_out, d, w, (const float *)nullptr, act_in, dz_in);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_data");
 }
 
@@ -777,10 +856,22 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
     if (s != TSPNN_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     Dims d{N, D0, D1, D2};
-    const int64_t rows = (int64_t)N * D0 * D1;
-    const int nb = wgrad_blocks(rows);
+    // tiles of two e-rows; never more workgroups than the workspace holds
+    // partial sums for (wgrad_blocks of the row count)
+    const int64_t tiles = (int64_t)N * D0 * ((D1 + kWRows - 1) / kWRows);
+    const int nb = wgrad_blocks(tiles);
     float *part = (float *)work;
-    hipLaunchKernelGGL(k_conv_wgrad_mfma, dim3(nb), dim3(256), 0, st, x, dz, d, part);
+    const size_t lds = wgrad_lds_bytes(D2);
+    static size_t lds_enabled = 0;  // dynamic LDS above the default needs opting in
+    if (lds > lds_enabled) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k_conv_wgrad_tiled,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)wgrad_lds_bytes(kMaxD2));
+        if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight (LDS size)");
+        lds_enabled = wgrad_lds_bytes(kMaxD2);
+    }
+    hipLaunchKernelGGL(k_conv_wgrad_tiled, dim3(nb), dim3(256), lds, st, x, dz,
+                       d, part);
     reduce_parts(part, nb, 27 * C * C, 27 * C * C, dw, part + (int64_t)nb * 27 * C * C, st);
     if (db) {
         const int64_t nv = d.vox();

@@ -71,7 +71,7 @@ def test_adam_matches_reference(nn):
     assert torch.equal(pb, p.to(torch.bfloat16))
 
 
-SHAPES = [(2, 5, 4, 64), (1, 3, 6, 32)]
+SHAPES = [(2, 5, 4, 64), (1, 3, 6, 32), (1, 2, 5, 96), (1, 3, 9, 128)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
