@@ -302,74 +302,107 @@ __global__ __launch_bounds__(256) void k_conv_out_bwd_data(const uint16_t *x, co
 
 constexpr int kChunk = 1024;  // voxels per block of the channel sums
 constexpr int kRowsPerBlk = 16;  // azimuth rows per block of the small weight gradients
-constexpr int kSub = 8;          // voxel subsets per block (threads per channel)
 
 // mode 0 (input layer):  part[blk][t*32+o] = sum_p dz[p][o] * xin[p + off(t)]
 //                        part[blk][864+o]  = sum_p dz[p][o]
 // mode 1 (output layer): part[blk][t*32+i] = sum_p dout[p] * x[p + off(t)][i]
 //                        part[blk][864]    = sum_p dout[p]
-// Thread (c, s) owns channel c and azimuth positions s, s + 8, ... of the
-// block's rows, with the 27 tap sums in registers: each gradient value is
-// loaded once per voxel, the single-channel operand is a broadcast load.  The
-// 8 subsets are added in a fixed order through LDS.
+// A block takes azimuth rows blk * kRowsPerBlk .. +kRowsPerBlk-1.  Thread
+// (lr, dd, g) takes rows lr, lr + 7, ... of them, the neighbour row dd =
+// (dr, de) of each and channels 8 g .. 8 g + 7: it walks the row's azimuths
+// with the neighbour row's values at a - 1, a and a + 1 (circular) in
+// registers, one new load per azimuth, and sums the three taps dd * 3 + da.
+// The 7 row lanes are added in a fixed order through LDS.
+constexpr int kRowLanes = 7;  // 7 x 36 threads
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_small_wgrad(const float *xin, const uint16_t *xb,
                                                      const uint16_t *dzb, const float *dout,
                                                      Dims d, float *part, int n_out) {
-    __shared__ float sh[kSub][28][C];
-    const int c = threadIdx.x % C, sub = threadIdx.x / C;
-    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowsPerBlk;
-    float acc[27], bacc = 0.0f;
+    __shared__ float sh[kRowLanes][28 * C];
+    const int tid = threadIdx.x;
+    const int lr = tid / 36, dd = (tid % 36) / 4, g = tid % 4;
+    const int D2 = d.D2;
+    float acc[3][8], bacc[8];
 #pragma unroll
-    for (int t = 0; t < 27; t++) acc[t] = 0.0f;
-    for (int64_t row = r0; row < r0 + kRowsPerBlk && row < rows; row++) {
+    for (int e = 0; e < 8; e++) {
+        acc[0][e] = acc[1][e] = acc[2][e] = 0.0f;
+        bacc[e] = 0.0f;
+    }
+    const int64_t rows = (int64_t)d.N * d.D0 * d.D1;
+    const int64_t rend = min(rows, ((int64_t)blockIdx.x + 1) * kRowsPerBlk);
+    for (int64_t row = (int64_t)blockIdx.x * kRowsPerBlk + lr; lr < kRowLanes && row < rend;
+         row += kRowLanes) {
         const int i = (int)((row / d.D1) % d.D0), j = (int)(row % d.D1);
         const int n = (int)(row / d.D1 / d.D0);
-        int64_t nb9[9];  // neighbour rows (dr, de), -1 outside the r / e range (zero padding)
+        const int ii = i + dd / 3 - 1, jj = j + dd % 3 - 1;
+        const bool ok = ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1;
+        const int64_t qb = ok ? (((int64_t)n * d.D0 + ii) * d.D1 + jj) * D2 : 0;
+        const int64_t pb = row * D2;
+        if (MODE == 1) {
+            float xm[8], x0[8];
+            const u16x8 vm = *reinterpret_cast<const u16x8 *>(xb + (qb + D2 - 1) * C + 8 * g);
+            const u16x8 v0 = *reinterpret_cast<const u16x8 *>(xb + qb * C + 8 * g);
 #pragma unroll
-        for (int q = 0; q < 9; q++) {
-            const int ii = i + q / 3 - 1, jj = j + q % 3 - 1;
-            nb9[q] = (ii < 0 || ii >= d.D0 || jj < 0 || jj >= d.D1)
-                         ? -1
-                         : (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2;
-        }
-        const int64_t pb = row * d.D2;
-        for (int k = sub; k < d.D2; k += kSub) {
-            const int64_t p = pb + k;
-            const float g = (MODE == 0) ? bf2f(dzb[p * C + c]) : dout[p];
-            bacc += g;
-            const int km = (k == 0) ? d.D2 - 1 : k - 1, kp = (k == d.D2 - 1) ? 0 : k + 1;
+            for (int e = 0; e < 8; e++) {
+                xm[e] = ok ? bf2f(vm[e]) : 0.0f;
+                x0[e] = ok ? bf2f(v0[e]) : 0.0f;
+            }
+#pragma unroll 2
+            for (int a = 0; a < D2; a++) {
+                const int ap = a + 1 == D2 ? 0 : a + 1;
+                const u16x8 vp = *reinterpret_cast<const u16x8 *>(xb + (qb + ap) * C + 8 * g);
+                const float gs = dout[pb + a];
+                bacc[0] += gs;
 #pragma unroll
-            for (int q = 0; q < 9; q++) {
-                if (nb9[q] < 0) continue;
-                const int64_t qb = nb9[q];
-                const int64_t q0 = qb + km, q1 = qb + k, q2 = qb + kp;  // da = -1, 0, +1
-                float x0, x1, x2;
-                if (MODE == 0) {
-                    x0 = xin[q0];
-                    x1 = xin[q1];
-                    x2 = xin[q2];
-                } else {
-                    x0 = bf2f(xb[q0 * C + c]);
-                    x1 = bf2f(xb[q1 * C + c]);
-                    x2 = bf2f(xb[q2 * C + c]);
+                for (int e = 0; e < 8; e++) {
+                    const float xp = ok ? bf2f(vp[e]) : 0.0f;
+                    acc[0][e] = fmaf(gs, xm[e], acc[0][e]);
+                    acc[1][e] = fmaf(gs, x0[e], acc[1][e]);
+                    acc[2][e] = fmaf(gs, xp, acc[2][e]);
+                    xm[e] = x0[e];
+                    x0[e] = xp;
                 }
-                acc[q * 3 + 0] = fmaf(g, x0, acc[q * 3 + 0]);
-                acc[q * 3 + 1] = fmaf(g, x1, acc[q * 3 + 1]);
-                acc[q * 3 + 2] = fmaf(g, x2, acc[q * 3 + 2]);
+            }
+        } else {
+            float xm = ok ? xin[qb + D2 - 1] : 0.0f, x0 = ok ? xin[qb] : 0.0f;
+#pragma unroll 2
+            for (int a = 0; a < D2; a++) {
+                const int ap = a + 1 == D2 ? 0 : a + 1;
+                const float xp = ok ? xin[qb + ap] : 0.0f;
+                const u16x8 gv = *reinterpret_cast<const u16x8 *>(dzb + (pb + a) * C + 8 * g);
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const float ge = bf2f(gv[e]);
+                    bacc[e] += ge;
+                    acc[0][e] = fmaf(ge, xm, acc[0][e]);
+                    acc[1][e] = fmaf(ge, x0, acc[1][e]);
+                    acc[2][e] = fmaf(ge, xp, acc[2][e]);
+                }
+                xm = x0;
+                x0 = xp;
             }
         }
     }
+    if (lr < kRowLanes) {
 #pragma unroll
-    for (int t = 0; t < 27; t++) sh[sub][t][c] = acc[t];
-    sh[sub][27][c] = bacc;
+        for (int da = 0; da < 3; da++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) sh[lr][(dd * 3 + da) * C + 8 * g + e] = acc[da][e];
+        if (dd == 4) {  // the centre row carries the bias sums once
+            if (MODE == 0) {
+#pragma unroll
+                for (int e = 0; e < 8; e++) sh[lr][27 * C + 8 * g + e] = bacc[e];
+            } else if (g == 0) {
+                sh[lr][27 * C] = bacc[0];
+            }
+        }
+    }
     __syncthreads();
-    for (int jo = threadIdx.x; jo < n_out; jo += 256) {
-        const int t = jo / C, cc = jo % C;  // t == 27: the bias row
+    for (int jo = tid; jo < n_out; jo += 256) {
         float v = 0.0f;
 #pragma unroll
-        for (int u = 0; u < kSub; u++) v += sh[u][t][cc];
+        for (int u = 0; u < kRowLanes; u++) v += sh[u][jo];
         part[(int64_t)blockIdx.x * n_out + jo] = v;
     }
 }
