@@ -436,7 +436,8 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
 // voxels of 64 bytes; rows outside the grid as zeros), then wavefront w
 // computes e-row j0 + w: 27 taps of 8 MFMAs with no branch between them, the
 // voxel fragments read from LDS and the weight fragments (which every
-// workgroup shares, so they stay in cache) loaded one tap ahead.
+// workgroup shares, so they stay in cache) loaded, like the voxel fragments,
+// one tap ahead.
 // A staged voxel r keeps its four 16-byte channel groups c at position
 // c ^ s(r), s(r) = ((r >> 1) ^ (r >> 3)) & 3: 8 (16) consecutive voxels then
 // cover all 32 (64) LDS banks.
@@ -483,21 +484,30 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
     for (int t = 0; t < NT; t++)
 #pragma unroll
         for (int u = 0; u < 2; u++) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    // voxel fragments of tap k (NT tiles of 16 azimuths)
+    auto load_a = [&](int k, bf16x8 *av) {
+        const int dr = k / 9, de = (k / 3) % 3, da = k % 3;  // offsets + 1
+        const int row = dr * (kTileRows + 2) + wv + de;
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+            av[t] = *reinterpret_cast<const bf16x8 *>(
+                &xs[swz_off(row * kStageVox + 16 * t + m + da, kq)]);
+    };
+    bf16x8 av[2][NT];
+    load_a(0, av[0]);
+    // both operands of the next tap are loaded while this tap's MFMAs run
 #pragma unroll
     for (int tap = 0; tap < 27; tap++) {
         const int cur = tap & 1;
         if (tap + 1 < 27) {
             b0[cur ^ 1] = ld8(wl + (tap + 1) * C * C);
             b1[cur ^ 1] = ld8(wl + (tap + 1) * C * C + 16 * C);
+            load_a(tap + 1, av[cur ^ 1]);
         }
-        const int dr = tap / 9, de = (tap / 3) % 3, da = tap % 3;  // offsets + 1
-        const int row = dr * (kTileRows + 2) + wv + de;
 #pragma unroll
         for (int t = 0; t < NT; t++) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(
-                &xs[swz_off(row * kStageVox + 16 * t + m + da, kq)]);
-            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b0[cur], acc[t][0], 0, 0, 0);
-            acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b1[cur], acc[t][1], 0, 0, 0);
+            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cur][t], b0[cur], acc[t][0], 0, 0, 0);
+            acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cur][t], b1[cur], acc[t][1], 0, 0, 0);
         }
     }
     const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2;

@@ -132,8 +132,11 @@ def test_conv_hidden_weight_gradient_mfma(nn, shape):
     assert torch.equal(dw, dw2)
 
 
-def test_conv_edge_layers(nn):
-    N, D0, D1, D2 = 2, 4, 5, 32
+@pytest.mark.parametrize("D2", [32, 3, 2, 1])
+def test_conv_edge_layers(nn, D2):
+    """The 1 -> 32 and 32 -> 1 layers accept any azimuth width; at 1 and 2
+    the circular neighbours a - 1, a, a + 1 coincide."""
+    N, D0, D1 = 2, 4, 5
     g = torch.Generator().manual_seed(5)
     x = torch.randn((N, D0, D1, D2), generator=g)
     w0 = torch.randn((27, 32), generator=g) * 0.2
