@@ -300,7 +300,6 @@ __global__ __launch_bounds__(256) void k_conv_out_bwd_data(const uint16_t *x, co
     }
 }
 
-constexpr int kChunk = 1024;  // voxels per block of the channel sums
 constexpr int kRowsPerBlk = 16;  // azimuth rows per block of the small weight gradients
 
 // mode 0 (input layer):  part[blk][t*32+o] = sum_p dz[p][o] * xin[p + off(t)]
@@ -404,22 +403,6 @@ __global__ __launch_bounds__(256) void k_small_wgrad(const float *xin, const uin
 #pragma unroll
         for (int u = 0; u < kRowLanes; u++) v += sh[u][jo];
         part[(int64_t)blockIdx.x * n_out + jo] = v;
-    }
-}
-
-// per-block channel sums of dz (bias gradient of the 32 -> 32 layers)
-__global__ __launch_bounds__(256) void k_chan_sum(const uint16_t *dz, int64_t nv, float *part) {
-    __shared__ float sh[256];
-    const int64_t p0 = (int64_t)blockIdx.x * kChunk;
-    const int c = threadIdx.x & 31, r = threadIdx.x >> 5;  // 8 voxel lanes x 32 channels
-    float s = 0.0f;
-    for (int64_t p = p0 + r; p < p0 + kChunk && p < nv; p += 8) s += bf2f(dz[p * C + c]);
-    sh[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < 32) {
-        float a = 0.0f;
-        for (int i = 0; i < 8; i++) a += sh[i * 32 + threadIdx.x];
-        part[(int64_t)blockIdx.x * C + threadIdx.x] = a;
     }
 }
 
@@ -576,7 +559,8 @@ __device__ __forceinline__ uint32_t pack_bf16x2(uint16_t lo, uint16_t hi) {
 
 __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ dz, Dims d,
-                                                          float *__restrict__ part) {
+                                                          float *__restrict__ part,
+                                                          float *__restrict__ bpart) {
     extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
     const int D2 = d.D2;
     const int sx = D2 + 24, sz = D2 + 8;  // channel-row strides (bf16 elements)
@@ -591,6 +575,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__rest
     f32x4 acc[27];
 #pragma unroll
     for (int t = 0; t < 27; t++) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;  // bias gradient: wavefronts of input tile 0 add up their dz operands
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int j0 = (int)(tile % njb) * kWRows;
         const int i = (int)((tile / njb) % d.D0), n = (int)(tile / njb / d.D0);
@@ -633,8 +618,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__rest
             if (j0 + r >= d.D1) break;  // uniform over the workgroup; zeros otherwise
             for (int kb = 0; kb < nkb; kb++) {
                 const int a = 32 * kb + 8 * kq;
-                const bf16x8 A = *reinterpret_cast<const bf16x8 *>(
-                    zT + (r * C + 16 * ot + m) * sz + a);
+                const u16x8 Au = *reinterpret_cast<const u16x8 *>(zT + (r * C + 16 * ot + m) * sz + a);
+                const bf16x8 A = __builtin_bit_cast(bf16x8, Au);
+                if (ct == 0) {  // uniform per wavefront
+#pragma unroll
+                    for (int e = 0; e < 8; e++) bsum += bf2f(Au[e]);
+                }
 #pragma unroll
                 for (int dd = 0; dd < 9; dd++) {  // (dr, de) offsets + 1
                     const int row = (dd / 3) * (kWRows + 2) + r + dd % 3;
@@ -660,7 +649,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__rest
             }
         }
     }
-    // partial sums: part[blk][tap][o][i]
+    // partial sums: part[blk][tap][o][i], bpart[blk][o]
     float *pb = part + (int64_t)blockIdx.x * 27 * C * C;
 #pragma unroll
     for (int t = 0; t < 27; t++)
@@ -669,6 +658,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__rest
             const int o = 16 * ot + 4 * kq + e, ci = 16 * ct + m;
             pb[((int64_t)t * C + o) * C + ci] = acc[t][e];
         }
+    if (ct == 0) {  // lanes m, m + 16, m + 32, m + 48 hold channel 16 ot + m
+        bsum += __shfl_xor(bsum, 16, 64);
+        bsum += __shfl_xor(bsum, 32, 64);
+        if (kq == 0) bpart[(int64_t)blockIdx.x * C + 16 * ot + m] = bsum;
+    }
 }
 
 size_t wgrad_lds_bytes(int D2) {
@@ -840,17 +834,15 @@ tspnn_status tspnn_from_bf16(const uint16_t *x, float *y, int64_t n, void *strea
 }
 
 size_t tspnn_conv_workspace(int32_t N, int32_t D0, int32_t D1, int32_t D2) {
-    const int64_t nv = (int64_t)N * D0 * D1 * D2;
     const int64_t rows = (int64_t)N * D0 * D1;
-    const int64_t chunks = (nv + kChunk - 1) / kChunk;
-    const size_t a = sizeof(float) * (size_t)wgrad_blocks(rows) * 27 * C * C;
+    const int64_t wb = wgrad_blocks(rows);
+    // 32 -> 32 layers: weight partials and their group sums, then the bias
+    // partials and theirs; edge layers: partials and group sums
+    const size_t a = sizeof(float) * ((size_t)(wb + kRedGroups) * 27 * C * C +
+                                      (size_t)(wb + kRedGroups) * C);
     const int64_t rblk = (rows + kRowsPerBlk - 1) / kRowsPerBlk;
-    const size_t b = sizeof(float) * (size_t)rblk * (27 * C + C);
-    const size_t c = sizeof(float) * (size_t)chunks * C;
-    size_t mx = a > b ? a : b;
-    mx = mx > c ? mx : c;
-    // the first-stage group sums of reduce_parts follow the partials
-    return mx + sizeof(float) * (size_t)kRedGroups * 27 * C * C + 256;
+    const size_t b = sizeof(float) * ((size_t)rblk + kRedGroups) * (27 * C + C);
+    return (a > b ? a : b) + 256;
 }
 
 tspnn_status tspnn_conv_in_fwd(const float *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
@@ -913,15 +905,12 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
         if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight (LDS size)");
         lds_enabled = wgrad_lds_bytes(kMaxD2);
     }
-    hipLaunchKernelGGL(k_conv_wgrad_tiled, dim3(nb), dim3(256), lds, st, x, dz,
-                       d, part);
+    // workspace: weight partials, their reduction's group sums, bias
+    // partials, theirs (tspnn_conv_workspace sizes it)
+    float *bpart = part + (int64_t)(nb + kRedGroups) * 27 * C * C;
+    hipLaunchKernelGGL(k_conv_wgrad_tiled, dim3(nb), dim3(256), lds, st, x, dz, d, part, bpart);
     reduce_parts(part, nb, 27 * C * C, 27 * C * C, dw, part + (int64_t)nb * 27 * C * C, st);
-    if (db) {
-        const int64_t nv = d.vox();
-        const int nc = (int)((nv + kChunk - 1) / kChunk);
-        hipLaunchKernelGGL(k_chan_sum, dim3(nc), dim3(256), 0, st, dz, nv, part);
-        reduce_parts(part, nc, C, C, db, part + (int64_t)nc * C, st);
-    }
+    if (db) reduce_parts(bpart, nb, C, C, db, bpart + (int64_t)nb * C, st);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_weight");
 }
 

@@ -307,15 +307,13 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
 #pragma unroll
             for (int b = 0; b < NB; b++) cb[b] = (v >= 0) ? l * yv[b] : 0.0f;
             uint64_t pend = __ballot(v >= 0);
-            while (pend) {
+            while (pend) {  // uniform over the wavefront: every lane is active
                 const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int v0 = __shfl(v, leader, kWave);
+                const int v0 = __builtin_amdgcn_readlane(v, leader);
                 const bool mine = (v == v0);
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    float sb = mine ? cb[b] : 0.0f;
-#pragma unroll
-                    for (int o = 32; o > 0; o >>= 1) sb += __shfl_xor(sb, o, kWave);
+                    const float sb = wave_sum_f32(mine ? cb[b] : 0.0f);
                     if (lane == leader && b < nb) atomicAdd(x + b * V + v0, sb);
                 }
                 pend &= ~__ballot(mine);

@@ -160,16 +160,12 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                 prefix += ck;
             }
             uint64_t pend = __ballot(v >= 0);
-            while (pend) {
+            while (pend) {  // uniform over the wavefront: every lane is active
                 const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int v0 = __shfl(v, leader, kWave);
+                const int v0 = __builtin_amdgcn_readlane(v, leader);
                 const bool mine = (v == v0);
-                float sa = mine ? a : 0.0f, sb = mine ? bterm : 0.0f;
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) {
-                    sa += __shfl_xor(sa, o, kWave);
-                    sb += __shfl_xor(sb, o, kWave);
-                }
+                const float sa = wave_sum_f32(mine ? a : 0.0f);
+                const float sb = wave_sum_f32(mine ? bterm : 0.0f);
                 if (lane == leader) {
                     atomicAdd(gw + v0, sa);
                     atomicAdd(gs + v0, sb);

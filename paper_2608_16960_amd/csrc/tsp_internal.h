@@ -135,6 +135,21 @@ __device__ __forceinline__ float decode_entry(int c, float l, int32_t &v, int na
 constexpr int kSlotEsc = 255;
 constexpr int kSlotMaxStep = 254;
 
+// Sum of x over the 64 lanes of a wavefront, returned to every lane: an
+// inclusive scan by DPP (row shifts 1, 2, 4, 8 within rows of 16 lanes, then
+// the broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3;
+// lanes a step gives no source keep the old value 0), then lane 63.  Every
+// lane must be active.
+__device__ __forceinline__ float wave_sum_f32(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xf, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
 // Ray-major sliced store: slice s holds 64 rays (one per lane); segment j of
 // lane l sits at slice_ptr[s] + 256 (j / 4) + 4 l + (j % 4), so each lane
 // reads four consecutive segments with one 16-byte load and a wavefront reads
