@@ -264,7 +264,8 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
 // Atomic adjoint from the ray-major store.  The 64 rays of a slice (one 16x16
 // detector window) cross similar voxels; each step the wavefront takes the
 // j-th segment of every lane, adds up the contributions that land in the same
-// voxel, and one lane per distinct voxel issues the atomic add.
+// voxel, and one lane per distinct voxel issues the atomic add (for up to
+// kMaxMerges distinct voxels; the rest add directly).
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ perm,
                                                      const int32_t *__restrict__ cnt_sorted,
@@ -307,7 +308,8 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
 #pragma unroll
             for (int b = 0; b < NB; b++) cb[b] = (v >= 0) ? l * yv[b] : 0.0f;
             uint64_t pend = __ballot(v >= 0);
-            while (pend) {  // uniform over the wavefront: every lane is active
+            // uniform over the wavefront: every lane is active
+            for (int it = 0; pend && it < kMaxMerges; it++) {
                 const int leader = __ffsll((unsigned long long)pend) - 1;
                 const int v0 = __builtin_amdgcn_readlane(v, leader);
                 const bool mine = (v == v0);
@@ -317,6 +319,11 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
                     if (lane == leader && b < nb) atomicAdd(x + b * V + v0, sb);
                 }
                 pend &= ~__ballot(mine);
+            }
+            if ((pend >> lane) & 1ull) {  // past the merge limit
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    if (b < nb) atomicAdd(x + b * V + v, cb[b]);
             }
         }
     }

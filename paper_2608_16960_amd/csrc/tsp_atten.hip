@@ -160,7 +160,8 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                 prefix += ck;
             }
             uint64_t pend = __ballot(v >= 0);
-            while (pend) {  // uniform over the wavefront: every lane is active
+            // uniform over the wavefront: every lane is active
+            for (int it = 0; pend && it < kMaxMerges; it++) {
                 const int leader = __ffsll((unsigned long long)pend) - 1;
                 const int v0 = __builtin_amdgcn_readlane(v, leader);
                 const bool mine = (v == v0);
@@ -171,6 +172,10 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                     atomicAdd(gs + v0, sb);
                 }
                 pend &= ~__ballot(mine);
+            }
+            if ((pend >> lane) & 1ull) {  // past the merge limit
+                atomicAdd(gw + v, a);
+                atomicAdd(gs + v, bterm);
             }
         }
     }

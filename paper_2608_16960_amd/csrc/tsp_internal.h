@@ -140,6 +140,15 @@ constexpr int kSlotMaxStep = 254;
 // the broadcasts of lane 15 to rows 1 and 3 and of lane 31 to rows 2 and 3;
 // lanes a step gives no source keep the old value 0), then lane 63.  Every
 // lane must be active.
+// Atomic scatters merge, per step, the lanes of a wavefront that hold the
+// same voxel (one DPP sum and one global atomic per distinct voxel), for at
+// most kMaxMerges distinct voxels; the lanes left over add directly.  A
+// slice's lanes are rays sorted by segment count, not neighbours, and a step
+// can touch dozens of voxels: past about 16 the merges cost more than the
+// contention they save (stored atomic adjoint and attenuated backward at
+// Medium: 16 best of 4, 8, 12, 16, 24, 32 and no limit).
+constexpr int kMaxMerges = 16;
+
 __device__ __forceinline__ float wave_sum_f32(float x) {
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xf, 0xf, false));
     x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xf, 0xf, false));
