@@ -897,13 +897,17 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
     const int nb = wgrad_blocks(tiles);
     float *part = (float *)work;
     const size_t lds = wgrad_lds_bytes(D2);
-    static size_t lds_enabled = 0;  // dynamic LDS above the default needs opting in
-    if (lds > lds_enabled) {
-        const hipError_t e = hipFuncSetAttribute((const void *)k_conv_wgrad_tiled,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)wgrad_lds_bytes(kMaxD2));
+    // dynamic LDS above the default needs opting in, once per device
+    static bool lds_enabled[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight");
+    if (dev < 0 || dev >= 64 || !lds_enabled[dev]) {
+        e = hipFuncSetAttribute((const void *)k_conv_wgrad_tiled,
+                                hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)wgrad_lds_bytes(kMaxD2));
         if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight (LDS size)");
-        lds_enabled = wgrad_lds_bytes(kMaxD2);
+        if (dev >= 0 && dev < 64) lds_enabled[dev] = true;
     }
     // workspace: weight partials, their reduction's group sums, bias
     // partials, theirs (tspnn_conv_workspace sizes it)

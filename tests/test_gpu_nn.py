@@ -126,10 +126,31 @@ def test_conv_hidden_weight_gradient_mfma(nn, shape):
     for got, ref in ((dw, wr.grad), (db, br.grad)):
         scale = float(ref.abs().max())
         assert float((got.cpu().double() - ref).abs().max()) <= 1e-5 * scale
-    dw2 = torch.empty_like(dw)
+    dw2, db2 = torch.empty_like(dw), torch.empty_like(db)
     nn.check(nn.lib.tspnn_conv_bwd_weight(nn._p(D["x"]), nn._p(D["dz"]), N, D0, D1, D2,
-                                          nn._p(dw2), nn._p(db), nn._p(ws), nn._s()))
-    assert torch.equal(dw, dw2)
+                                          nn._p(dw2), nn._p(db2), nn._p(ws), nn._s()))
+    assert torch.equal(dw, dw2) and torch.equal(db, db2)
+
+
+def test_conv_hidden_weight_gradient_many_tiles(nn):
+    """600 tiles of two e-rows against at most 512 workgroups: workgroups
+    take a second tile (re-staging after a barrier), as at the training size
+    (8192 tiles at batch 8 of 64x32x64)."""
+    N, D0, D1, D2 = 2, 20, 30, 32
+    g = torch.Generator().manual_seed(6)
+    x = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    dz = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
+    ws = torch.empty(int(nn.lib.tspnn_conv_workspace(N, D0, D1, D2)) // 4 + 1, device="cuda")
+    dw = torch.empty((27, 32, 32), device="cuda")
+    db = torch.empty(32, device="cuda")
+    D = _dev(dz=dz, x=x)
+    nn.check(nn.lib.tspnn_conv_bwd_weight(nn._p(D["x"]), nn._p(D["dz"]), N, D0, D1, D2,
+                                          nn._p(dw), nn._p(db), nn._p(ws), nn._s()))
+    wr = torch.zeros((27, 32, 32), dtype=torch.float64, requires_grad=True)
+    br = torch.zeros(32, dtype=torch.float64, requires_grad=True)
+    (OC.conv(x.double(), wr, br) * dz.double()).sum().backward()
+    for got, ref in ((dw, wr.grad), (db, br.grad)):
+        assert float((got.cpu().double() - ref).abs().max()) <= 1e-5 * float(ref.abs().max())
 
 
 @pytest.mark.parametrize("D2", [32, 3, 2, 1])
