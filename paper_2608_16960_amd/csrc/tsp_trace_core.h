@@ -203,7 +203,8 @@ struct Walker {
 
     TSP_HD void next_a(const Tab &T) {
         if (aleft > 0) {
-            const int k = (adir > 0) ? ((ia + 1) % T.np) : ia;
+            // 0 <= ia < np: wrap by a compare, not a division
+            const int k = (adir > 0) ? (ia + 1 == T.np ? 0 : ia + 1) : ia;
             const double lo = fmax(alast, tin);
             t_a = fmin(fmax(plane_t(T, k, x, n, lo), lo), tout);
         } else if (!ajump) {
@@ -441,7 +442,7 @@ struct Walker {
                 ajump = false;
                 t_a = INFINITY;
             } else {
-                ia = (adir > 0) ? (ia + 1) % np : (ia - 1 + np) % np;
+                ia = (adir > 0) ? (ia + 1 == np ? 0 : ia + 1) : (ia == 0 ? np - 1 : ia - 1);
                 aleft--;
                 alast = t_a;
                 next_a(T);
