@@ -412,20 +412,24 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// The same layer with its inputs staged in LDS.  A workgroup of four
-// wavefronts takes four consecutive e-rows (j0 .. j0+3) of one (n, i) and up
-// to 64 azimuths a0 .. a0+63.  It stages the 3 x 6 neighbour rows those
-// outputs read, each with one azimuth of circular halo on both sides (66
-// voxels of 64 bytes; rows outside the grid as zeros), then wavefront w
-// computes e-row j0 + w: 27 taps of 8 MFMAs with no branch between them, the
+// The same layer with its inputs staged in LDS.  A workgroup of eight
+// wavefronts takes two r-rows (i0, i0+1) by four e-rows (j0 .. j0+3) of one
+// object and up to 64 azimuths a0 .. a0+63.  It stages the 4 x 6 neighbour
+// rows those outputs read (each input row is fetched by 3 workgroups per
+// output row instead of 4.5 with tiles of one r-row), each with one azimuth
+// of circular halo on both sides (66 voxels of 64 bytes; rows outside the
+// grid as zeros), then wavefront w computes row (i0 + w / 4, j0 + w % 4):
+// 27 taps of 8 MFMAs with no branch between them, the
 // voxel fragments read from LDS and the weight fragments (which every
 // workgroup shares, so they stay in cache) loaded, like the voxel fragments,
 // one tap ahead.
 // A staged voxel r keeps its four 16-byte channel groups c at position
 // c ^ s(r), s(r) = ((r >> 1) ^ (r >> 3)) & 3: 8 (16) consecutive voxels then
 // cover all 32 (64) LDS banks.
-constexpr int kTileRows = 4;                    // e-rows per workgroup
-constexpr int kStageRows = 3 * (kTileRows + 2);  // (dr, de) rows staged
+constexpr int kTileRows = 4;                             // e-rows per workgroup
+constexpr int kTileR = 2;                                // r-rows per workgroup
+constexpr int kConvThreads = 64 * kTileRows * kTileR;    // one wavefront per row
+constexpr int kStageRows = (kTileR + 2) * (kTileRows + 2);  // rows staged
 constexpr int kStageVox = 66;                    // 64 azimuths + halo
 
 __device__ __forceinline__ int swz_off(int r, int c) {  // bf16 elements
@@ -437,14 +441,15 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
                                           const uint16_t *__restrict__ w,
                                           const float *__restrict__ bias,
                                           const uint16_t *__restrict__ mask,
-                                          uint16_t *__restrict__ y, uint16_t *xs, int n, int i,
+                                          uint16_t *__restrict__ y, uint16_t *xs, int n, int i0,
                                           int j0, int a0) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
+    const int ri = wv / kTileRows, wj = wv % kTileRows;  // this wavefront's output row
     constexpr int nq = NT * 16 + 2;  // staged voxels per row
-    for (int e = tid; e < kStageRows * nq * 4; e += 256) {
+    for (int e = tid; e < kStageRows * nq * 4; e += kConvThreads) {
         const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
-        const int ii = i + row / (kTileRows + 2) - 1, jj = j0 - 1 + row % (kTileRows + 2);
+        const int ii = i0 - 1 + row / (kTileRows + 2), jj = j0 - 1 + row % (kTileRows + 2);
         u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
         if (ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1) {
             int a = a0 - 1 + q;
@@ -454,14 +459,14 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
         }
         *reinterpret_cast<u16x8 *>(&xs[swz_off(row * kStageVox + q, c)]) = v;
     }
-    const int j = j0 + wv;
+    const int i = i0 + ri, j = j0 + wj;
     // weight fragments of tap 0 (output channels m and 16 + m)
     const uint16_t *wl = w + m * C + 8 * kq;
     bf16x8 b0[2], b1[2];
     b0[0] = ld8(wl);
     b1[0] = ld8(wl + 16 * C);
     __syncthreads();
-    if (j >= d.D1) return;  // uniform per wave; no barrier follows
+    if (i >= d.D0 || j >= d.D1) return;  // uniform per wave; no barrier follows
     f32x4 acc[NT][2];
 #pragma unroll
     for (int t = 0; t < NT; t++)
@@ -470,7 +475,7 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
     // voxel fragments of tap k (NT tiles of 16 azimuths)
     auto load_a = [&](int k, bf16x8 *av) {
         const int dr = k / 9, de = (k / 3) % 3, da = k % 3;  // offsets + 1
-        const int row = dr * (kTileRows + 2) + wv + de;
+        const int row = (ri + dr) * (kTileRows + 2) + wj + de;
 #pragma unroll
         for (int t = 0; t < NT; t++)
             av[t] = *reinterpret_cast<const bf16x8 *>(
@@ -515,24 +520,25 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
 }
 
 template <int EPI>
-__global__ __launch_bounds__(256) void k_conv_lds(const uint16_t *__restrict__ x, Dims d,
+__global__ __launch_bounds__(kConvThreads) void k_conv_lds(const uint16_t *__restrict__ x, Dims d,
                                                   const uint16_t *__restrict__ w,
                                                   const float *__restrict__ bias,
                                                   const uint16_t *__restrict__ mask,
                                                   uint16_t *__restrict__ y) {
     __shared__ __attribute__((aligned(16))) uint16_t xs[kStageRows * kStageVox * C];
     const int nchunk = (d.D2 + 63) / 64, njb = (d.D1 + kTileRows - 1) / kTileRows;
+    const int nib = (d.D0 + kTileR - 1) / kTileR;
     int64_t b = blockIdx.x;
     const int ac = (int)(b % nchunk);
     b /= nchunk;
     const int jb = (int)(b % njb);
     b /= njb;
-    const int i = (int)(b % d.D0), n = (int)(b / d.D0);
-    const int a0 = ac * 64, j0 = jb * kTileRows;
+    const int ib = (int)(b % nib), n = (int)(b / nib);
+    const int a0 = ac * 64, j0 = jb * kTileRows, i0 = ib * kTileR;
     if (d.D2 - a0 >= 64)  // uniform over the workgroup
-        conv_tile<EPI, 4>(x, d, w, bias, mask, y, xs, n, i, j0, a0);
+        conv_tile<EPI, 4>(x, d, w, bias, mask, y, xs, n, i0, j0, a0);
     else  // D2 % 32 == 0: the last chunk holds 32 azimuths
-        conv_tile<EPI, 2>(x, d, w, bias, mask, y, xs, n, i, j0, a0);
+        conv_tile<EPI, 2>(x, d, w, bias, mask, y, xs, n, i0, j0, a0);
 }
 
 constexpr int kMaxD2 = 128;  // widest azimuth row of the MFMA layers
@@ -765,10 +771,10 @@ tspnn_status hipret(hipError_t e, const char *what) {
     return TSPNN_OK;
 }
 
-// workgroups of k_conv_lds: (n, i, block of e-rows, 64-azimuth chunk)
+// workgroups of k_conv_lds: (n, block of r-rows, block of e-rows, 64-azimuth chunk)
 unsigned conv_blocks(const Dims &d) {
-    return (unsigned)((int64_t)d.N * d.D0 * ((d.D1 + kTileRows - 1) / kTileRows) *
-                      ((d.D2 + 63) / 64));
+    return (unsigned)((int64_t)d.N * ((d.D0 + kTileR - 1) / kTileR) *
+                      ((d.D1 + kTileRows - 1) / kTileRows) * ((d.D2 + 63) / 64));
 }
 
 tspnn_status mfma_dims(int N, int D0, int D1, int D2) {
@@ -863,7 +869,8 @@ tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    hipLaunchKernelGGL(k_conv_lds<0>, dim3(conv_blocks(d)), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_conv_lds<0>, dim3(conv_blocks(d)), dim3(kConvThreads), 0,
+                       (hipStream_t)stream,
                        x, d, w, b, (const uint16_t *)nullptr, y);
     return hipret(hipGetLastError(), "tspnn_conv_fwd");
 }
@@ -877,7 +884,8 @@ tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, 
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    hipLaunchKernelGGL(k_conv_lds<1>, dim3(conv_blocks(d)), dim3(256), 0, (hipStream_t)stream,
+    hipLaunchKernelGGL(k_conv_lds<1>, dim3(conv_blocks(d)), dim3(kConvThreads), 0,
+                       (hipStream_t)stream,
                        dz_out, d, w, (const float *)nullptr, act_in, dz_in);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_data");
 }
