@@ -522,51 +522,61 @@ __global__ __launch_bounds__(256) void k_rs_scatter_direct(const int32_t *kin, c
 // The same pass with the tile reordered by digit in LDS first, so that each
 // digit's run goes out contiguously at its place (goff, from the histogram
 // scan) and global writes coalesce instead of scattering over 256 buckets:
-// used for the lowest digit, which is spread at random over the input.
-__global__ __launch_bounds__(256) void k_rs_scatter_tiled(const int32_t *kin, const uint64_t *vin,
-                                                     int32_t *kout, uint64_t *vout, int64_t n,
-                                                     int shift, const int64_t *offs,
-                                                     int64_t nblk) {
-    __shared__ unsigned run[4][256];
-    __shared__ unsigned wbase[4][256];
+// used for the lowest digit, which is spread at random over the input.  The
+// tile (48 KB of items in LDS) is taken by eight wavefronts, so that two
+// tiles fit a CU with 16 wavefronts between them.
+constexpr int kTiledWaves = 8;
+constexpr int kTiledThreads = 64 * kTiledWaves;
+constexpr int kTiledItems = kRsTile / kTiledThreads;  // per thread
+constexpr int kTiledWaveItems = 64 * kTiledItems;
+
+__global__ __launch_bounds__(kTiledThreads) void k_rs_scatter_tiled(
+    const int32_t *kin, const uint64_t *vin, int32_t *kout, uint64_t *vout, int64_t n, int shift,
+    const int64_t *offs, int64_t nblk) {
+    __shared__ unsigned run[kTiledWaves][256];
+    __shared__ unsigned wbase[kTiledWaves][256];
     __shared__ unsigned loff[256];  // start of each digit within the tile
     __shared__ unsigned wsum[4];
     __shared__ int64_t goff[256];
     __shared__ int32_t lk[kRsTile];
     __shared__ uint64_t lv[kRsTile];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    for (int i = tid; i < 1024; i += 256) (&run[0][0])[i] = 0;
-    goff[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
+    for (int i = tid; i < kTiledWaves * 256; i += kTiledThreads) (&run[0][0])[i] = 0;
+    if (tid < 256) goff[tid] = offs[(int64_t)tid * nblk + blockIdx.x];
     __syncthreads();
-    const int64_t wb = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kRsWaveItems;
-    for (int c = 0; c < kRsItems; c++) {
+    const int64_t wb = (int64_t)blockIdx.x * kRsTile + (int64_t)w * kTiledWaveItems;
+    for (int c = 0; c < kTiledItems; c++) {
         const int64_t idx = wb + c * 64 + lane;
         if (idx < n) atomicAdd(&run[w][(kin[idx] >> shift) & 255], 1u);
     }
     __syncthreads();
-    unsigned tot = 0;  // items of digit tid in the tile
+    // threads 0 .. 255 (wavefronts 0 .. 3) take one digit each
+    unsigned tot = 0, incl = 0;  // items of digit tid in the tile, inclusive scan
+    if (tid < 256) {
 #pragma unroll
-    for (int ww = 0; ww < 4; ww++) {
-        const unsigned cc = run[ww][tid];
-        wbase[ww][tid] = tot;
-        tot += cc;
-        run[ww][tid] = 0;
-    }
-    // exclusive scan of the digit counts over the tile
-    unsigned incl = tot;
+        for (int ww = 0; ww < kTiledWaves; ww++) {
+            const unsigned cc = run[ww][tid];
+            wbase[ww][tid] = tot;
+            tot += cc;
+            run[ww][tid] = 0;
+        }
+        incl = tot;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned t = __shfl_up(incl, o, kWave);
-        if (lane >= o) incl += t;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned t = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) wsum[w] = incl;
     }
-    if (lane == 63) wsum[w] = incl;
     __syncthreads();
-    unsigned wpre = 0;
-    for (int ww = 0; ww < w; ww++) wpre += wsum[ww];
-    loff[tid] = wpre + incl - tot;
+    if (tid < 256) {
+        unsigned wpre = 0;
+        for (int ww = 0; ww < w; ww++) wpre += wsum[ww];
+        loff[tid] = wpre + incl - tot;
+    }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
-    for (int c = 0; c < kRsItems; c++) {
+    for (int c = 0; c < kTiledItems; c++) {
         const int64_t idx = wb + c * 64 + lane;
         const bool valid = idx < n;
         const int32_t k = valid ? kin[idx] : 0;
@@ -593,7 +603,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter_tiled(const int32_t *kin, co
     }
     __syncthreads();
     const unsigned nvalid = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    for (unsigned i = tid; i < nvalid; i += 256) {
+    for (unsigned i = tid; i < nvalid; i += kTiledThreads) {
         const int32_t k = lk[i];
         const int d = (k >> shift) & 255;
         const int64_t pos = goff[d] + (int64_t)(i - loff[d]);
@@ -677,7 +687,8 @@ hipError_t launch_radix_sort(int32_t *keys, uint64_t *vals, int32_t *keys2, uint
         hipError_t e = launch_scan_i32(hist, h, 1, offs, tmp, st);
         if (e != hipSuccess) return e;
         if (shift == 0)
-            hipLaunchKernelGGL(k_rs_scatter_tiled, dim3((unsigned)nb), dim3(256), 0, st, ka, va, kb,
+            hipLaunchKernelGGL(k_rs_scatter_tiled, dim3((unsigned)nb), dim3(kTiledThreads), 0, st,
+                               ka, va, kb,
                                vb, n, shift, offs, nb);
         else
             hipLaunchKernelGGL(k_rs_scatter_direct, dim3((unsigned)nb), dim3(256), 0, st, ka, va,
