@@ -356,3 +356,25 @@ def test_cone_ray_ids_equal_full_generation(ora):
     ids = np.array([0, 5, 1023, 1024, 4095, 2222])
     s2, d2 = ora.cone_ray_ids(v.pos, v.look, v.up, v.fov_deg, v.H, v.W, ids)
     assert np.array_equal(s2, s[ids]) and np.array_equal(d2, d[ids])
+
+
+def test_fused_project_equals_trace_then_forward(ora):
+    """The fused trace + forward (used for bounded CPU timing) returns the
+    stored path's result bit for bit: same segments, same summation order.
+    Tiny cone views (batch 2, noisy object) and random explicit rays on a
+    wedge grid; both pinned through trace() and forward() above."""
+    w = W.tiny()
+    s, d = _rays_of(ora, w.views)
+    rng = np.random.default_rng(21)
+    rho = np.stack([w.rho[0], rng.normal(size=w.grid.shape)]).astype(np.float64)
+    tr = ora.trace(w.grid.arrays(), s, d)
+    y, n = ora.project(w.grid.arrays(), s, d, rho)
+    assert n == int(tr["counts"].sum())
+    assert np.array_equal(y, ora.forward(tr, rho))
+    g = W.uniform_grid((5, 4, 6), r=(1.0, 4.0), e=(0.3, 2.5), a=(0.2, 4.0))
+    s2, d2 = W.random_rays(3000, rng, r_start=(6.0, 9.0), aim=3.0)
+    rho2 = rng.normal(size=(1, *g.shape))
+    tr2 = ora.trace(g.arrays(), s2, d2)
+    y2, n2 = ora.project(g.arrays(), s2, d2, rho2)
+    assert n2 == int(tr2["counts"].sum()) and n2 > 3000
+    assert np.array_equal(y2, ora.forward(tr2, rho2).reshape(1, -1))
