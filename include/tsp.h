@@ -244,6 +244,33 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
                            int32_t method, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * deterministic adjoint of tsp_backproject (TSP_ADJ_DETERMINISTIC, same
+ * kernels, bit-identical result) with no allocation of any kind.  The
+ * slot-ordered copy of y that tsp_backproject keeps in a stream-ordered
+ * temporary lives here in a fixed device array of
+ * TSP_NOALLOC_SCRATCH_BYTES, held by every device the library runs on
+ * until the process ends (its address is looked up on the first call on a
+ * device).  It needs n_stored_slots * 4 * min(batch rounded up to 2 or 4,
+ * 4) bytes, where the slots are the rays padded to whole 16 x 16 pixel
+ * windows: for example 1966080 slots (30 views of 256 x 256) fit up to
+ * batch 4, 26214400 slots (100 views of 512 x 512) batch 1.
+ * Arguments, layouts and ownership as tsp_backproject; batches above 4 are
+ * taken in groups of four through the same array.
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (different streams, threads) race and must be serialised by
+ * the caller; nothing carries over from one call to the next.
+ * Errors: TSP_E_INVALID (NULL, batch < 1), TSP_E_STATE (before tsp_trace,
+ * or without the voxel-major store: on the fly or TSP_TRACE_NO_CSC),
+ * TSP_E_NOMEM when the copy of y exceeds TSP_NOALLOC_SCRATCH_BYTES (use
+ * tsp_backproject), TSP_E_HIP.
+ */
+#define TSP_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+tsp_status tsp_backproject_noalloc(const tsp_geometry *g, const float *y, int32_t batch,
+                                   float *x, void *stream);
+
+/*
  * Attenuated emission model (Sec. 9.3, Eqs. 14-18).
  *
  * Sunward geometry: one explicit ray per voxel v, starting at v's centroid

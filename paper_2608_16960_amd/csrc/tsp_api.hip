@@ -9,10 +9,19 @@
 #include <array>
 #include <vector>
 
+#include <mutex>
+
 #include "tsp.h"
 #include "tsp_internal.h"
 
 using namespace tsp;
+
+// Workspace of tsp_backproject_noalloc (the slot-ordered copy of y), a
+// file-scope device array: every device the library runs on holds one copy
+// from module load until the process ends.  In host code `scratch` names a
+// host-side stand-in, not device memory; kernels get the device address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float scratch[TSP_NOALLOC_SCRATCH_BYTES / sizeof(float)];
 
 namespace {
 
@@ -257,7 +266,7 @@ hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, fl
                             int method, hipStream_t st) {
     if (method == TSP_ADJ_DETERMINISTIC)
         return launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_code, g->d_col_len, g->T.nr,
-                                  g->T.ne, g->T.na, y, batch, x, st);
+                                  g->T.ne, g->T.na, y, batch, x, nullptr, st);
     hipError_t e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
     if (e != hipSuccess) return e;
     if (g->mode == TSP_MODE_CSR)
@@ -265,6 +274,28 @@ hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, fl
                                      g->d_slice_len, g->d_code, g->d_len, y, batch, g->V,
                                      g->T.na, g->T.ne * g->T.na, x, st);
     return launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+}
+
+// Device address of `scratch` on device `dev` (the current device), looked
+// up once per device and kept: each device holds its own copy of the array
+// at its own address.
+constexpr int kMaxDevices = 256;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+tsp_status scratch_of_device(int dev, void **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TSP_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TSP_E_HIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                       hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TSP_OK;
 }
 
 // Checks shared by the attenuated forward and backward (Sec. 9.3).
@@ -1189,6 +1220,37 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
     if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
         return chunked_adjoint(g, y, batch, x, (hipStream_t)stream);
     const hipError_t e = adjoint_dispatch(g, y, batch, x, method, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_backproject_noalloc(const tsp_geometry *g, const float *y, int32_t batch,
+                                   float *x, void *stream) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if (!x || !y) return fail(TSP_E_INVALID, "y or x is NULL");
+    if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
+    if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject_noalloc before tsp_trace");
+    if (g->mode != TSP_MODE_CSR || !g->d_col_ptr)
+        return fail(TSP_E_STATE, "tsp_backproject_noalloc needs the voxel-major store "
+                                 "(TSP_MODE_CSR without TSP_TRACE_NO_CSC)");
+    const size_t need = adjoint_csc_ws_bytes(g->rd, batch);
+    if (need > (size_t)TSP_NOALLOC_SCRATCH_BYTES) {
+        char buf[200];
+        std::snprintf(buf, sizeof buf,
+                      "tsp_backproject_noalloc: the slot-ordered copy of y needs %llu bytes, "
+                      "more than the fixed workspace of %llu bytes",
+                      (unsigned long long)need, (unsigned long long)TSP_NOALLOC_SCRATCH_BYTES);
+        return fail(TSP_E_NOMEM, buf);
+    }
+    DeviceGuard dg(g->device);
+    if (!dg.ok) return fail(TSP_E_HIP, "hipSetDevice failed");
+    void *ws = nullptr;
+    const tsp_status s = scratch_of_device(g->device, &ws);
+    if (s != TSP_OK) return s;
+    const hipError_t e =
+        launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_code, g->d_col_len, g->T.nr, g->T.ne,
+                           g->T.na, y, batch, x, ws, (hipStream_t)stream);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
     return TSP_OK;
 }

@@ -411,14 +411,21 @@ static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_base, cons
     return hipGetLastError();
 }
 
+size_t adjoint_csc_ws_bytes(const RayDesc &rd, int B) {
+    const int width = B >= 3 ? 4 : B;
+    return (size_t)rd.n_slots * width * sizeof(float);
+}
+
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
                               const float *len, int nr, int ne, int na, const float *y, int B,
-                              float *x, hipStream_t st) {
+                              float *x, void *ws, hipStream_t st) {
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
-    const int width = B >= 3 ? 4 : B;
-    void *yt = nullptr;
-    hipError_t e = hipMallocAsync(&yt, (size_t)rd.n_slots * width * sizeof(float), st);
-    if (e != hipSuccess) return e;
+    void *yt = ws;
+    hipError_t e = hipSuccess;
+    if (!ws) {
+        e = hipMallocAsync(&yt, adjoint_csc_ws_bytes(rd, B), st);
+        if (e != hipSuccess) return e;
+    }
     for (int b0 = 0; b0 < B && e == hipSuccess; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
@@ -430,6 +437,7 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const 
         else
             e = adj_csc_chunk<4>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
     }
+    if (ws) return e;
     const hipError_t f = hipFreeAsync(yt, st);
     return e != hipSuccess ? e : f;
 }

@@ -272,11 +272,13 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
 // col_base is indexed by object frame, then the voxel's store key: the
 // packed voxel-major store (codes and lengths, see kSlotEsc) of key k spans
 // entries col_base[k] .. col_base[k+1]; x is written in (frame, r, e, a)
-// order.  y is first copied into slot order (batch interleaved) in a
-// stream-ordered temporary.
+// order.  y is first copied into slot order (batch interleaved, groups of
+// up to four objects in turn) in `ws`, adjoint_csc_ws_bytes(rd, B) bytes of
+// device memory, or, when ws is null, in a stream-ordered temporary.
+size_t adjoint_csc_ws_bytes(const RayDesc &rd, int B);
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
                               const float *len, int nr, int ne, int na, const float *y, int B,
-                              float *x, hipStream_t st);
+                              float *x, void *ws, hipStream_t st);
 hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *cnt_sorted, const int64_t *slice_ptr,
                                  const int32_t *slice_len, const uint8_t *code, const float *len,

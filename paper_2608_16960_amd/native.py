@@ -78,6 +78,7 @@ SIGNATURES = {
     "tsp_trace": (_st, [_vp, ctypes.c_int32, _vp]),
     "tsp_forward": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "tsp_backproject": (_st, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp]),
+    "tsp_backproject_noalloc": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "tsp_segments": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tsp_rays": (_st, [_vp, _vp, _vp, _vp]),
     "tsp_query": (_st, [_vp, ctypes.POINTER(tsp_info)]),
