@@ -223,22 +223,28 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
                        void *stream);
 
 /*
- * Adjoint: x[b][f][v] = sum over all segments in voxel v of rays of views in
+ * Adjoint (Sec. 4.4: the operator is differentiable, so reconstruction can
+ * take gradients through it; F is linear, and the gradient of <g, F rho>
+ * with respect to rho is F^T g, the adjoint of Eq. 5):
+ * x[b][f][v] = sum over all segments in voxel v of rays of views in
  * object frame f of len * y[b][ray].
  * y: device float32 [batch][R]; x: device float32 [batch][F][V], overwritten.
  * method TSP_ADJ_DETERMINISTIC (bitwise reproducible) or TSP_ADJ_ATOMIC.
  * The deterministic adjoint reads the transposed store when the geometry was
  * traced in CSR mode with it.  Otherwise (on the fly, or TSP_TRACE_NO_CSC) it
  * is traced within the call: the views (explicit rays: runs of whole 256-ray
- * windows) are cut into ceil(S / C) equal chunks, C = 2^30 segments or the
- * environment variable TSP_CHUNK_SEGMENTS; each chunk is traced into stores
- * of its own, transposed, and its adjoint added into x in chunk order.  That
- * costs about a full CSR trace per call and synchronises `stream`.  The
- * first such call allocates the chunks' working memory (about 37 bytes per
- * segment of the largest chunk expected, 1.5 times the mean; TSP_E_NOMEM if
- * it does not fit), which the geometry keeps for later calls until tsp_trace
- * or tsp_geometry_destroy.  Bitwise reproducible for a given geometry and C;
- * with one chunk it equals the stored deterministic adjoint bit for bit.
+ * windows) are cut into ceil(S / C) chunks of about equal segment counts
+ * (C = 2^30 segments or the environment variable TSP_CHUNK_SEGMENTS; a cut
+ * follows the first view or window at which the running count reaches a
+ * multiple of S / chunks); each chunk is traced into stores of its own,
+ * transposed, and its adjoint added into x in chunk order.  That costs about
+ * a full CSR trace per call and synchronises `stream`.  The first such call
+ * allocates the chunks' working memory (about 55 bytes per segment of the
+ * largest chunk; TSP_E_NOMEM if it does not fit), which the geometry keeps
+ * for later calls until tsp_trace or tsp_geometry_destroy; calls of this
+ * kind on one geometry are serialised.  Bitwise reproducible for a given
+ * geometry and C; with one chunk it equals the stored deterministic adjoint
+ * bit for bit.
  */
 tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
                            int32_t method, void *stream);

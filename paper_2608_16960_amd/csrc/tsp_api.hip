@@ -101,6 +101,12 @@ struct tsp_geometry {
     std::vector<std::array<int64_t, 3>> arena_blocks;
     mutable char *chunk_arena = nullptr;
     mutable int64_t chunk_arena_size = 0;
+    // canonical segments per window of kWindow natural slots (host copy,
+    // from the count pass): chunk boundaries of the deterministic adjoint
+    // without a stored transposed list follow them
+    std::vector<int32_t> win_segs;
+    // serialises that adjoint's use of chunk_arena across threads
+    mutable std::mutex chunk_mu;
 };
 
 namespace {
@@ -527,29 +533,9 @@ tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int
     g->R = R;
 
     // boundary tables
-    const bool cyclic = std::fabs(span - kTwoPi) <= 1e-12;
-    const int np = cyclic ? na : na + 1;
-    TabDesc &T = g->T;
-    T.ab0 = grid->a_b[0];
-    T.nr = nr;
-    T.ne = ne;
-    T.na = na;
-    T.np = np;
-    T.cyclic = cyclic ? 1 : 0;
-    T.off_rb = 0;
-    T.off_ce = T.off_rb + nr + 1;
-    T.off_ca = T.off_ce + ne + 1;
-    T.off_sa = T.off_ca + np;
-    T.off_ab = T.off_sa + np;
-    T.n_tab = T.off_ab + na + 1;
-    std::vector<double> tab((size_t)T.n_tab);
-    for (int k = 0; k <= nr; k++) tab[T.off_rb + k] = grid->r_b[k];
-    for (int k = 0; k <= ne; k++) tab[T.off_ce + k] = std::cos(grid->e_b[k]);
-    for (int k = 0; k < np; k++) {
-        tab[T.off_ca + k] = std::cos(grid->a_b[k]);
-        tab[T.off_sa + k] = std::sin(grid->a_b[k]);
-    }
-    for (int k = 0; k <= na; k++) tab[T.off_ab + k] = grid->a_b[k] - grid->a_b[0];
+    std::vector<double> tab;
+    make_tables(grid->r_b, nr, grid->e_b, ne, grid->a_b, na, &g->T, &tab);
+    const TabDesc &T = g->T;
 
     RayDesc &rd = g->rd;
     rd.R = R;
@@ -881,28 +867,36 @@ tsp_status trace_impl(tsp_geometry *g, int base_mode, bool want_csc, hipStream_t
     // pass 1: store entries and canonical segments per ray (entries only in
     // CSR mode, where they lay out the store)
     const bool csr = base_mode == TSP_MODE_CSR;
-    int32_t *cnt_nat = nullptr, *seg_nat = nullptr;
+    const int64_t n_win = ns / kWindow;
+    int32_t *cnt_nat = nullptr, *seg_nat = nullptr, *win_seg = nullptr;
     int64_t *counters = nullptr;  // [0] total (u64), [1] max count (int), [2] fill error (int)
     auto free_tmp = [&]() {
         dfree(g, cnt_nat);
         dfree(g, seg_nat);
         dfree(g, counters);
-        cnt_nat = seg_nat = nullptr;
+        dfree(g, win_seg);
+        cnt_nat = seg_nat = win_seg = nullptr;
         counters = nullptr;
     };
     if ((csr && (s = dalloc_n(g, &cnt_nat, ns, "entry counts")) != TSP_OK) ||
         (csr && (s = dalloc_n(g, &seg_nat, ns, "segment counts")) != TSP_OK) ||
+        (s = dalloc_n(g, &win_seg, n_win, "window segment counts")) != TSP_OK ||
         (s = dalloc_n(g, &counters, 4, "counters")) != TSP_OK) {
         free_tmp();
         return s;
     }
     hipError_t e = hipMemsetAsync(counters, 0, 4 * sizeof(int64_t), st);
+    if (e == hipSuccess) e = hipMemsetAsync(win_seg, 0, n_win * sizeof(int32_t), st);
     if (e == hipSuccess)
         e = launch_count(g->T, g->d_tab, rd, cnt_nat, seg_nat, (unsigned long long *)counters,
-                         (int *)(counters + 1), st);
+                         (int *)(counters + 1), win_seg, st);
     int64_t host_ctr[4] = {0, 0, 0, 0};
+    g->win_segs.assign(n_win, 0);
     if (e == hipSuccess)
         e = hipMemcpyAsync(host_ctr, counters, sizeof host_ctr, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(g->win_segs.data(), win_seg, n_win * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         free_tmp();
@@ -1016,47 +1010,66 @@ int64_t chunk_segments() {
 // Deterministic adjoint of a geometry without a stored transposed list (on
 // the fly, or stored lists traced without it).  The views (explicit rays: runs
 // of whole windows of 256 rays) are cut into ceil(S / chunk_segments())
-// chunks of equal size, a rule that depends on the geometry alone.  Each
-// chunk is traced into stores of its own (ray-major, then voxel-major,
-// packed), its deterministic adjoint computed, and the chunks' results added
-// into x in chunk order.  So x is bitwise reproducible for a given geometry
-// and setting, and with one chunk it equals the stored deterministic adjoint.
-// Memory: the stores of one chunk at a time.  Synchronises the stream.
+// chunks of about equal segment counts: a cut falls after the first view
+// (window) at which the running segment count, known per window from the
+// count pass, reaches a multiple of S / chunks.  The rule depends on the
+// geometry alone.  Each chunk is traced into stores of its own (ray-major,
+// then voxel-major, packed), its deterministic adjoint computed, and the
+// chunks' results added into x in chunk order.  So x is bitwise
+// reproducible for a given geometry and setting, and with one chunk it
+// equals the stored deterministic adjoint.  Memory: the stores of one chunk
+// at a time, in an arena the geometry keeps.  Calls on one geometry are
+// serialised (they share the arena).  Synchronises the stream.
 tsp_status chunked_adjoint(const tsp_geometry *g, const float *y, int B, float *x,
                            hipStream_t st) {
+    std::lock_guard<std::mutex> lock(g->chunk_mu);
     const RayDesc &rd = g->rd;
     const int64_t FV = g->FV(), R = g->R, S = g->S;
     const int64_t lim = chunk_segments();
     const int64_t nch = S > lim ? (S + lim - 1) / lim : 1;
-    std::vector<int64_t> cut{0};  // chunk boundaries in rays
-    if (!rd.explicit_rays) {
-        const int64_t hw = (int64_t)rd.H * rd.W, nv = rd.n_views;
-        const int64_t per = (nv + nch - 1) / nch;
-        for (int64_t v = per; v < nv; v += per) cut.push_back(v * hw);
-    } else {
-        const int64_t nwin = (R + kWindow - 1) / kWindow;
-        const int64_t per = (nwin + nch - 1) / nch * kWindow;
-        for (int64_t r = per; r < R; r += per) cut.push_back(r);
+    // units that a chunk holds whole: cone views, or windows of explicit rays
+    const int64_t n_win = (int64_t)g->win_segs.size();
+    const int64_t wpu = rd.explicit_rays ? 1 : (int64_t)rd.tiles_h * rd.tiles_w;
+    const int64_t n_units = rd.explicit_rays ? n_win : rd.n_views;
+    if (n_units * wpu != n_win) return fail(TSP_E_STATE, "chunked adjoint: no window counts");
+    std::vector<int64_t> ucut{0}, cseg;
+    int64_t acc = 0, prev = 0, next = 1;
+    for (int64_t u = 0; u < n_units; u++) {
+        for (int64_t k = 0; k < wpu; k++) acc += g->win_segs[u * wpu + k];
+        bool passed = false;
+        while (next < nch && acc * nch >= next * S) {
+            next++;
+            passed = true;
+        }
+        if (passed && u + 1 < n_units) {
+            ucut.push_back(u + 1);
+            cseg.push_back(acc - prev);
+            prev = acc;
+        }
     }
-    cut.push_back(R);
-    int64_t rmax = 0;
-    for (size_t c = 0; c + 1 < cut.size(); c++) rmax = std::max(rmax, cut[c + 1] - cut[c]);
+    ucut.push_back(n_units);
+    cseg.push_back(acc - prev);
+    std::vector<int64_t> cut;  // chunk boundaries in rays
+    for (int64_t u : ucut)
+        cut.push_back(rd.explicit_rays ? std::min<int64_t>(u * kWindow, R)
+                                       : u * (int64_t)rd.H * rd.W);
+    int64_t rmax = 0, smax = 0;
+    for (size_t c = 0; c + 1 < cut.size(); c++) {
+        rmax = std::max(rmax, cut[c + 1] - cut[c]);
+        smax = std::max(smax, cseg[c]);
+    }
 
     // the chunks' working memory, allocated once and kept for later calls:
     // both stores (about 10.5 bytes per segment), one transpose pass over the
-    // whole chunk (25), the trace's per-slot arrays and the block offsets; the
-    // segment count of a chunk is taken as 1.5 times the mean, and a larger
-    // chunk is transposed in passes within the same memory
+    // whole chunk (25), the trace's per-slot arrays and the block offsets,
+    // for the largest chunk with half again as many segments of room (the
+    // stores' padding and the sort's workspace; with less room the transpose
+    // of a large chunk falls back to several passes, 40% slower at Large)
     if (!g->chunk_arena) {
         int64_t ns_max = 0;
-        for (size_t c = 0; c + 1 < cut.size(); c++) {
-            const int64_t rc = cut[c + 1] - cut[c];
-            ns_max = std::max<int64_t>(ns_max, rd.explicit_rays
-                                                   ? (rc + kWindow - 1) / kWindow * kWindow
-                                                   : rc / ((int64_t)rd.H * rd.W) * rd.tiles_h *
-                                                         rd.tiles_w * kWindow);
-        }
-        const int64_t sc = (S / (int64_t)(cut.size() - 1)) * 3 / 2 + 4096;
+        for (size_t c = 0; c + 1 < ucut.size(); c++)
+            ns_max = std::max<int64_t>(ns_max, (ucut[c + 1] - ucut[c]) * wpu * kWindow);
+        const int64_t sc = smax * 3 / 2 + 4096;
         int64_t want = sc * 37 + ns_max * 48 + FV * 40 + ((int64_t)64 << 20);
         const int64_t dcap = device_cap();
         if (dcap > 0) want = std::min<int64_t>(want, dcap - g->bytes);

@@ -3,7 +3,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
+#include <vector>
 
 namespace tsp {
 
@@ -25,6 +27,38 @@ struct TabDesc {
     int nr, ne, na, np, cyclic;
     int off_rb, off_ce, off_ca, off_sa, off_ab, n_tab;
 };
+
+// Boundary tables of a validated grid (host): the descriptor and the packed
+// values, in the layout above.  The grid is cyclic in azimuth when a_b spans
+// 2 pi within 1e-12; then boundary na is boundary 0 and np = na half-planes
+// remain, else np = na + 1.
+inline void make_tables(const double *r_b, int nr, const double *e_b, int ne, const double *a_b,
+                        int na, TabDesc *T, std::vector<double> *tab) {
+    const double span = a_b[na] - a_b[0];
+    const bool cyclic = std::fabs(span - 6.283185307179586476925286766559) <= 1e-12;
+    const int np = cyclic ? na : na + 1;
+    T->ab0 = a_b[0];
+    T->nr = nr;
+    T->ne = ne;
+    T->na = na;
+    T->np = np;
+    T->cyclic = cyclic ? 1 : 0;
+    T->off_rb = 0;
+    T->off_ce = T->off_rb + nr + 1;
+    T->off_ca = T->off_ce + ne + 1;
+    T->off_sa = T->off_ca + np;
+    T->off_ab = T->off_sa + np;
+    T->n_tab = T->off_ab + na + 1;
+    tab->assign((size_t)T->n_tab, 0.0);
+    double *t = tab->data();
+    for (int k = 0; k <= nr; k++) t[T->off_rb + k] = r_b[k];
+    for (int k = 0; k <= ne; k++) t[T->off_ce + k] = std::cos(e_b[k]);
+    for (int k = 0; k < np; k++) {
+        t[T->off_ca + k] = std::cos(a_b[k]);
+        t[T->off_sa + k] = std::sin(a_b[k]);
+    }
+    for (int k = 0; k <= na; k++) t[T->off_ab + k] = a_b[k] - a_b[0];
+}
 
 // Where rays come from: cone views (frames) or explicit arrays.
 struct RayDesc {
@@ -197,9 +231,11 @@ __host__ __device__ __forceinline__ int32_t store_voxel(int64_t k, int nr, int n
 }
 
 // ---- launchers (tsp_trace.hip) ----
+// win_seg (may be null, zeroed by the caller): canonical segments per window
+// of kWindow natural slots
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
                         int32_t *seg_nat, unsigned long long *total, int *maxcnt,
-                        hipStream_t st);
+                        int32_t *win_seg, hipStream_t st);
 hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
                        const int32_t *perm, const int32_t *cnt_sorted, const int64_t *slice_ptr,
                        const int32_t *slice_len, uint8_t *code, float *len, int *err,

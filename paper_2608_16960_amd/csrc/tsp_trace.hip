@@ -157,10 +157,13 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 // Per natural slot: store entries (cnt_nat) and canonical segments (seg_nat,
-// may be null); total and maxcnt over segments.
+// may be null); total and maxcnt over segments; per window (a workgroup's
+// 256 slots) the canonical segments, added into win_seg (zeroed first; may
+// be null).
 __global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, RayDesc rd,
                                                 int32_t *cnt_nat, int32_t *seg_nat,
-                                                unsigned long long *total, int *maxcnt) {
+                                                unsigned long long *total, int *maxcnt,
+                                                int32_t *win_seg) {
     extern __shared__ double lds[];
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
@@ -187,6 +190,7 @@ __global__ __launch_bounds__(256) void k_count(TabDesc D, const double *tab, Ray
     if ((threadIdx.x & 63) == 0) {
         atomicAdd(total, (unsigned long long)s);
         atomicMax(maxcnt, m);
+        if (win_seg) atomicAdd(win_seg + blockIdx.x, s);
     }
 }
 
@@ -421,9 +425,9 @@ inline unsigned grid_of(int64_t n_slots) { return (unsigned)((n_slots + 255) / 2
 
 hipError_t launch_count(const TabDesc &T, const double *tab, const RayDesc &rd, int32_t *cnt_nat,
                         int32_t *seg_nat, unsigned long long *total, int *maxcnt,
-                        hipStream_t st) {
+                        int32_t *win_seg, hipStream_t st) {
     hipLaunchKernelGGL(k_count, dim3(grid_of(rd.n_slots)), dim3(256), T.n_tab * sizeof(double),
-                       st, T, tab, rd, cnt_nat, seg_nat, total, maxcnt);
+                       st, T, tab, rd, cnt_nat, seg_nat, total, maxcnt, win_seg);
     return hipGetLastError();
 }
 
