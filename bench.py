@@ -47,61 +47,92 @@ def _args():
     p.add_argument("--large-only", action="store_true",
                    help="only the Large on-the-fly forward and adjoint (for counter runs)")
     p.add_argument("--extras", default="all",
-                   help="comma-separated extra workloads after the Medium line (onthefly_large, "
-                        "stored_large, diff_csr, explicit_rays_medium, attenuated_medium, "
-                        "learned_warm_start) or 'all'")
+                   help="comma-separated extra workloads after the Medium line (tiny, "
+                        "cnn_layers, onthefly_large, stored_large, diff_csr, "
+                        "explicit_rays_medium, attenuated_medium, learned_warm_start) or 'all'")
     p.add_argument("--cpu-views", type=int, default=30,
                    help="views of the workload the CPU oracle traces (bounded sample)")
+    p.add_argument("--cpu-full", action="store_true",
+                   help="CPU oracle on all 100 Differentiation views (minutes, ~46 GB of "
+                        "host memory) instead of 10")
     return p.parse_args()
 
 
-def _cpu_model():
+def _host():
+    """CPU model (lscpu, else /proc/cpuinfo), logical CPUs, and the CPUs this
+    process may run on."""
+    import subprocess
+    model = None
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
-    except OSError:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
         pass
-    return platform.processor() or platform.machine()
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            model = platform.processor() or platform.machine()
+    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(w, n_views, large_views=6):
+def cpu_baseline(w, n_views, large_views=6, diff_views=10, full=False):
     """The FP64 oracle as it stands, on the host cores: trace (steps 1-3) and
-    apply (forward + adjoint from its own lists) timed separately, with all
-    threads and with one; `value` is the all-thread apply rate in rays/s over
-    `n_views` views of the workload, like the GPU's.  Also the trace and apply
-    rates on a fixed subset of the Large workload (every 30th view)."""
+    apply (forward + adjoint from its own lists) timed separately, mirroring
+    the paper's precompute / raytrace split.  The forward runs on all OpenMP
+    threads; the oracle's adjoint is a plain serial loop and is timed as such.
+    `value` is the apply rate in rays/s over `n_views` views of the workload,
+    like the GPU's.  Also: one thread; the Learned geometry in full (trace
+    once, apply on the whole configuration); the Differentiation workload on
+    `diff_views` of its 100 views (all of them with full=True: about 2.3e9
+    segments, 46 GB of host memory); and a fixed subset of the Large workload
+    (every 30th view)."""
     import numpy as np
 
     import oracle
     from paper_2608_16960_amd import workloads as W
 
-    def run(wl, sel):
-        v = wl.views
+    def run(grid, v, sel, rho):
         s, d = oracle.cone_rays(v.pos[sel], v.look[sel], v.up[sel], v.fov_deg[sel], v.H, v.W)
         t0 = time.perf_counter()
-        tr = oracle.trace(wl.grid.arrays(), s, d)
+        tr = oracle.trace(grid.arrays(), s, d)
         t1 = time.perf_counter()
-        rho = wl.rho[0].reshape(-1).astype(np.float64)
         y = oracle.forward(tr, rho)
         t2 = time.perf_counter()
-        oracle.adjoint(tr, y, wl.grid.size)
+        oracle.adjoint(tr, y, grid.size)
         t3 = time.perf_counter()
-        return tr, rho, len(s), int(tr["counts"].sum()), (t1 - t0, t2 - t1, t3 - t2)
+        return tr, len(s), int(tr["counts"].sum()), (t1 - t0, t2 - t1, t3 - t2)
+
+    def leg(name, grid, v, sel, rho):
+        _log(f"cpu baseline: {name}")
+        tr, R, S, (ts, fs, as_) = run(grid, v, sel, rho)
+        del tr
+        return {"views": f"{len(sel)} of {v.n_views}", "rays": R, "segments": S,
+                "trace_s": ts, "forward_s": fs, "adjoint_s": as_,
+                "trace_rays_per_s": R / ts, "apply_rays_per_s": R / (fs + as_),
+                "apply_segments_per_s": S / (fs + as_)}
 
     nt = oracle.num_threads()
     v = w.views
     sel = np.linspace(0, v.n_views - 1, n_views).round().astype(int)
-    tr, rho, R, S, (ts, fs, as_) = run(w, sel)
+    rho = w.rho[0].reshape(-1).astype(np.float64)
+    _log("cpu baseline: main workload")
+    tr, R, S, (ts, fs, as_) = run(w.grid, v, sel, rho)
     out = {
         "value": R / (fs + as_), "unit": "rays/s", "cores": nt, "kind": "oracle",
         "sample": f"{len(sel)} of {v.n_views} views ({R} rays, {S} segments) of the "
-                  f"{w.name} workload; forward (OpenMP) + adjoint (serial) from the oracle's "
-                  f"own segment lists, FP64",
+                  f"{w.name} workload; forward on {nt} OpenMP threads + adjoint on one thread "
+                  f"(the oracle's adjoint loop is serial), from the oracle's own segment "
+                  f"lists, FP64",
         "segments_per_s": S / (fs + as_),
         "trace_rays_per_s": R / ts,
-        "trace_s": ts, "forward_s": fs, "adjoint_s": as_,
-        "host": _cpu_model(),
+        "trace_s": ts, "forward_s": fs, "adjoint_s": as_, "adjoint_threads": 1,
+        "host": _host(),
     }
     # one thread: apply on the same lists; trace on the first view only
     oracle.set_num_threads(1)
@@ -110,39 +141,56 @@ def cpu_baseline(w, n_views, large_views=6):
         oracle.forward(tr, rho)
         f1 = time.perf_counter() - t0
         del tr
-        _, _, R1, _, (t1s, _, _) = run(w, sel[:1])
+        _, R1, _, (t1s, _, _) = run(w.grid, v, sel[:1], rho)
     finally:
         oracle.set_num_threads(nt)
     out["one_thread"] = {"apply_rays_per_s": R / (f1 + as_), "forward_s": f1,
                          "trace_rays_per_s": R1 / t1s, "trace_sample": f"1 view ({R1} rays)"}
+    # Learned geometry, whole configuration (first training phantom)
+    g, lv = W.learned_geometry()
+    lrho = W.learned_phantoms(g, 1, seed=6)[0].reshape(-1).astype(np.float64)
+    out["learned_full"] = leg("learned", g, lv, np.arange(lv.n_views), lrho)
+    # Differentiation workload (views spread over the orbit)
+    D = W.diff()
+    nd = D.views.n_views if full else diff_views
+    dsel = np.linspace(0, D.views.n_views - 1, nd).round().astype(int)
+    out["diff_full" if full else "diff_subset"] = leg(
+        "differentiation", D.grid, D.views, dsel, D.rho[0].reshape(-1).astype(np.float64))
+    del D
     # Large subset, all threads
     L = W.large()
     lsel = np.arange(0, L.views.n_views, L.views.n_views // large_views)[:large_views]
-    trL, _, RL, SL, (tl, fl, al) = run(L, lsel)
-    del trL
-    out["large_subset"] = {"views": lsel.tolist(), "rays": RL, "segments": SL,
-                           "trace_rays_per_s": RL / tl, "apply_rays_per_s": RL / (fl + al),
-                           "apply_segments_per_s": SL / (fl + al), "object": "first of 4"}
+    out["large_subset"] = dict(leg("large", L.grid, L.views, lsel,
+                                   L.rho[0].reshape(-1).astype(np.float64)),
+                               view_ids=lsel.tolist(), object="first of 4")
     return out
 
 
-def measured_copy_gbps(dev, nbytes=1 << 30, reps=10):
-    """Bytes read + written per second by a plain device-to-device copy of
-    `nbytes` (torch's copy kernel), the practical streaming ceiling."""
+def measured_stream_gbps(dev, nbytes=1 << 30, reps=10):
+    """HBM rates of plain streams of `nbytes` on this device: the library's
+    hand-written non-temporal copy (bytes read + written per second) and
+    read, each at its best grid size of a few, and torch's copy for
+    reference."""
     import torch
-    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+
+    from paper_2608_16960_amd import nn as NN
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    ms = a.elapsed_time(b) / reps
-    del src, dst
-    return 2.0 * nbytes / ms / 1e6
+    part = torch.empty(1 << 16, dtype=torch.float32, device=dev)
+    out = {}
+    for blocks in (1024, 2048, 4096, 8192, 16384):
+        c = _time_ms(lambda: NN.stream_copy(src, dst, blocks), reps)
+        r = _time_ms(lambda: NN.stream_read(src, part, blocks), reps)
+        out.setdefault("copy", []).append((2.0 * nbytes / c / 1e6, blocks))
+        out.setdefault("read", []).append((nbytes / r / 1e6, blocks))
+    assert torch.equal(dst[:1024], src[:1024])
+    t = _time_ms(lambda: dst.copy_(src), reps)
+    del src, dst, part
+    best_c, best_r = max(out["copy"]), max(out["read"])
+    return {"copy_GBps": best_c[0], "copy_blocks": best_c[1],
+            "read_GBps": best_r[0], "read_blocks": best_r[1],
+            "torch_copy_GBps": 2.0 * nbytes / t / 1e6, "bytes": nbytes}
 
 
 def _log(msg):
@@ -161,6 +209,64 @@ def _time_ms(fn, reps, warm=1):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def extra_tiny(reps=200):
+    """Tiny workload (latency-bound: about 1e5 segments): time per launch of
+    the stored-list forward and deterministic adjoint."""
+    import torch
+
+    from paper_2608_16960_amd import workloads as W
+    from paper_2608_16960_amd.projector import Projector
+    w = W.tiny()
+    P = Projector(w.grid, views=w.views)
+    rho = torch.from_numpy(w.rho).cuda()
+    y = P.forward(rho)
+    x = torch.empty_like(rho)
+    f_ms = _time_ms(lambda: P.forward(rho, out=y), reps, warm=5)
+    a_ms = _time_ms(lambda: P.backproject(y, "deterministic", out=x), reps, warm=5)
+    inf = P.info()
+    P.close()
+    return {"workload": f"tiny: grid {P.shape}, {w.views.n_views} cone views "
+                        f"{w.views.H}x{w.views.W}, {inf['n_rays']} rays, {inf['n_segments']} "
+                        f"segments, batch 1",
+            "forward_us": f_ms * 1e3, "adjoint_us": a_ms * 1e3, "step_us": (f_ms + a_ms) * 1e3,
+            "note": "latency-bound (under 1 MB moved); time only"}
+
+
+def extra_cnn(reps=20):
+    """The 32 -> 32 convolution kernels (BF16 MFMA, FP32 accumulation) at the
+    training shape, batch 8 of 64 x 32 x 64 voxels: forward, input gradient
+    and weight gradient (with the bias gradient), each 2 * 27 * 32 * 32
+    flop per voxel, against the dense BF16 peak."""
+    import torch
+
+    from paper_2608_16960_amd import nn as NN
+    N, D = 8, (64, 32, 64)
+    g = torch.Generator(device="cpu").manual_seed(3)
+    x = torch.randn((N, *D, 32), generator=g).to(torch.bfloat16).cuda()
+    dz = torch.randn((N, *D, 32), generator=g).to(torch.bfloat16).cuda()
+    w = (0.05 * torch.randn((27, 32, 32), generator=g)).to(torch.bfloat16).cuda()
+    b = torch.zeros(32, device="cuda")
+    out = torch.empty_like(x)
+    dw = torch.empty((27, 32, 32), device="cuda")
+    db = torch.empty(32, device="cuda")
+    ws = torch.empty(int(NN.lib.tspnn_conv_workspace(N, *D)) // 4 + 1, device="cuda")
+    p, s = NN._p, NN._s
+    fwd = lambda: NN.check(NN.lib.tspnn_conv_fwd(p(x), N, *D, p(w), p(b), p(out), s()))
+    bwd_d = lambda: NN.check(NN.lib.tspnn_conv_bwd_data(p(dz), N, *D, p(w), p(x), p(out), s()))
+    bwd_w = lambda: NN.check(NN.lib.tspnn_conv_bwd_weight(p(x), p(dz), N, *D, p(dw), p(db),
+                                                          p(ws), s()))
+    flops = 2.0 * 27 * 32 * 32 * N * D[0] * D[1] * D[2]
+    res = {}
+    for name, kern, fn in (("forward", "k_conv_lds<0>", fwd),
+                           ("input_gradient", "k_conv_lds<1>", bwd_d),
+                           ("weight_gradient", "k_conv_wgrad_tiled", bwd_w)):
+        ms = _time_ms(fn, reps, warm=3)
+        tf = flops / ms / 1e9
+        res[name] = {"kernel": kern, "us": ms * 1e3, "TFLOPs": tf, "frac_of_bf16_peak": tf / 2500.0}
+    return {"workload": "batch 8 of 64x32x64 voxels, 32 -> 32 channels, 3x3x3 taps",
+            "flop_per_launch": flops, "peak_TFLOPs": 2500.0, **res}
 
 
 def extra_large_onthefly():
@@ -360,7 +466,7 @@ def extra_learned(epochs=6):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     del x_in, train
-    res = ws.evaluate(torch.from_numpy(W.learned_phantoms(g, 200, seed=7)).cuda())
+    res = ws.evaluate(torch.from_numpy(W.learned_phantoms(g, 200, seed=7)).cuda(), curves=True)
     warm = np.array(res["warm_calls"])
     plain = np.array(res["plain_calls"])
     P.close()
@@ -371,7 +477,11 @@ def extra_learned(epochs=6):
             "warm_calls_p90": float(np.percentile(warm, 90)), "warm_calls_max": int(warm.max()),
             "fallback_rate": float(np.mean(res["fallback"])),
             "reduction": float(np.median(plain) / np.median(warm)),
-            "train_epochs": epochs, "train_s": train_s, "train_mse_last": hist[-1]}
+            "train_epochs": epochs, "train_s": train_s, "train_mse_last": hist[-1],
+            # median over the held-out phantoms of residual / R* against
+            # projector calls: plain GD from zero, and the warm start (4 input
+            # calls + 1 for the CNN output's residual, then GD)
+            "curves": res["curves"]}
 
 
 def main():
@@ -450,11 +560,20 @@ def main():
               "GBps_algorithmic": adj_bytes / atomic_ms / 1e6,
               "max_rel_diff_vs_deterministic":
                   float((xa - x).abs().max() / x.abs().max().clamp_min(1e-30))}
-    copy_gbps = measured_copy_gbps(dev)
+    stream = measured_stream_gbps(dev)
+    copy_gbps = stream["copy_GBps"]
     dom = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom]
-    from paper_2608_16960_amd.profiling import read_traffic
-    traffic = read_traffic(os.path.join(ROOT, "profiles", "hbm_traffic_medium.txt"), d["kernel"])
+    from paper_2608_16960_amd.profiling import read_occupancy, read_traffic
+    prof = os.path.join(ROOT, "profiles")
+    for k in kern.values():
+        k["traffic_bytes"] = read_traffic(os.path.join(prof, "hbm_traffic_medium.txt"), k["kernel"])
+        if k["traffic_bytes"] is not None:
+            k["traffic_GBps"] = k["traffic_bytes"] / k["ms"] / 1e6
+    traffic = d["traffic_bytes"]
+    occ = {k: read_occupancy(os.path.join(prof, "occupancy.md"), k)
+           for k in ("k_fwd_sell<1>", "k_tile_y<1>", "k_adj_csc<1>", "k_otf_forward<4>",
+                     "k_otf_adjoint<4>")}
     line = {
         "metric": "rays/s & segments/s fwd+adjoint (%HBM roofline); projector calls to residual",
         "value": R / (ms_step / 1e3),
@@ -468,7 +587,18 @@ def main():
         "segments_per_s": S / (ms_step / 1e3),
         "roofline": {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": d["kernel"],
-                     "copy_GBps": copy_gbps, "frac_of_copy": d["GBps"] / copy_gbps},
+                     "timed_unit": "the whole call (k_tile_y<1> then k_adj_csc<1>)"
+                     if dom == "adjoint" else "the kernel",
+                     # bytes the counters saw moved, over the same time: the
+                     # physical fraction (the stores hold ~5 B per segment, not 8)
+                     "traffic_frac": None if traffic is None
+                     else traffic / d["ms"] / 1e6 / HBM_PEAK_GBS,
+                     "copy_GBps": copy_gbps, "frac_of_copy": d["GBps"] / copy_gbps,
+                     "read_GBps": stream["read_GBps"],
+                     "traffic_frac_of_read": None if traffic is None
+                     else traffic / d["ms"] / 1e6 / stream["read_GBps"]},
+        "stream": stream,
+        "occupancy_waves_per_cu": occ,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv)
                         for kk, vv in v.items()} for k, v in kern.items()},
         "atomic_adjoint": atomic,
@@ -488,7 +618,9 @@ def main():
         # the Large workloads last: device memory that a process has just
         # released takes the driver noticeably longer to hand out again, which
         # would show in the trace times of whatever follows them
-        extras = [("diff_csr", "differentiation workload", extra_diff_csr),
+        extras = [("tiny", "tiny workload", extra_tiny),
+                  ("cnn_layers", "cnn layers", extra_cnn),
+                  ("diff_csr", "differentiation workload", extra_diff_csr),
                   ("explicit_rays_medium", "explicit rays", extra_explicit_medium),
                   ("attenuated_medium", "attenuated model", extra_atten_medium),
                   ("learned_warm_start", "learned warm start", extra_learned),
@@ -503,7 +635,7 @@ def main():
                 line[key] = fn()
     if not a.no_cpu_baseline:
         _log("cpu baseline")
-        line["cpu_baseline"] = cpu_baseline(w, a.cpu_views)
+        line["cpu_baseline"] = cpu_baseline(w, a.cpu_views, full=a.cpu_full)
     print(json.dumps(line))
 
 

@@ -163,6 +163,23 @@ tspnn_status tspnn_conv_flip_weights(const uint16_t *w, uint16_t *wt, void *stre
 tspnn_status tspnn_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream);
 tspnn_status tspnn_from_bf16(const uint16_t *x, float *y, int64_t n, void *stream);
 
+/* ------------------------------------------------------------------ measurement */
+/*
+ * Plain HBM streams, for the roofline of the projector kernels (the rate a
+ * simple stream reaches on this device next to the published peak): a copy
+ * of n float32 from src to dst, and a read of n float32 whose per-block sums
+ * land in partial[blocks].  Non-temporal 16-byte loads and stores, a
+ * grid-stride loop over `blocks` workgroups of 256 threads, four loads in
+ * flight per thread.  n: a positive multiple of 4; src, dst: 16-byte
+ * aligned, not overlapping; blocks in [1, TSPNN_STREAM_MAX_BLOCKS].
+ * TSPNN_E_INVALID otherwise.
+ */
+#define TSPNN_STREAM_MAX_BLOCKS 65536
+tspnn_status tspnn_stream_copy(const float *src, float *dst, int64_t n, int32_t blocks,
+                               void *stream);
+tspnn_status tspnn_stream_read(const float *src, int64_t n, int32_t blocks, float *partial,
+                               void *stream);
+
 const char *tspnn_last_error(void);
 
 #ifdef __cplusplus

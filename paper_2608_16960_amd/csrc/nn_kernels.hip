@@ -784,6 +784,50 @@ tspnn_status mfma_dims(int N, int D0, int D1, int D2) {
     return TSPNN_OK;
 }
 
+// Streaming copy and read of 16-byte elements with non-temporal loads and
+// stores: a measurement of the HBM rate a plain stream reaches on this
+// device, for the roofline of the projector kernels.  Each thread keeps
+// kStreamUnroll independent 16-byte loads in flight per iteration of a
+// grid-stride loop over the whole array.
+constexpr int kStreamUnroll = 4;
+
+__global__ __launch_bounds__(256) void k_stream_copy(const f32x4 *__restrict__ src,
+                                                      f32x4 *__restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
+        f32x4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; u++) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; u++) __builtin_nontemporal_store(v[u], dst + i + u * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// partial[block] = sum of the elements the block read (keeps the loads live)
+__global__ __launch_bounds__(256) void k_stream_read(const f32x4 *__restrict__ src, int64_t n,
+                                                      float *__restrict__ partial) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
+        f32x4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; u++) v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; u++) acc += v[u];
+    }
+    for (; i < n; i += stride) acc += __builtin_nontemporal_load(src + i);
+    float t = acc[0] + acc[1] + acc[2] + acc[3];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    __shared__ float ws[4];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1046,6 +1090,28 @@ tspnn_status tspnn_scale(const float *src, float alpha, int64_t n, float *dst, v
     hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, src, alpha,
                        n, dst);
     return hipret(hipGetLastError(), "tspnn_scale");
+}
+
+tspnn_status tspnn_stream_copy(const float *src, float *dst, int64_t n, int32_t blocks,
+                               void *stream) {
+    g_err.clear();
+    if (!src || !dst || n < 4 || n % 4 || ((uintptr_t)src | (uintptr_t)dst) % 16 ||
+        blocks < 1 || blocks > TSPNN_STREAM_MAX_BLOCKS)
+        return fail(TSPNN_E_INVALID, "tspnn_stream_copy: bad arguments");
+    hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const f32x4 *)src, (f32x4 *)dst, n / 4);
+    return hipret(hipGetLastError(), "tspnn_stream_copy");
+}
+
+tspnn_status tspnn_stream_read(const float *src, int64_t n, int32_t blocks, float *partial,
+                               void *stream) {
+    g_err.clear();
+    if (!src || !partial || n < 4 || n % 4 || (uintptr_t)src % 16 || blocks < 1 ||
+        blocks > TSPNN_STREAM_MAX_BLOCKS)
+        return fail(TSPNN_E_INVALID, "tspnn_stream_read: bad arguments");
+    hipLaunchKernelGGL(k_stream_read, dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const f32x4 *)src, n / 4, partial);
+    return hipret(hipGetLastError(), "tspnn_stream_read");
 }
 
 }  // extern "C"

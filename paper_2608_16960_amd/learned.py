@@ -75,11 +75,17 @@ class WarmStart:
         return self.net.forward(NN.scale(x_in, self.scale), keep=False)
 
     # ------------------------------------------------------------ evaluation
-    def evaluate(self, truth, batch=8):
+    def evaluate(self, truth, batch=8, curves=False, curve_iters=20):
         """Per object: plain calls to R* (= 2K by definition), warm-start calls
-        to R*, whether the fallback was taken, and the residual curves."""
+        to R*, whether the fallback was taken, and the residuals of the CNN
+        output and of x_in.  With curves=True also the residual-vs-calls
+        curves, as medians over the objects of residual / R*: plain GD from
+        zero after 2k calls (k = 0 .. K), and the warm start after 5 + 2k
+        calls (k = 0 .. curve_iters; the GD run for the curve is separate
+        from the counted solve and not counted)."""
         out = {"plain_calls": [], "warm_calls": [], "fallback": [], "R_star": [],
                "warm_res0": [], "xin_res": []}
+        plain_rel, warm_rel = [], []
         for b0 in range(0, truth.shape[0], batch):
             t = truth[b0:b0 + batch]
             B = t.shape[0]
@@ -102,10 +108,23 @@ class WarmStart:
             Fstart = torch.where(use_net.reshape(B, *([1] * (F0.dim() - 1))), F0, F_in)
             solvers.gd(self.op, y, start, self.lam, target=r_star, max_iters=4 * self.K,
                        Fr0=Fstart)
+            if curves:
+                rs = r_star.clamp_min(1e-30)
+                plain_rel.append(torch.stack([h / rs for h in hist]).cpu())
+                free = solvers.CountingOperator(self.P)
+                _, wh, _, _ = solvers.gd(free, y, start, self.lam, iters=curve_iters, Fr0=Fstart)
+                warm_rel.append(torch.stack([h / rs for h in wh]).cpu())
             out["plain_calls"] += plain_calls.tolist()
             out["warm_calls"] += self.op.calls.tolist()
             out["fallback"] += (~use_net).cpu().tolist()
             out["R_star"] += r_star.cpu().tolist()
             out["warm_res0"] += res0.cpu().tolist()
             out["xin_res"] += res_in.cpu().tolist()
+        if curves:
+            pm = torch.cat(plain_rel, 1).double().median(1).values
+            wm = torch.cat(warm_rel, 1).double().median(1).values
+            out["curves"] = {
+                "plain": [[2 * k, float(pm[k])] for k in range(len(pm))],
+                "warm": [[2 * self.k0 + 1 + 2 * k, float(wm[k])] for k in range(len(wm))],
+                "y": "median residual / R*"}
         return out

@@ -48,6 +48,8 @@ SIGNATURES = {
     "tspnn_dot": (_st, [_vp, _vp, _i32, _i64, _vp, _vp, _vp]),
     "tspnn_axpy": (_st, [_vp, _vp, _f, _i32, _i64, _vp, _vp]),
     "tspnn_scale": (_st, [_vp, _f, _i64, _vp, _vp]),
+    "tspnn_stream_copy": (_st, [_vp, _vp, _i64, _i32, _vp]),
+    "tspnn_stream_read": (_st, [_vp, _i64, _i32, _vp, _vp]),
     "tspnn_last_error": (ctypes.c_char_p, []),
 }
 
@@ -330,3 +332,17 @@ class CNN:
         check(lib.tspnn_conv_in_bwd_weight(_p(x), _p(dz), N, D0, D1, D2, _p(dw0), _p(db0),
                                            _p(ws), _s()))
         return [dw0, db0, *gw, *gb, dw5, db5]
+
+
+# ------------------------------------------------------------------ measurement
+
+def stream_copy(src, dst, blocks=4096):
+    """dst <- src by the library's streaming copy kernel (float32, 16-byte aligned)."""
+    check(lib.tspnn_stream_copy(_p(_req(src, torch.float32, "src")),
+                                _p(_req(dst, torch.float32, "dst")), src.numel(), blocks, _s()))
+
+
+def stream_read(src, partial, blocks=4096):
+    """Read every element of src; per-block sums into partial[:blocks]."""
+    check(lib.tspnn_stream_read(_p(_req(src, torch.float32, "src")), src.numel(), blocks,
+                                _p(_req(partial, torch.float32, "partial")), _s()))

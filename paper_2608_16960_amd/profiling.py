@@ -22,6 +22,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {"k_fwd_sell<1>": "csrc/tsp_apply.hip", "k_adj_csc<1>": "csrc/tsp_apply.hip",
+                  "k_tile_y<1>": "csrc/tsp_apply.hip",
                   "k_otf_forward<4>": "csrc/tsp_trace.hip", "k_otf_adjoint<4>": "csrc/tsp_trace.hip"}
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64, published
 COPY_KIB = 1 << 20  # the calibration copy moves 1 GiB each way
@@ -186,6 +187,25 @@ def main_occupancy(argv):
             f.write(f"| `{k}` | {res[0]} | {res[1]} | {res[2]} | {res[3]} | {th} | "
                     f"{c.get('MeanOccupancyPerCU', float('nan')):.1f} | "
                     f"{c.get('OccupancyPercent', float('nan')):.1f}% |\n")
+        f.write("\n# machine-readable: occupancy <kernel> <mean waves per CU> <source sha1>\n")
+        for k in kernels:
+            c = _per_dispatch(pmc_dir, k)
+            if c and k in KERNEL_SOURCES:
+                f.write(f"occupancy {k} {c.get('MeanOccupancyPerCU', float('nan')):.2f} "
+                        f"{source_sha(k)}\n")
+
+
+def read_occupancy(path, kernel):
+    """Mean resident wavefronts per CU of `kernel` from an occupancy summary
+    (its machine-readable lines), or None when absent or taken on a different
+    source of the kernel."""
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 4 and parts[0] == "occupancy" and parts[1] == kernel:
+            return float(parts[2]) if parts[3] == source_sha(kernel) else None
+    return None
 
 
 def main(argv):
