@@ -294,10 +294,11 @@ template <int NB> struct OtfHash {
     static_assert(kBytes <= kOtfHashBytes, "hash table exceeds its LDS reserve");
 };
 
-// Five wavefronts per SIMD (at most 96 VGPRs): the walker fits, and one fewer
-// wavefront to hide the LDS atomics behind costs about 6%.
+// The batch-4 kernel allocates 96 VGPRs, five wavefronts per SIMD; one
+// fewer wavefront to hide the LDS atomics behind costs about 6%.  (Asking
+// for five with amdgpu_waves_per_eu now makes the compiler spill instead.)
 template <int NB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
+__global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
                                                       const float *y, int nb, int64_t V,
                                                       float *x_out) {
     constexpr int HS = OtfHash<NB>::kSize;

@@ -93,9 +93,16 @@ TSP_HD int class_a(const Tab &T, double px, double py, double *phi) {
 
 // Root of cone k's quadratic that lies on the current monotone run of the
 // colatitude.  u_incr: cos(theta) increases across the crossing (Eq. 12
-// "negative").  Roots on the other nappe (z c < 0) and roots where m.n has
-// the wrong sign belong elsewhere.  Falls back to `fb` when rounding leaves
-// no admissible root (a grazing crossing at the run's turning point).
+// "negative").  With f(t) = z^2 - c^2 |p|^2 = A t^2 + 2 B t + C, the two
+// roots have f'/2 = A t + B = +-sqrt(B^2 - A C), and on the nappe z c > 0
+// the test cos(theta) > c reads f > 0 for c > 0 and f < 0 for c < 0.  So the
+// crossing in the wanted direction is the root with sign(f') =
+// (u_incr == (c > 0)) ? + : -, one root of the stable pair
+// q = -(B + sign(B) sqrt(disc)): q / A when that sign is -sign(B), else
+// C / q.  One square root and one division.  Falls back to `fb` when
+// rounding leaves no admissible root (no real root, or the root on the other
+// nappe: a grazing crossing at the run's turning point).  A cone with
+// |c| < 1e-12 is the plane z = 0.
 TSP_HD double cone_root(const Tab &T, int k, bool u_incr, const V3 &x,
                                             const V3 &n, double xx, double xn, double lo,
                                             double hi, double fb) {
@@ -112,28 +119,10 @@ TSP_HD double cone_root(const Tab &T, int k, bool u_incr, const V3 &x,
         if (disc >= 0.0) {
             const double s = sqrt(disc);
             const double q = -(B + copysign(s, B));
-            double r[2];
-            r[0] = (A != 0.0) ? q / A : INFINITY;
-            r[1] = (q != 0.0) ? C / q : ((A != 0.0) ? -B / A : INFINITY);
-            double best = INFINITY, bestd = INFINITY;
-#pragma unroll
-            for (int i = 0; i < 2; i++) {
-                const double tr = r[i];
-                if (!(fabs(tr) < INFINITY)) continue;
-                const double pz = x.z + n.z * tr;
-                if (pz * c < 0.0) continue;  // other nappe
-                const double px = x.x + n.x * tr, py = x.y + n.y * tr;
-                const double pp = px * px + py * py + pz * pz;
-                const double pn = xn + tr;
-                const double dudt = n.z * pp - pz * pn;  // Eq. 12: m . n
-                if (u_incr ? (dudt < 0.0) : (dudt > 0.0)) continue;
-                const double d = (tr < lo) ? lo - tr : ((tr > hi) ? tr - hi : 0.0);
-                if (d < bestd) {
-                    bestd = d;
-                    best = tr;
-                }
-            }
-            if (bestd < INFINITY) t = best;
+            const bool want_pos = (u_incr == (c > 0.0));
+            const bool via_a = want_pos == (copysign(1.0, B) < 0.0);  // wanted sign == -sign(B)
+            const double tr = via_a ? q / A : C / q;
+            if (fabs(tr) < INFINITY && (x.z + n.z * tr) * c >= 0.0) t = tr;
         }
     }
     return fmin(fmax(t, lo), hi);
