@@ -217,6 +217,27 @@ class Adam:
         self.v = [torch.zeros_like(p) for p in self.params]
         self.t = 0
 
+    def state_dict(self):
+        """Optimiser state as host arrays (moments per parameter, step count
+        and hyper-parameters)."""
+        sd = {"t": np.int64(self.t), "lr": np.float64(self.lr),
+              "betas": np.asarray(self.betas, np.float64), "eps": np.float64(self.eps),
+              "wd": np.float64(self.wd)}
+        for k, (m, v) in enumerate(zip(self.m, self.v)):
+            sd[f"m{k}"] = m.detach().cpu().numpy()
+            sd[f"v{k}"] = v.detach().cpu().numpy()
+        return sd
+
+    def load_state_dict(self, sd):
+        self.t = int(sd["t"])
+        self.lr, self.eps, self.wd = float(sd["lr"]), float(sd["eps"]), float(sd["wd"])
+        self.betas = tuple(float(b) for b in np.asarray(sd["betas"]))
+        for k, (m, v) in enumerate(zip(self.m, self.v)):
+            if tuple(sd[f"m{k}"].shape) != tuple(m.shape):
+                raise ValueError(f"moment {k}: shape {sd[f'm{k}'].shape} != {tuple(m.shape)}")
+            m.copy_(torch.from_numpy(np.asarray(sd[f"m{k}"])).to(m.device))
+            v.copy_(torch.from_numpy(np.asarray(sd[f"v{k}"])).to(v.device))
+
     def step(self, grads, bf16_copies=None):
         self.t += 1
         for k, (p, g) in enumerate(zip(self.params, grads)):
@@ -300,9 +321,11 @@ class CNN:
 
     __call__ = forward
 
-    def backward(self, dout):
+    def backward(self, dout, keep=False):
         """Gradients of sum(dout * out) with respect to the parameters, in
-        parameters() order, after forward(..., keep=True)."""
+        parameters() order, after forward(..., keep=True).  keep=True also
+        keeps the gradients reaching each layer's pre-activation (the dz of
+        layers 0 .. 4, bfloat16) in self.dz, for inspection."""
         x, acts = self._acts
         dout = _req(dout.contiguous(), torch.float32, "dout")
         N, D0, D1, D2 = x.shape
@@ -315,6 +338,7 @@ class CNN:
         dz = torch.empty_like(acts[-1])
         check(lib.tspnn_conv_out_bwd(_p(acts[-1]), _p(dout), N, D0, D1, D2, _p(self.w5), _p(dw5),
                                      _p(db5), _p(dz), _p(ws), _s()))
+        kept = [dz]
         for k in range(n - 1, -1, -1):
             # layer k maps acts[k] -> acts[k+1]; dz = dL/d(pre-activation of layer k)
             gw[k] = torch.empty_like(self.wh[k])
@@ -327,6 +351,8 @@ class CNN:
             check(lib.tspnn_conv_bwd_data(_p(dz), N, D0, D1, D2, _p(wt), _p(acts[k]),
                                           _p(dz_prev), _s()))
             dz = dz_prev
+            kept.append(dz)
+        self.dz = kept[::-1] if keep else None
         dw0 = torch.empty_like(self.w0)
         db0 = torch.empty_like(self.b0)
         check(lib.tspnn_conv_in_bwd_weight(_p(x), _p(dz), N, D0, D1, D2, _p(dw0), _p(db0),
@@ -346,3 +372,26 @@ def stream_read(src, partial, blocks=4096):
     """Read every element of src; per-block sums into partial[:blocks]."""
     check(lib.tspnn_stream_read(_p(_req(src, torch.float32, "src")), src.numel(), blocks,
                                 _p(_req(partial, torch.float32, "partial")), _s()))
+
+
+# ------------------------------------------------------------------ checkpoints
+
+def save_checkpoint(path, net, opt=None, **extra):
+    """Write the CNN's FP32 master weights, the optimiser state (if given)
+    and extra scalars to an .npz file (plain arrays, no pickled objects)."""
+    arrs = {f"net_{k}": v for k, v in net.state_dict().items()}
+    if opt is not None:
+        arrs.update({f"opt_{k}": v for k, v in opt.state_dict().items()})
+    arrs.update({f"extra_{k}": np.asarray(v) for k, v in extra.items()})
+    np.savez(path, **arrs)
+
+
+def load_checkpoint(path, net, opt=None):
+    """Restore what save_checkpoint wrote (the BF16 weight copies are
+    re-derived from the masters); returns the extra scalars."""
+    with np.load(path, allow_pickle=False) as z:
+        net.load_state_dict({k[4:]: z[k] for k in z.files if k.startswith("net_")})
+        if opt is not None:
+            opt.load_state_dict({k[4:]: z[k] for k in z.files if k.startswith("opt_")})
+        return {k[6:]: z[k][()] for k in z.files if k.startswith("extra_")}
+

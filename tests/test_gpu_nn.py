@@ -71,7 +71,7 @@ def test_adam_matches_reference(nn):
     assert torch.equal(pb, p.to(torch.bfloat16))
 
 
-SHAPES = [(2, 5, 4, 64), (1, 3, 6, 32), (1, 2, 5, 96), (1, 3, 9, 128)]
+SHAPES = [(2, 5, 4, 64), (1, 3, 6, 32), (1, 2, 5, 96), (1, 3, 9, 128), (2, 6, 5, 32), (1, 4, 7, 64)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -212,8 +212,27 @@ def test_conv_edge_layers(nn, D2):
 
 
 def test_cnn_end_to_end_gradient(nn):
-    """Whole-network gradient against an FP64 replica that rounds weights and
-    activations to bfloat16 at the same points as the kernels."""
+    """The whole network's forward and backward, element by element, link by
+    link on the kernels' own intermediates.
+
+    Each activation must be the FP64 layer of the previous activation the
+    network produced, rounded once to bfloat16 (within one BF16 rounding,
+    2^-8 relative, plus 1e-6 of the scale for the FP32 accumulation); each
+    dz (the gradient reaching a pre-activation, kept in bfloat16) the FP64
+    transposed layer of the next dz with the ReLU mask of the activation;
+    and every parameter's gradient, element by element, the FP64 sum over
+    the network's own activation and dz pairs, within 1e-5 of the sum of the
+    terms' magnitudes (FP32 accumulation).  So every step of the chain and
+    its wiring (which activation meets which dz, the flipped weights, the
+    masks, the output layer and the residual) is checked exactly.
+
+    A replica run from the input in FP64 cannot be held to that bar: a BF16
+    rounding that FP32 and FP64 decide differently changes one element by
+    one unit, and through the next layer's 864-term sums that moves enough
+    neighbours across a rounding boundary that the share of differing
+    elements grows about tenfold per layer (measured: 3e-5, 1e-4, 2e-4,
+    2e-3, 1e-2 of the activations of layers 0 .. 4).  It is checked here by
+    its norm instead: within 5% for every parameter's gradient."""
     N, D0, D1, D2 = 2, 6, 5, 32
     net = nn.CNN(device="cuda", seed=11, scale_out=1.0)
     g = torch.Generator().manual_seed(6)
@@ -221,26 +240,73 @@ def test_cnn_end_to_end_gradient(nn):
     dout = torch.randn((N, D0, D1, D2), generator=g)
     D = _dev(x=x, dout=dout)
     out = net.forward(D["x"])
-    grads = net.backward(D["dout"])
+    grads = net.backward(D["dout"], keep=True)
+    acts = [a.float().cpu().double() for a in net._acts[1]]      # a_0 .. a_4
+    dzs = [t.float().cpu().double() for t in net.dz]            # dz of layers 0 .. 4
+    assert len(acts) == 5 and len(dzs) == 5
 
+    def bf(t):
+        return t.to(torch.bfloat16).double()
+
+    w0, b0 = net.w0.cpu().double(), net.b0.cpu().double()
+    wh = [bf(w.cpu().double()) for w in net.wh]
+    assert all(torch.equal(bf(w.cpu().double()), w2.float().cpu().double())
+               for w, w2 in zip(net.wh, net.wh_bf))
+    bh = [b.cpu().double() for b in net.bh]
+    w5, b5 = net.w5.cpu().double(), net.b5.cpu().double()
+    x64, d64 = x.double(), dout.double()
+
+    # forward, link by link
+    _close_bf16(net._acts[1][0], torch.relu(OC.conv(x64[..., None], w0[:, :, None], b0)))
+    for k in range(4):
+        _close_bf16(net._acts[1][k + 1], torch.relu(OC.conv(acts[k], wh[k], bh[k])))
+    ref_out = x64 + OC.conv(acts[4], w5[:, None, :], b5)[..., 0]
+    assert float((out.cpu().double() - ref_out).abs().max()) <= 1e-5 * float(ref_out.abs().max())
+
+    def conv_t(e, w):  # gradient of <conv(A, w), e> with respect to A
+        A = torch.zeros((*e.shape[:-1], w.shape[2]), dtype=torch.float64, requires_grad=True)
+        (OC.conv(A, w) * e).sum().backward()
+        return A.grad
+
+    # backward, link by link: dz_4 from dout, then dz_{k-1} from dz_k
+    _close_bf16(net.dz[4], conv_t(d64[..., None], w5[:, None, :]) * (acts[4] > 0))
+    for k in range(4, 0, -1):
+        _close_bf16(net.dz[k - 1], conv_t(dzs[k], wh[k - 1]) * (acts[k - 1] > 0))
+
+    def wsum(a, e, wshape, bshape):  # sum_p a(p + tap) e(p) per weight and sum_p e(p)
+        wd = torch.zeros(wshape, dtype=torch.float64, requires_grad=True)
+        bd = torch.zeros(bshape, dtype=torch.float64, requires_grad=True)
+        (OC.conv(a, wd, bd) * e).sum().backward()
+        return wd.grad, bd.grad
+
+    refs, mags = [], []
+    for a_in, e, ws, bs in [(x64[..., None], dzs[0], (27, 32, 1), (32,))] + \
+            [(acts[k], dzs[k + 1], (27, 32, 32), (32,)) for k in range(4)] + \
+            [(acts[4], d64[..., None], (27, 1, 32), (1,))]:
+        refs.append(wsum(a_in, e, ws, bs))
+        mags.append(wsum(a_in.abs(), e.abs(), ws, bs))
+    ref_list = [refs[0][0][:, :, 0], refs[0][1], *[r[0] for r in refs[1:5]],
+                *[r[1] for r in refs[1:5]], refs[5][0][:, 0, :], refs[5][1]]
+    mag_list = [mags[0][0][:, :, 0], mags[0][1], *[m[0] for m in mags[1:5]],
+                *[m[1] for m in mags[1:5]], mags[5][0][:, 0, :], mags[5][1]]
+    for k, (gg, ref, mag) in enumerate(zip(grads, ref_list, mag_list)):
+        err = (gg.cpu().double() - ref).abs()
+        tol = 1e-5 * mag + 1e-7 * float(mag.max())
+        assert bool((err <= tol).all()), (k, float((err / tol).max()))
+
+    # a replica from the input: gradients within 5% in norm (BF16 chaos above)
     params = [p.detach().cpu().double().clone().requires_grad_(True) for p in net.parameters()]
-    w0, b0 = params[0], params[1]
-    wh, bh = params[2:6], params[6:10]
-    w5, b5 = params[10], params[11]
 
-    def bfr(t):  # round to bf16 in the forward pass, identity gradient
+    def bfr(t):
         return t + (t.to(torch.bfloat16).double() - t).detach()
 
-    a = bfr(torch.relu(OC.conv(x.double()[..., None], w0[:, :, None], b0)))
-    for w, b in zip(wh, bh):
+    a = bfr(torch.relu(OC.conv(x64[..., None], params[0][:, :, None], params[1])))
+    for w, b in zip(params[2:6], params[6:10]):
         a = bfr(torch.relu(OC.conv(a, bfr(w), b)))
-    ref_out = x.double() + OC.conv(a, w5[:, None, :], b5)[..., 0]
-    (ref_out * dout.double()).sum().backward()
-    assert float((out.cpu().double() - ref_out).abs().max()) <= 1e-2 * float(ref_out.abs().max())
+    ((x64 + OC.conv(a, params[10][:, None, :], params[11])[..., 0]) * d64).sum().backward()
     for k, (gg, p) in enumerate(zip(grads, params)):
         gc, gr = gg.cpu().double().reshape(-1), p.grad.reshape(-1)
-        cos = float(gc @ gr / (gc.norm() * gr.norm() + 1e-30))
-        assert cos > 0.995, (k, cos)
+        assert float((gc - gr).norm()) <= 0.05 * float(gr.norm()), k
 
 
 def test_vector_steps(nn):
@@ -283,3 +349,41 @@ def test_vector_steps(nn):
     with pytest.raises(TspnnError):
         nn.check(nn.lib.tspnn_residual(nn._p(yt), nn._p(ft), 0, n, None, nn._p(out), None,
                                        nn._p(out), nn._s()))
+
+
+def test_checkpoint_resume_is_bitwise(nn, tmp_path):
+    """Training resumed from a checkpoint (FP32 master weights + Adam state,
+    an .npz of plain arrays) continues bit for bit as the uninterrupted run:
+    the kernels are deterministic and the BF16 copies are re-derived from
+    the masters."""
+    N, D0, D1, D2 = 2, 4, 5, 32
+    g = torch.Generator().manual_seed(21)
+    batches = [(torch.randn((N, D0, D1, D2), generator=g).cuda(),
+                torch.randn((N, D0, D1, D2), generator=g).cuda()) for _ in range(5)]
+
+    def train(net, opt, bs):
+        for x, t in bs:
+            out = net.forward(x)
+            nn.residual(t.reshape(1, -1), out.reshape(1, -1), diff=out.reshape(1, -1))
+            grads = net.backward(nn.scale(out, 2.0 / out.numel(), out=out))
+            opt.step(grads, bf16_copies=net.bf16_targets())
+
+    net = nn.CNN(device="cuda", seed=3)
+    opt = nn.Adam(net.parameters(), lr=1e-3, weight_decay=1e-4)
+    train(net, opt, batches[:2])
+    ck = tmp_path / "ck.npz"
+    nn.save_checkpoint(ck, net, opt, scale=1.25, epoch=2)
+    train(net, opt, batches[2:])
+
+    net2 = nn.CNN(device="cuda", seed=99)
+    opt2 = nn.Adam(net2.parameters(), lr=0.5)
+    extra = nn.load_checkpoint(ck, net2, opt2)
+    assert float(extra["scale"]) == 1.25 and int(extra["epoch"]) == 2
+    assert opt2.t == 2 and opt2.lr == 1e-3 and opt2.wd == 1e-4
+    train(net2, opt2, batches[2:])
+    for p, q in zip(net.parameters(), net2.parameters()):
+        assert torch.equal(p, q)
+    for a, b in zip(net.wh_bf, net2.wh_bf):
+        assert torch.equal(a, b)
+    for a, b in zip(opt.m + opt.v, opt2.m + opt2.v):
+        assert torch.equal(a, b)
