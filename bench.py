@@ -374,12 +374,21 @@ def extra_diff_csr():
     fb, ab = 8 * S + 8 * R + 4 * R + 4 * V, 8 * S + 8 * V + 4 * V + 4 * R
     P.close()
     torch.cuda.empty_cache()
+    from paper_2608_16960_amd.profiling import read_traffic
+    tf = os.path.join(ROOT, "profiles", "hbm_traffic_diff.txt")
+    traffic = {k: read_traffic(tf, kern) for k, kern in (("forward", "k_fwd_sell<1>"),
+                                                           ("adjoint", "k_adj_csc<1>"))}
     return {"workload": f"diff: grid {P.shape}, {w.views.n_views} cone views "
                         f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch 1",
             "trace_s": trace_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
             "rays_per_s": R / (f_ms + a_ms) * 1e3, "segments_per_s": S / (f_ms + a_ms) * 1e3,
             "forward_hbm_frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
-            "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS}
+            "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS,
+            "forward_traffic_frac": None if traffic["forward"] is None
+            else traffic["forward"] / f_ms / 1e6 / HBM_PEAK_GBS,
+            "adjoint_traffic_frac": None if traffic["adjoint"] is None
+            else traffic["adjoint"] / a_ms / 1e6 / HBM_PEAK_GBS,
+            "traffic_bytes": traffic}
 
 
 def extra_atten_medium(reps=10):
@@ -405,12 +414,14 @@ def extra_atten_medium(reps=10):
     y, tau = M.forward(rho, keep_tau=True)
     gy = torch.randn_like(y)
     f_ms = _time_ms(lambda: M.forward(rho, keep_tau=True), reps)
-    b_ms = _time_ms(lambda: M.backward(rho, tau, gy), reps)
+    b_ms = _time_ms(lambda: M.backward(rho, tau, gy, "deterministic"), reps)
+    ba_ms = _time_ms(lambda: M.backward(rho, tau, gy, "atomic"), reps)
     inf, infs = P.info(), M.sun.info()
     R = inf["n_rays"]
     out = {"workload": f"medium with attenuation: {R} lines of sight, {inf['n_voxels']} sunward "
                        f"rays, {inf['n_segments']} + {infs['n_segments']} segments, batch 1",
            "sun_trace_s": sun_s, "forward_ms": f_ms, "backward_ms": b_ms,
+           "backward_atomic_ms": ba_ms,
            "forward_rays_per_s": R / f_ms * 1e3, "forward_backward_rays_per_s": R / (f_ms + b_ms) * 1e3}
     P.close()
     M.sun.close()
@@ -567,7 +578,8 @@ def main():
     from paper_2608_16960_amd.profiling import read_occupancy, read_traffic
     prof = os.path.join(ROOT, "profiles")
     for k in kern.values():
-        k["traffic_bytes"] = read_traffic(os.path.join(prof, "hbm_traffic_medium.txt"), k["kernel"])
+        k["traffic_bytes"] = read_traffic(os.path.join(prof, f"hbm_traffic_{w.name}.txt"),
+                                          k["kernel"])
         if k["traffic_bytes"] is not None:
             k["traffic_GBps"] = k["traffic_bytes"] / k["ms"] / 1e6
     traffic = d["traffic_bytes"]

@@ -316,17 +316,29 @@ tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, c
 
 /*
  * Gradient of sum_b <gy[b], y[b]> with respect to rho for the attenuated
- * forward: through w (exp(-tau1) gw), through T along each line of sight, and
- * through tau1 (F_sun^T of -w gw).  The line-of-sight scatter uses atomic
- * adds, so the result is not bitwise reproducible.
+ * forward (Sec. 9.3, Eqs. 17-18 differentiated): through w (exp(-tau1) gw),
+ * through T along each line of sight, and through tau1 (F_sun^T of -w gw).
+ * method:
+ *   TSP_ADJ_ATOMIC: the line-of-sight terms are scattered with float atomic
+ *     adds (merged per voxel across a wavefront first); the summation order,
+ *     and so the last bits, vary from run to run.
+ *   TSP_ADJ_DETERMINISTIC: the same merged terms are added as exact
+ *     fixed-point integers (three 32-bit limbs of a 96-bit value with a
+ *     scale from a bound on the terms, in 64-bit integer atomics), so every
+ *     voxel's sum is exact up to terms below 2^-95 of that bound and the
+ *     result is bitwise reproducible; F_sun^T uses the sunward geometry's
+ *     deterministic adjoint, which must have its voxel-major store
+ *     (TSP_E_STATE otherwise).
  * rho, sigma as for tsp_atten_forward; tau1: [batch][V] from
  * tsp_atten_forward of the same rho; gy: device float32 [batch][R];
  * grad: device float32 [batch][V], overwritten.  Temporaries: 6 floats per
- * voxel and object, stream-ordered.  Errors as for tsp_atten_forward.
+ * voxel and object (and 48 bytes per voxel for the deterministic sums),
+ * stream-ordered.  Errors as for tsp_atten_forward, and TSP_E_INVALID for an
+ * unknown method.
  */
 tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
                               const float *sigma, const float *tau1, const float *gy,
-                              int32_t batch, float *grad, void *stream);
+                              int32_t batch, float *grad, int32_t method, void *stream);
 
 /*
  * Export the canonical segment lists (the region index and length arrays of

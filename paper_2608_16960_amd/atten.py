@@ -51,14 +51,20 @@ class Attenuated:
                                         N.stream_handle()))
         return (y, tau) if keep_tau else y
 
-    def backward(self, rho, tau, gy):
-        """d<gy, y>/d rho for the rho whose forward produced tau."""
+    def backward(self, rho, tau, gy, method=None):
+        """d<gy, y>/d rho for the rho whose forward produced tau.  method:
+        "deterministic" (exact fixed-point sums, bitwise reproducible; needs
+        the sunward geometry's voxel-major store), "atomic", or None: the
+        deterministic one when the sunward geometry has its store."""
         rho, lead, B = self._lead(rho)
         tau = self._f32(tau, "tau")
         gy = self._f32(gy, "gy")
+        if method is None:
+            method = "deterministic" if self.sun.csc else "atomic"
+        m = {"deterministic": N.TSP_ADJ_DETERMINISTIC, "atomic": N.TSP_ADJ_ATOMIC}[method]
         grad = torch.empty_like(rho)
         N.check(N.lib.tsp_atten_backward(self.P._h, self.sun._h, N.ptr(rho), N.ptr(self.sigma),
-                                         N.ptr(tau), N.ptr(gy), B, N.ptr(grad),
+                                         N.ptr(tau), N.ptr(gy), B, N.ptr(grad), m,
                                          N.stream_handle()))
         return grad
 

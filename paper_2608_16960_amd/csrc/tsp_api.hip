@@ -72,6 +72,7 @@ struct tsp_geometry {
     RayDesc rd{};
     double *d_frames = nullptr, *d_starts = nullptr, *d_dirs = nullptr;
     int64_t V = 0, R = 0;
+    double r_out = 0.0;  // outer radius of the grid
     int mode = 0;
     int64_t S = 0, max_per_ray = 0, n_stored = 0;
     // ray-major sliced store
@@ -531,6 +532,7 @@ tsp_status create_geometry(const tsp_grid_desc *grid, const tsp_view *views, int
     }
     g->V = V;
     g->R = R;
+    g->r_out = Rout;
 
     // boundary tables
     std::vector<double> tab;
@@ -1334,16 +1336,22 @@ tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, c
 
 tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, const float *rho,
                               const float *sigma, const float *tau1, const float *gy,
-                              int32_t batch, float *grad, void *stream) {
+                              int32_t batch, float *grad, int32_t method, void *stream) {
     g_err.clear();
     tsp_status s;
     if ((s = atten_check(g, g_sun, batch)) != TSP_OK) return s;
     if (!rho || !sigma || !tau1 || !gy || !grad)
         return fail(TSP_E_INVALID, "rho, sigma, tau1, gy or grad is NULL");
+    if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC)
+        return fail(TSP_E_INVALID, "method must be TSP_ADJ_DETERMINISTIC or TSP_ADJ_ATOMIC");
+    const bool det = method == TSP_ADJ_DETERMINISTIC;
+    if (det && !g_sun->d_col_ptr)
+        return fail(TSP_E_STATE, "deterministic attenuated backward needs the sunward geometry "
+                                 "traced with its voxel-major store");
     DeviceGuard dg(g->device);
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = g->V * batch;
-    const int method = g_sun->d_col_ptr ? TSP_ADJ_DETERMINISTIC : TSP_ADJ_ATOMIC;
+    const int sun_method = g_sun->d_col_ptr ? TSP_ADJ_DETERMINISTIC : TSP_ADJ_ATOMIC;
     hipError_t e = hipSuccess;
     AsyncBufs tmp(st);
     float *sv = tmp.get(n, &e);
@@ -1352,16 +1360,17 @@ tsp_status tsp_atten_backward(const tsp_geometry *g, const tsp_geometry *g_sun, 
     float *gsl = tmp.get(n, &e);
     float *gt = tmp.get(n, &e);
     float *gsun = tmp.get(n, &e);
+    float *ws = det ? tmp.get((int64_t)(atten_fixed_ws_bytes(g->V) + 3) / 4, &e) : nullptr;
     if (e == hipSuccess) e = launch_atten_s(sigma, rho, g->V, batch, sv, st);
     if (e == hipSuccess) e = launch_atten_w(tau1, rho, n, w, st);
-    if (e == hipSuccess) e = launch_zero_f32(gw, n, st);
-    if (e == hipSuccess) e = launch_zero_f32(gsl, n, st);
+    if (e == hipSuccess && !det) e = launch_zero_f32(gw, n, st);
+    if (e == hipSuccess && !det) e = launch_zero_f32(gsl, n, st);
     if (e == hipSuccess)
         e = launch_bwd_atten(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr, g->d_slice_len,
                              g->d_code, g->d_len, sv, w, gy, batch, g->V, g->T.na,
-                             g->T.ne * g->T.na, gw, gsl, st);
+                             g->T.ne * g->T.na, g->r_out, gw, gsl, ws, st);
     if (e == hipSuccess) e = launch_atten_gtau(w, gw, n, gt, st);
-    if (e == hipSuccess) e = adjoint_dispatch(g_sun, gt, batch, gsun, method, st);  // F_1^T
+    if (e == hipSuccess) e = adjoint_dispatch(g_sun, gt, batch, gsun, sun_method, st);  // F_1^T
     if (e == hipSuccess)
         e = launch_atten_grad(tau1, sigma, gw, gsl, gsun, g->V, batch, grad, st);
     const hipError_t r = tmp.release();

@@ -21,6 +21,17 @@
 // same voxel in the same step are summed before one atomic add, as in the
 // atomic adjoint.  The chain rule through w and tau_1 (F_1^T) and the
 // elementwise combination run as separate small kernels.
+//
+// Deterministic backward: the merged contributions are added as exact
+// fixed-point integers instead of floats.  Each value v becomes the signed
+// integer round-toward-zero(v / 2^qe), a 96-bit magnitude held in three
+// 32-bit limbs, and each limb goes into its own 64-bit accumulator of the
+// voxel with an integer atomic add.  Integer addition is exact and
+// associative, so the sums (and the float each voxel finally gets) do not
+// depend on the order in which the atomics land: bitwise reproducible.  qe
+// comes from a bound M on any merged value, M < 2^95 2^qe, so no limb sum
+// can overflow for fewer than 2^31 contributions per voxel; values below
+// 2^qe (about 2^-95 M) are truncated.
 
 #include "tsp_internal.h"
 
@@ -98,6 +109,65 @@ __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ p
     y[ray] = acc;
 }
 
+// Add v (exact) into the three limb accumulators acc[0..2][i] of stride V:
+// |v| / 2^qe = l2 2^64 + l1 2^32 + l0 with 0 <= l < 2^32, signed by v.
+__device__ __forceinline__ void fixed_add(unsigned long long *acc, int64_t V, int64_t i, float v,
+                                          int qe) {
+    if (v == 0.0f) return;
+    const double a = ldexp(fabs((double)v), -qe);  // exact: a power-of-two scaling
+    const double l2 = floor(ldexp(a, -64));
+    const double r = a - ldexp(l2, 64);              // exact
+    const double l1 = floor(ldexp(r, -32));
+    const double l0 = floor(r - ldexp(l1, 32));      // truncates below 2^qe
+    const int64_t sg = (v < 0.0f) ? -1 : 1;
+    // a zero limb adds nothing: most values lie far below the bound, and
+    // their top limb (and often the middle one) is zero
+    if (l0 != 0.0) atomicAdd(acc + i, (unsigned long long)(sg * (int64_t)l0));
+    if (l1 != 0.0) atomicAdd(acc + V + i, (unsigned long long)(sg * (int64_t)l1));
+    if (l2 != 0.0) atomicAdd(acc + 2 * V + i, (unsigned long long)(sg * (int64_t)l2));
+}
+
+// Scale exponent of the fixed-point sums: M = 64 max|g| 2 R (1 + 2 R max|w|)
+// bounds any merged contribution of either gradient term (64 lanes, a
+// length below the outer sphere's diameter 2 R, exp(-T) <= 1, and a suffix
+// sum below 2 R max|w|); bits[0], bits[1] hold max|g| and max|w| as float
+// bits (non-negative floats order like their bit patterns).
+__device__ __forceinline__ int fixed_exponent(const unsigned *bits, double two_r) {
+    const double mg = (double)__uint_as_float(bits[0]);
+    const double mw = (double)__uint_as_float(bits[1]);
+    const double M = 64.0 * fmax(mg, 1e-30) * two_r * (1.0 + two_r * mw);
+    return ilogb(M) + 1 - 95;
+}
+
+// out[0] = max |a| over n floats, as float bits, by atomicMax (out zeroed first)
+__global__ void k_absmax(const float *__restrict__ a, int64_t n, unsigned *out) {
+    unsigned m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, __float_as_uint(fabsf(a[i])));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+// x[i] = the float of the exact sum held in the limbs, times 2^qe: the limbs
+// are carried into canonical form first, then converted once to double
+// (rounded) and to float.
+__global__ void k_fixed_to_float(const unsigned long long *acc, int64_t V,
+                                 const unsigned *bits, double two_r, float *x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V) return;
+    const int qe = fixed_exponent(bits, two_r);
+    int64_t a0 = (int64_t)acc[i], a1 = (int64_t)acc[V + i], a2 = (int64_t)acc[2 * V + i];
+    a1 += a0 >> 32;  // arithmetic shifts: floor division by 2^32
+    const uint64_t r0 = (uint64_t)a0 & 0xffffffffull;
+    a2 += a1 >> 32;
+    const uint64_t r1 = (uint64_t)a1 & 0xffffffffull;
+    const double lo = (double)((r1 << 32) | r0);
+    x[i] = (float)ldexp(ldexp((double)a2, 64) + lo, qe);
+}
+
+template <bool FIXED>
 __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cnt_sorted,
                                                     const int64_t *__restrict__ slice_ptr,
@@ -107,9 +177,13 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                                                     int64_t n_slots, const float *__restrict__ s,
                                                     const float *__restrict__ w,
                                                     const float *__restrict__ gy, int na,
-                                                    int nena, float *gw, float *gs) {
+                                                    int nena, float *gw, float *gs,
+                                                    unsigned long long *acc, int64_t V,
+                                                    const unsigned *bits, double two_r) {
+    // FIXED: acc holds the limbs of gw ([3][V]) then of gs ([3][V])
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
+    const int qe = FIXED ? fixed_exponent(bits, two_r) : 0;
     const int lane = (int)(slot & 63);
     const int32_t ray = perm[slot];
     const int c = (ray >= 0) ? cnt_sorted[slot] : 0;
@@ -160,7 +234,11 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                 prefix += ck;
             }
             uint64_t pend = __ballot(v >= 0);
-            // uniform over the wavefront: every lane is active
+            // uniform over the wavefront: every lane is active.  The merged
+            // sums stay with their leader lanes (mv, ma, mb); the fixed-point
+            // path then converts and adds them on all those lanes at once.
+            int mv = -1;
+            float ma = 0.0f, mb = 0.0f;
             for (int it = 0; pend && it < kMaxMerges; it++) {
                 const int leader = __ffsll((unsigned long long)pend) - 1;
                 const int v0 = __builtin_amdgcn_readlane(v, leader);
@@ -168,14 +246,30 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                 const float sa = wave_sum_f32(mine ? a : 0.0f);
                 const float sb = wave_sum_f32(mine ? bterm : 0.0f);
                 if (lane == leader) {
-                    atomicAdd(gw + v0, sa);
-                    atomicAdd(gs + v0, sb);
+                    if (FIXED) {
+                        mv = v0;
+                        ma = sa;
+                        mb = sb;
+                    } else {
+                        atomicAdd(gw + v0, sa);
+                        atomicAdd(gs + v0, sb);
+                    }
                 }
                 pend &= ~__ballot(mine);
             }
             if ((pend >> lane) & 1ull) {  // past the merge limit
-                atomicAdd(gw + v, a);
-                atomicAdd(gs + v, bterm);
+                if (FIXED) {
+                    mv = v;
+                    ma = a;
+                    mb = bterm;
+                } else {
+                    atomicAdd(gw + v, a);
+                    atomicAdd(gs + v, bterm);
+                }
+            }
+            if (FIXED && mv >= 0) {
+                fixed_add(acc, V, mv, ma, qe);
+                fixed_add(acc + 3 * V, V, mv, mb, qe);
             }
         }
     }
@@ -229,16 +323,37 @@ hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
 hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
                             const uint8_t *code, const float *len, const float *s, const float *w,
-                            const float *gy, int B, int64_t V, int na, int nena, float *gw,
-                            float *gs, hipStream_t st) {
+                            const float *gy, int B, int64_t V, int na, int nena, double r_out,
+                            float *gw, float *gs, void *ws, hipStream_t st) {
+    const double two_r = 2.0 * r_out;
     for (int b = 0; b < B; b++) {
-        hipLaunchKernelGGL(k_bwd_atten, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
-                           cnt_sorted, slice_ptr, slice_len, code, len, rd.n_slots, s + b * V,
-                           w + b * V, gy + b * rd.R, na, nena, gw + b * V, gs + b * V);
+        const unsigned grid = blocks_for(rd.n_slots, 256);
+        if (!ws) {
+            hipLaunchKernelGGL(k_bwd_atten<false>, dim3(grid), dim3(256), 0, st, perm, cnt_sorted,
+                               slice_ptr, slice_len, code, len, rd.n_slots, s + b * V, w + b * V,
+                               gy + b * rd.R, na, nena, gw + b * V, gs + b * V, nullptr, V,
+                               nullptr, two_r);
+        } else {
+            unsigned long long *acc = (unsigned long long *)ws;
+            unsigned *bits = (unsigned *)(acc + 6 * V);
+            hipError_t e = hipMemsetAsync(ws, 0, atten_fixed_ws_bytes(V), st);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_absmax, dim3(256), dim3(256), 0, st, gy + b * rd.R, rd.R, bits);
+            hipLaunchKernelGGL(k_absmax, dim3(256), dim3(256), 0, st, w + b * V, V, bits + 1);
+            hipLaunchKernelGGL(k_bwd_atten<true>, dim3(grid), dim3(256), 0, st, perm, cnt_sorted,
+                               slice_ptr, slice_len, code, len, rd.n_slots, s + b * V, w + b * V,
+                               gy + b * rd.R, na, nena, nullptr, nullptr, acc, V, bits, two_r);
+            hipLaunchKernelGGL(k_fixed_to_float, dim3(blocks_for(V, 256)), dim3(256), 0, st, acc,
+                               V, bits, two_r, gw + b * V);
+            hipLaunchKernelGGL(k_fixed_to_float, dim3(blocks_for(V, 256)), dim3(256), 0, st,
+                               acc + 3 * V, V, bits, two_r, gs + b * V);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
+
+size_t atten_fixed_ws_bytes(int64_t V) { return (size_t)V * 48 + 64; }
 
 }  // namespace tsp

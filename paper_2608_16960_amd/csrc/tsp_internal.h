@@ -337,11 +337,15 @@ hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
                             const int64_t *slice_ptr, const int32_t *slice_len,
                             const uint8_t *code, const float *len, const float *s, const float *w,
                             int B, int64_t V, int na, int nena, float *y, hipStream_t st);
+// gw, gs overwritten (zeroed by the caller when ws is null: float atomics);
+// ws non-null: atten_fixed_ws_bytes(V) bytes for the exact fixed-point sums
+// of the deterministic backward.  r_out: the grid's outer radius.
 hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
                             const uint8_t *code, const float *len, const float *s, const float *w,
-                            const float *gy, int B, int64_t V, int na, int nena, float *gw,
-                            float *gs, hipStream_t st);
+                            const float *gy, int B, int64_t V, int na, int nena, double r_out,
+                            float *gw, float *gs, void *ws, hipStream_t st);
+size_t atten_fixed_ws_bytes(int64_t V);
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st);
 
 }  // namespace tsp

@@ -74,7 +74,8 @@ SIGNATURES = {
     "tsp_geometry_create_sunward": (_st, [ctypes.POINTER(tsp_grid_desc), _dp,
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "tsp_atten_forward": (_st, [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
-    "tsp_atten_backward": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp, _vp]),
+    "tsp_atten_backward": (_st, [_vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                 ctypes.c_int32, _vp]),
     "tsp_trace": (_st, [_vp, ctypes.c_int32, _vp]),
     "tsp_forward": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "tsp_backproject": (_st, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32, _vp]),

@@ -6,7 +6,8 @@ Bars:
   - interior and sunward rays: the static parity bars (bit-exact index
     lists on non-tie rays, FP32 lengths, forward / adjoint within 1e-5 of the
     absolute integrand);
-  - attenuated model: the projection bar (1e-5 of the absolute integrand)
+  - attenuated model (both backward methods; the deterministic one is
+    also bitwise repeatable): the projection bar (1e-5 of the absolute integrand)
     carried through the model's arithmetic to first order.  A segment's
     term w[v] exp(-T) len has its optical depths tau_1[v] and T from FP32
     projections, each within 1e-5 of the same depth of |sigma rho|
@@ -127,20 +128,23 @@ def _check_atten(ora, grid, P, starts, dirs, rho, sun, seed, sample=None):
     if sample is not None:
         return
     gyt = torch.from_numpy(gy).to(dev).reshape(rho.shape[0], *P.out_shape)
-    grad = M.backward(rho_t, tau, gyt).reshape(rho.shape[0], -1).cpu().numpy()
-    for b in range(rho.shape[0]):
-        r64, s64 = rho[b].reshape(-1).astype(np.float64), sig.reshape(-1).astype(np.float64)
-        go = A.gradient(tr, trs, r64, s64, gy[b].astype(np.float64))
-        _, gbound, kappa = _bounds(ora, tr, trs, r64, s64, gy[b].astype(np.float64))
-        err = np.abs(grad[b] - go)
-        tol = 1e-5 * kappa * gbound + 1e-9 * gbound.max()
-        assert np.all(err <= tol), (b, float(np.max(err / (kappa * gbound + 1e-30))))
-    # the autograd wrapper runs the same backward
+    for method in ("deterministic", "atomic"):
+        grad = M.backward(rho_t, tau, gyt, method).reshape(rho.shape[0], -1).cpu().numpy()
+        for b in range(rho.shape[0]):
+            r64, s64 = rho[b].reshape(-1).astype(np.float64), sig.reshape(-1).astype(np.float64)
+            go = A.gradient(tr, trs, r64, s64, gy[b].astype(np.float64))
+            _, gbound, kappa = _bounds(ora, tr, trs, r64, s64, gy[b].astype(np.float64))
+            err = np.abs(grad[b] - go)
+            tol = 1e-5 * kappa * gbound + 1e-9 * gbound.max()
+            assert np.all(err <= tol), (method, b, float(np.max(err / (kappa * gbound + 1e-30))))
+    # the deterministic backward repeats bit for bit, and the autograd
+    # wrapper runs it
+    g1 = M.backward(rho_t, tau, gyt, "deterministic")
+    assert torch.equal(g1, M.backward(rho_t, tau, gyt, "deterministic"))
     from paper_2608_16960_amd.atten import AttenuatedFn
     r = rho_t.clone().requires_grad_(True)
     (AttenuatedFn.apply(r, M) * gyt).sum().backward()
-    assert torch.allclose(r.grad, M.backward(rho_t, tau, gyt), rtol=1e-5,
-                          atol=1e-6 * float(np.abs(grad).max()))
+    assert torch.equal(r.grad, g1)
 
 
 def test_attenuated_tiny(ora, dev):
