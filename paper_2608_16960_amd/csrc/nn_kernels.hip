@@ -412,13 +412,16 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// The same layer with its inputs staged in LDS.  A workgroup of eight
-// wavefronts takes two r-rows (i0, i0+1) by four e-rows (j0 .. j0+3) of one
-// object and up to 64 azimuths a0 .. a0+63.  It stages the 4 x 6 neighbour
-// rows those outputs read (each input row is fetched by 3 workgroups per
-// output row instead of 4.5 with tiles of one r-row), each with one azimuth
-// of circular halo on both sides (66 voxels of 64 bytes; rows outside the
-// grid as zeros), then wavefront w computes row (i0 + w / 4, j0 + w % 4):
+// The same layer with its inputs staged in LDS.  A workgroup of four
+// wavefronts takes two r-rows (i0, i0+1) by two e-rows (j0, j0+1) of one
+// object and up to 64 azimuths a0 .. a0+63.  It stages the 4 x 4 neighbour
+// rows those outputs read (67.6 KB, so that two workgroups share a CU and one
+// stages while the other computes: 106 -> 97 us at batch 8 of 64 x 32 x 64,
+// against tiles of 2 x 4 rows at one workgroup per CU, though each input row
+// is then fetched by 4 workgroups per output row instead of 3), each with
+// one azimuth of circular halo on both sides (66 voxels of 64 bytes; rows
+// outside the grid as zeros), then wavefront w computes row
+// (i0 + w / 2, j0 + w % 2):
 // 27 taps of 8 MFMAs with no branch between them, the
 // voxel fragments read from LDS and the weight fragments (which every
 // workgroup shares, so they stay in cache) loaded, like the voxel fragments,
@@ -426,7 +429,7 @@ __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
 // A staged voxel r keeps its four 16-byte channel groups c at position
 // c ^ s(r), s(r) = ((r >> 1) ^ (r >> 3)) & 3: 8 (16) consecutive voxels then
 // cover all 32 (64) LDS banks.
-constexpr int kTileRows = 4;                             // e-rows per workgroup
+constexpr int kTileRows = 2;                             // e-rows per workgroup
 constexpr int kTileR = 2;                                // r-rows per workgroup
 constexpr int kConvThreads = 64 * kTileRows * kTileR;    // one wavefront per row
 constexpr int kStageRows = (kTileR + 2) * (kTileRows + 2);  // rows staged
@@ -447,17 +450,33 @@ __device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const 
     const int m = lane & 15, kq = lane >> 4;
     const int ri = wv / kTileRows, wj = wv % kTileRows;  // this wavefront's output row
     constexpr int nq = NT * 16 + 2;  // staged voxels per row
-    for (int e = tid; e < kStageRows * nq * 4; e += kConvThreads) {
+    // Every 16-byte load of a thread is issued before the first LDS store, so
+    // that the staging waits for one memory round trip rather than one per
+    // element (a loop of load-then-store waits for each load in turn).
+    constexpr int kElems = kStageRows * nq * 4, kPer = (kElems + kConvThreads - 1) / kConvThreads;
+    // Out-of-grid rows load element 0 (always valid) and are zeroed after
+    // the loads, so that no load sits behind a branch.
+    u16x8 sv[kPer];
+    bool ok[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        const int e = min(tid + u * kConvThreads, kElems - 1);
         const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
         const int ii = i0 - 1 + row / (kTileRows + 2), jj = j0 - 1 + row % (kTileRows + 2);
-        u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        if (ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1) {
-            int a = a0 - 1 + q;
-            a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
-            const int64_t p = (((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + a;
-            v = *reinterpret_cast<const u16x8 *>(x + p * C + 8 * c);
-        }
-        *reinterpret_cast<u16x8 *>(&xs[swz_off(row * kStageVox + q, c)]) = v;
+        ok[u] = ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1;
+        int a = a0 - 1 + q;
+        a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
+        const int64_t p = ok[u] ? ((((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + a) * C + 8 * c
+                                : 0;
+        sv[u] = *reinterpret_cast<const u16x8 *>(x + p);
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+        const int e = tid + u * kConvThreads;
+        const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
+        const u16x8 z = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (e < kElems)
+            *reinterpret_cast<u16x8 *>(&xs[swz_off(row * kStageVox + q, c)]) = ok[u] ? sv[u] : z;
     }
     const int i = i0 + ri, j = j0 + wj;
     // weight fragments of tap 0 (output channels m and 16 + m)
