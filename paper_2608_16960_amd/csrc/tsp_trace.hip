@@ -359,28 +359,35 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
             merge_pairs<2, NB>(v, val, lane);
             merge_pairs<4, NB>(v, val, lane);
             merge_pairs<8, NB>(v, val, lane);
-            if (v < 0) continue;
-            unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
-            bool done = false;
-            for (int p = 0; p < kOtfProbes; p++) {
-                int key = __hip_atomic_load(hkey + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (key == -1) {
-                    key = atomicCAS(hkey + h, -1, v);
-                    if (key == -1) atomicAdd(&fill, 1);
-                }
-                if (key == -1 || key == v) {
+            bool claimed = false;
+            if (v >= 0) {
+                unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
+                bool done = false;
+                for (int p = 0; p < kOtfProbes; p++) {
+                    int key = __hip_atomic_load(hkey + h, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (key == -1) {
+                        key = atomicCAS(hkey + h, -1, v);
+                        claimed = key == -1;
+                    }
+                    if (key == -1 || key == v) {
 #pragma unroll
-                    for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, val[b]);
-                    done = true;
-                    break;
+                        for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, val[b]);
+                        done = true;
+                        break;
+                    }
+                    h = (h + 1) & (HS - 1);
                 }
-                h = (h + 1) & (HS - 1);
-            }
-            if (!done) {
+                if (!done) {
 #pragma unroll
-                for (int b = 0; b < NB; b++)
-                    if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, val[b]);
+                    for (int b = 0; b < NB; b++)
+                        if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, val[b]);
+                }
             }
+            // one add to the fill count per wavefront, not one per claim on a
+            // single LDS word (every lane is active here)
+            const uint64_t cl = __ballot(claimed);
+            if (lane == 0 && cl) atomicAdd(&fill, (int)__popcll(cl));
         }
         __syncthreads();  // every insertion of this round has landed
         const int f = fill;

@@ -3,6 +3,7 @@
     python -m paper_2608_16960_amd.profiling FETCH_DIR WRITE_DIR BYTES_JSON OUT_TXT
     python -m paper_2608_16960_amd.profiling valu PMC_DIR STATS_DIR OUT_TXT
     python -m paper_2608_16960_amd.profiling occupancy PMC_DIR OUT_TXT KERNEL...
+    python -m paper_2608_16960_amd.profiling stats STATS_DIR OUT_MD TITLE COMMAND [NOTE...]
 
 FETCH_DIR / WRITE_DIR hold the counter_collection CSV of a `rocprofv3 --pmc
 FETCH_SIZE` and a `--pmc WRITE_SIZE` run of `bench.py --calib-copy`; each
@@ -208,7 +209,31 @@ def read_occupancy(path, kernel):
     return None
 
 
+def main_stats(argv):
+    """stats STATS_DIR OUT_MD TITLE COMMAND [NOTE...]: the kernel_stats.csv of a
+    --kernel-trace --stats run as a markdown table (kernels by total time),
+    with the command that made it and free-form notes."""
+    stats_dir, out_md, title, command, *notes = argv
+    path = glob.glob(os.path.join(stats_dir, "*kernel_stats.csv"))[0]
+    rows = list(csv.DictReader(open(path)))
+    with open(out_md, "w") as f:
+        f.write(f"# {title}\n\nCommand (from the repository root, on one MI355X):\n\n```\n"
+                f"{command}\n```\n\n")
+        for n in notes:
+            f.write(n + "\n")
+        f.write("\n| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
+                "|---|---|---|---|---|---|\n")
+        for r in rows:
+            name = re.sub(r"\(.*$", "", r["Name"]).replace("(anonymous namespace)::", "")
+            name = re.sub(r"^(void )?(tsp::)?", "", name)
+            f.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                    f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                    f"{float(r['Percentage']):.2f}% |\n")
+
+
 def main(argv):
+    if argv and argv[0] == "stats":
+        return main_stats(argv[1:])
     if argv and argv[0] == "valu":
         return main_valu(argv[1:])
     if argv and argv[0] == "occupancy":
