@@ -223,12 +223,20 @@ def main_stats(argv):
             f.write(n + "\n")
         f.write("\n| kernel | calls | average (us) | min (us) | max (us) | share of GPU time |\n"
                 "|---|---|---|---|---|---|\n")
+        torch_calls, torch_share = 0, 0.0
         for r in rows:
-            name = re.sub(r"\(.*$", "", r["Name"]).replace("(anonymous namespace)::", "")
-            name = re.sub(r"^(void )?(tsp::)?", "", name)
+            name = r["Name"].replace("(anonymous namespace)::", "")
+            if re.match(r"^(void )?at::", name):  # PyTorch's own kernels: one line for all
+                torch_calls += int(r["Calls"])
+                torch_share += float(r["Percentage"])
+                continue
+            name = re.sub(r"^(void )?(tsp::)?", "", re.sub(r"\(.*$", "", name))
             f.write(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                     f"{float(r['Percentage']):.2f}% |\n")
+        if torch_calls:
+            f.write(f"| PyTorch's own kernels (all kinds) | {torch_calls} | | | | "
+                    f"{torch_share:.2f}% |\n")
 
 
 def main(argv):
@@ -242,8 +250,11 @@ def main(argv):
     s = summarise(fetch_dir, write_dir)
     algo = {}
     if os.path.exists(bench_json):
-        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
-        algo = {v["kernel"]: v["bytes"] for v in b["kernels"].values()}
+        for line in reversed(open(bench_json).read().strip().splitlines()):
+            if line.startswith("{") and '"kernels"' in line:
+                b = json.loads(line)
+                algo = {v["kernel"]: v["bytes"] for v in b["kernels"].values()}
+                break
     with open(out_txt, "a") as f:
         f.write("\n# machine-readable: traffic <kernel> <bytes per dispatch> <source sha1>\n")
         for k, v in s.items():
