@@ -18,6 +18,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -562,56 +563,73 @@ __global__ __launch_bounds__(kConvThreads) void k_conv_lds(const uint16_t *__res
 
 constexpr int kMaxD2 = 128;  // widest azimuth row of the MFMA layers
 
-// Weight gradient of a 32 -> 32 layer, tiled.  A tile is two e-rows (j0,
-// j0 + 1) of one (n, i); a workgroup takes tiles blockIdx.x, + gridDim.x, ...
-// and stages per tile, transposed to [channel][azimuth], the two rows of dz
-// and the 3 x 4 neighbour rows of x they meet (rows outside the grid as
-// zeros).  A staged x row keeps azimuth a at position a + 8, with a - 1 of
-// a = 0 at 7 and a + 1 of a = D2 - 1 at D2 + 8, so that the operand of shift
-// 0 is one aligned 16-byte read and those of shifts -1 and +1 follow from it
-// and two 4-byte neighbours by funnel shifts.  Staging stores pack two
-// azimuths of one channel into 4 bytes; channel rows have an odd number of
-// 16-byte units, so the 16 rows an MFMA reads fall in different banks.
-// Wavefront w owns output channels 16 (w >> 1) .. +15 and input channels
-// 16 (w & 1) .. +15 of all 27 taps; its sums stay in registers until the
-// workgroup's last tile, then go out as its partial sums.
-constexpr int kWRows = 2;                  // e-rows per tile
-constexpr int kWStage = 3 * (kWRows + 2);  // staged x rows per tile
+// Weight gradient of a 32 -> 32 layer.  A work item is a column of two
+// e-rows (j0, j0 + 1) of one object, walked along r over a chunk of
+// `ilen` r-rows; a workgroup takes items blockIdx.x, + gridDim.x, ...  The
+// x rows an output row meets are the 3 x 4 neighbour rows (r-rows i - 1 ..
+// i + 1, e-rows j0 - 1 .. j0 + 2); they sit in a ring of three r-slices of
+// four e-rows in LDS, so a step along r brings in one new slice (4 rows) and
+// the two dz rows; the first step of an item stages three slices.  The next
+// step's slice and dz rows are loaded into registers while this step's
+// products run, and stored to LDS after them.  Rows are staged transposed
+// to [channel][azimuth] (rows outside the grid as zeros).  A staged x row
+// keeps azimuth a at position a + 8, with a - 1 of a = 0 at 7 and a + 1 of
+// a = D2 - 1 at D2 + 8, so that the operand of shift 0 is one aligned
+// 16-byte read and those of shifts -1 and +1 follow from it and two 4-byte
+// neighbours by funnel shifts.  Staging stores pack two azimuths of one
+// channel into 4 bytes; channel rows have an odd number of 16-byte units,
+// so the 16 rows an MFMA reads fall in different banks.  Wavefront w owns
+// output channels 16 (w >> 1) .. +15 and input channels 16 (w & 1) .. +15 of
+// all 27 taps; its sums stay in registers until the workgroup's last item,
+// then go out as its partial sums.
+constexpr int kWRows = 2;                  // e-rows per column
+constexpr int kWStage = 3 * (kWRows + 2);  // x rows in the ring: 3 slices of 4
 
 __device__ __forceinline__ uint32_t pack_bf16x2(uint16_t lo, uint16_t hi) {
     return (uint32_t)lo | ((uint32_t)hi << 16);
 }
 
-__global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
+// ring slot of r-row ii (ii >= -1)
+__device__ __forceinline__ int ring_of(int ii) { return (ii + 3) % 3; }
+
+template <int D2>
+__global__ __launch_bounds__(256, D2 <= 64 ? 2 : 1) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ dz, Dims d,
-                                                          float *__restrict__ part,
+                                                          int ilen, float *__restrict__ part,
                                                           float *__restrict__ bpart) {
     extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
-    const int D2 = d.D2;
-    const int sx = D2 + 24, sz = D2 + 8;  // channel-row strides (bf16 elements)
-    uint16_t *xT = lds;                   // [kWStage][C][sx]
+    constexpr int sx = D2 + 24, sz = D2 + 8;  // channel-row strides (bf16 elements)
+    // staging elements: an x element is two azimuths (2 pi - 2, 2 pi - 1 mod D2,
+    // at positions 6 + 2 pi) of 8 channels of one row; a dz element two
+    // azimuths (2 pi, 2 pi + 1) of 8 channels
+    constexpr int npx = D2 / 2 + 2, npz = D2 / 2;
+    constexpr int kSlice = (kWRows + 2) * 4 * npx, kZ = kWRows * 4 * npz;
+    constexpr int KX = (kSlice + 255) / 256, KZ = (kZ + 255) / 256;
+    constexpr int nkb = D2 / 32;
+    uint16_t *xT = lds;                     // [kWStage][C][sx]: row 4 ring_of(ii) + (jj - j0 + 1)
     uint16_t *zT = lds + kWStage * C * sx;  // [kWRows][C][sz]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int ot = wv >> 1, ct = wv & 1;  // output / input channel tiles
     const int njb = (d.D1 + kWRows - 1) / kWRows;
-    const int64_t ntiles = (int64_t)d.N * d.D0 * njb;
-    const int nkb = D2 / 32;
+    const int nch = (d.D0 + ilen - 1) / ilen;
+    const int64_t nitems = (int64_t)d.N * njb * nch;
     f32x4 acc[27];
 #pragma unroll
     for (int t = 0; t < 27; t++) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
     float bsum = 0.0f;  // bias gradient: wavefronts of input tile 0 add up their dz operands
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int j0 = (int)(tile % njb) * kWRows;
-        const int i = (int)((tile / njb) % d.D0), n = (int)(tile / njb / d.D0);
-        __syncthreads();  // the previous tile's reads are done
-        // x rows (i + s / 4 - 1, j0 - 1 + s % 4); pairs of azimuths at positions
-        // 6 + 2 pi, pi = 0 .. D2 / 2 + 1 (azimuths 2 pi - 2, 2 pi - 1 mod D2)
-        const int npx = D2 / 2 + 2;
-        for (int e = tid; e < kWStage * 4 * npx; e += 256) {
-            const int pi = e % npx, c8 = ((e / npx) & 3) * 8, s = e / npx / 4;
-            const int ii = i + s / (kWRows + 2) - 1, jj = j0 - 1 + s % (kWRows + 2);
-            u16x8 v0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, v1 = v0;
+    const u16x8 zero8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const int ch = (int)(item % nch);
+        const int64_t col = item / nch;
+        const int j0 = (int)(col % njb) * kWRows, n = (int)(col / njb);
+        const int i0 = ch * ilen, i1 = min(d.D0, i0 + ilen);
+        // element e of the x slice of r-row ii, and its LDS place
+        auto load_x = [&](int ii, int e, u16x8 &v0, u16x8 &v1) {
+            const int pi = e % npx, c8 = ((e / npx) & 3) * 8, sl = e / npx / 4;
+            const int jj = j0 - 1 + sl;
+            v0 = zero8;
+            v1 = zero8;
             if (ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1) {
                 int a = 2 * pi - 2;
                 a = a < 0 ? a + D2 : (a >= D2 ? a - D2 : a);
@@ -620,56 +638,123 @@ __global__ __launch_bounds__(256) void k_conv_wgrad_tiled(const uint16_t *__rest
                 v0 = *reinterpret_cast<const u16x8 *>(x + (rb + a) * C + c8);
                 v1 = *reinterpret_cast<const u16x8 *>(x + (rb + a1) * C + c8);
             }
-            uint32_t *dst = reinterpret_cast<uint32_t *>(xT + (s * C + c8) * sx + 6 + 2 * pi);
+        };
+        auto store_x = [&](int ii, int e, const u16x8 &v0, const u16x8 &v1) {
+            const int pi = e % npx, c8 = ((e / npx) & 3) * 8, sl = e / npx / 4;
+            const int row = ring_of(ii) * (kWRows + 2) + sl;
+            uint32_t *dst = reinterpret_cast<uint32_t *>(xT + (row * C + c8) * sx + 6 + 2 * pi);
 #pragma unroll
             for (int q = 0; q < 8; q++) dst[q * (sx / 2)] = pack_bf16x2(v0[q], v1[q]);
-        }
-        // dz rows j0, j0 + 1 at positions 0 .. D2 - 1
-        const int npz = D2 / 2;
-        for (int e = tid; e < kWRows * 4 * npz; e += 256) {
+        };
+        // element e of the dz rows (ii, j0), (ii, j0 + 1)
+        auto load_z = [&](int ii, int e, u16x8 &v0, u16x8 &v1) {
             const int pi = e % npz, c8 = ((e / npz) & 3) * 8, r = e / npz / 4;
-            u16x8 v0 = u16x8{0, 0, 0, 0, 0, 0, 0, 0}, v1 = v0;
+            v0 = zero8;
+            v1 = zero8;
             if (j0 + r < d.D1) {
-                const int64_t rb = (((int64_t)n * d.D0 + i) * d.D1 + j0 + r) * D2;
+                const int64_t rb = (((int64_t)n * d.D0 + ii) * d.D1 + j0 + r) * D2;
                 v0 = *reinterpret_cast<const u16x8 *>(dz + (rb + 2 * pi) * C + c8);
                 v1 = *reinterpret_cast<const u16x8 *>(dz + (rb + 2 * pi + 1) * C + c8);
             }
+        };
+        auto store_z = [&](int e, const u16x8 &v0, const u16x8 &v1) {
+            const int pi = e % npz, c8 = ((e / npz) & 3) * 8, r = e / npz / 4;
             uint32_t *dst = reinterpret_cast<uint32_t *>(zT + (r * C + c8) * sz + 2 * pi);
 #pragma unroll
             for (int q = 0; q < 8; q++) dst[q * (sz / 2)] = pack_bf16x2(v0[q], v1[q]);
+        };
+        __syncthreads();  // the previous item's reads are done
+        // first step: slices i0 - 1 .. i0 + 1 and dz of r-row i0
+        for (int e = tid; e < 3 * kSlice; e += 256) {
+            u16x8 v0, v1;
+            load_x(i0 - 1 + e / kSlice, e % kSlice, v0, v1);
+            store_x(i0 - 1 + e / kSlice, e % kSlice, v0, v1);
         }
-        __syncthreads();
-        for (int r = 0; r < kWRows; r++) {
-            if (j0 + r >= d.D1) break;  // uniform over the workgroup; zeros otherwise
+        for (int e = tid; e < kZ; e += 256) {
+            u16x8 v0, v1;
+            load_z(i0, e, v0, v1);
+            store_z(e, v0, v1);
+        }
+        u16x8 px0[KX], px1[KX], pz0[KZ], pz1[KZ];  // the next step's rows in flight
+        for (int i = i0; i < i1; i++) {
+            if (i > i0) {
+                __syncthreads();  // the previous step's reads are done
+#pragma unroll
+                for (int k = 0; k < KX; k++)
+                    if (tid + 256 * k < kSlice) store_x(i + 1, tid + 256 * k, px0[k], px1[k]);
+#pragma unroll
+                for (int k = 0; k < KZ; k++)
+                    if (tid + 256 * k < kZ) store_z(tid + 256 * k, pz0[k], pz1[k]);
+            }
+            __syncthreads();
+            if (i + 1 < i1) {  // slice i + 2 and dz of r-row i + 1, for the next step
+#pragma unroll
+                for (int k = 0; k < KX; k++)
+                    if (tid + 256 * k < kSlice) load_x(i + 2, tid + 256 * k, px0[k], px1[k]);
+#pragma unroll
+                for (int k = 0; k < KZ; k++)
+                    if (tid + 256 * k < kZ) load_z(i + 1, tid + 256 * k, pz0[k], pz1[k]);
+            }
+            int slot[3];  // ring slots of r-rows i - 1, i, i + 1
+#pragma unroll
+            for (int dr = 0; dr < 3; dr++) slot[dr] = ring_of(i - 1 + dr);
+#pragma unroll
             for (int kb = 0; kb < nkb; kb++) {
                 const int a = 32 * kb + 8 * kq;
-                const u16x8 Au = *reinterpret_cast<const u16x8 *>(zT + (r * C + 16 * ot + m) * sz + a);
-                const bf16x8 A = __builtin_bit_cast(bf16x8, Au);
+                // dz operands of both e-rows (a row beyond the grid was staged
+                // as zeros and adds nothing)
+                const u16x8 A0u = *reinterpret_cast<const u16x8 *>(zT + (16 * ot + m) * sz + a);
+                const u16x8 A1u = *reinterpret_cast<const u16x8 *>(zT + (C + 16 * ot + m) * sz + a);
+                const bf16x8 A0 = __builtin_bit_cast(bf16x8, A0u);
+                const bf16x8 A1 = __builtin_bit_cast(bf16x8, A1u);
                 if (ct == 0) {  // uniform per wavefront
 #pragma unroll
-                    for (int e = 0; e < 8; e++) bsum += bf2f(Au[e]);
+                    for (int e = 0; e < 8; e++) bsum += bf2f(A0u[e]) + bf2f(A1u[e]);
                 }
+                // the 12 staged x rows (3 r-slices x 4 e-rows); x row sl of a
+                // slice meets dz row 0 at e-offset sl and dz row 1 at sl - 1,
+                // so each row is read once for both.  The next row's reads are
+                // issued before this row's products.
+                typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+                const uint16_t *xb = xT + (16 * ct + m) * sx + a + 8;
+                auto load_row = [&](int q, u32x4 &c, uint32_t &lo, uint32_t &hi) {
+                    const uint16_t *bp = xb + (slot[q >> 2] * (kWRows + 2) + (q & 3)) * C * sx;
+                    c = *reinterpret_cast<const u32x4 *>(bp);
+                    lo = *reinterpret_cast<const uint32_t *>(bp - 2);
+                    hi = *reinterpret_cast<const uint32_t *>(bp + 8);
+                };
+                u32x4 c;
+                uint32_t lo, hi;
+                load_row(0, c, lo, hi);
 #pragma unroll
-                for (int dd = 0; dd < 9; dd++) {  // (dr, de) offsets + 1
-                    const int row = (dd / 3) * (kWRows + 2) + r + dd % 3;
-                    const uint16_t *bp = xT + (row * C + 16 * ct + m) * sx + a + 8;
-                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                    const u32x4 c = *reinterpret_cast<const u32x4 *>(bp);
-                    const uint32_t lo = *reinterpret_cast<const uint32_t *>(bp - 2);
-                    const uint32_t hi = *reinterpret_cast<const uint32_t *>(bp + 8);
+                for (int q = 0; q < 3 * (kWRows + 2); q++) {
+                    u32x4 cn = c;
+                    uint32_t lon = lo, hin = hi;
+                    if (q + 1 < 3 * (kWRows + 2)) load_row(q + 1, cn, lon, hin);
                     const uint32_t f0 = __builtin_amdgcn_alignbit(c[0], lo, 16);
                     const uint32_t f1 = __builtin_amdgcn_alignbit(c[1], c[0], 16);
                     const uint32_t f2 = __builtin_amdgcn_alignbit(c[2], c[1], 16);
                     const uint32_t f3 = __builtin_amdgcn_alignbit(c[3], c[2], 16);
                     const uint32_t f4 = __builtin_amdgcn_alignbit(hi, c[3], 16);
-                    const u32x4 bm = u32x4{f0, f1, f2, f3}, bpl = u32x4{f1, f2, f3, f4};
-                    const int t0 = dd * 3;
-                    acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        A, __builtin_bit_cast(bf16x8, bm), acc[t0], 0, 0, 0);
-                    acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        A, __builtin_bit_cast(bf16x8, c), acc[t0 + 1], 0, 0, 0);
-                    acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        A, __builtin_bit_cast(bf16x8, bpl), acc[t0 + 2], 0, 0, 0);
+                    const bf16x8 bm = __builtin_bit_cast(bf16x8, u32x4{f0, f1, f2, f3});
+                    const bf16x8 b0 = __builtin_bit_cast(bf16x8, c);
+                    const bf16x8 bpl = __builtin_bit_cast(bf16x8, u32x4{f1, f2, f3, f4});
+                    const int dr = q / (kWRows + 2), sl = q % (kWRows + 2);
+                    if (sl <= 2) {  // dz row 0, e-offset sl - 1
+                        const int t0 = (dr * 3 + sl) * 3;
+                        acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bm, acc[t0], 0, 0, 0);
+                        acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, b0, acc[t0 + 1], 0, 0, 0);
+                        acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bpl, acc[t0 + 2], 0, 0, 0);
+                    }
+                    if (sl >= 1) {  // dz row 1, e-offset sl - 2
+                        const int t0 = (dr * 3 + sl - 1) * 3;
+                        acc[t0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bm, acc[t0], 0, 0, 0);
+                        acc[t0 + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, b0, acc[t0 + 1], 0, 0, 0);
+                        acc[t0 + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bpl, acc[t0 + 2], 0, 0, 0);
+                    }
+                    c = cn;
+                    lo = lon;
+                    hi = hin;
                 }
             }
         }
@@ -962,28 +1047,38 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
     if (s != TSPNN_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     Dims d{N, D0, D1, D2};
-    // tiles of two e-rows; never more workgroups than the workspace holds
-    // partial sums for (wgrad_blocks of the row count)
-    const int64_t tiles = (int64_t)N * D0 * ((D1 + kWRows - 1) / kWRows);
-    const int nb = wgrad_blocks(tiles);
+    // columns of two e-rows, cut along r into chunks so that there are about
+    // 512 work items; never more workgroups than the workspace holds partial
+    // sums for (wgrad_blocks of the row count)
+    const int64_t cols = (int64_t)N * ((D1 + kWRows - 1) / kWRows);
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(D0, (512 + cols - 1) / cols));
+    const int ilen = (int)((D0 + nch - 1) / nch);
+    const int64_t items = cols * ((D0 + ilen - 1) / ilen);
+    const int nb = wgrad_blocks(items);
     float *part = (float *)work;
     const size_t lds = wgrad_lds_bytes(D2);
+    using wgrad_fn = void (*)(const uint16_t *, const uint16_t *, Dims, int, float *, float *);
+    const wgrad_fn fns[4] = {k_conv_wgrad_tiled<32>, k_conv_wgrad_tiled<64>,
+                             k_conv_wgrad_tiled<96>, k_conv_wgrad_tiled<128>};
     // dynamic LDS above the default needs opting in, once per device
     static bool lds_enabled[64] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight");
     if (dev < 0 || dev >= 64 || !lds_enabled[dev]) {
-        e = hipFuncSetAttribute((const void *)k_conv_wgrad_tiled,
-                                hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)wgrad_lds_bytes(kMaxD2));
-        if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight (LDS size)");
+        for (int k = 0; k < 4; k++) {
+            e = hipFuncSetAttribute((const void *)fns[k],
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)wgrad_lds_bytes(32 * (k + 1)));
+            if (e != hipSuccess) return hipret(e, "tspnn_conv_bwd_weight (LDS size)");
+        }
         if (dev >= 0 && dev < 64) lds_enabled[dev] = true;
     }
     // workspace: weight partials, their reduction's group sums, bias
     // partials, theirs (tspnn_conv_workspace sizes it)
     float *bpart = part + (int64_t)(nb + kRedGroups) * 27 * C * C;
-    hipLaunchKernelGGL(k_conv_wgrad_tiled, dim3(nb), dim3(256), lds, st, x, dz, d, part, bpart);
+    hipLaunchKernelGGL(fns[D2 / 32 - 1], dim3(nb), dim3(256), lds, st, x, dz, d, ilen, part,
+                       bpart);
     reduce_parts(part, nb, 27 * C * C, 27 * C * C, dw, part + (int64_t)nb * 27 * C * C, st);
     if (db) reduce_parts(bpart, nb, C, C, db, bpart + (int64_t)nb * C, st);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_weight");

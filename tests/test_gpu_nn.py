@@ -132,11 +132,21 @@ def test_conv_hidden_weight_gradient_mfma(nn, shape):
     assert torch.equal(dw, dw2) and torch.equal(db, db2)
 
 
-def test_conv_hidden_weight_gradient_many_tiles(nn):
-    """600 tiles of two e-rows against at most 512 workgroups: workgroups
-    take a second tile (re-staging after a barrier), as at the training size
-    (8192 tiles at batch 8 of 64x32x64)."""
-    N, D0, D1, D2 = 2, 20, 30, 32
+# (N, D0, D1, D2): the weight gradient walks columns of two e-rows along r in
+# chunks of ilen r-rows (about 512 work items); these shapes give
+#   ilen 2, 300 items;
+#   ilen 7 with a last chunk of one r-row;
+#   ilen 4 with an odd e-row count (a last column of one e-row);
+#   ilen 3, 524 columns against 512 workgroups (a second item after a barrier);
+#   the 128-wide template at ilen 2.
+WALKS = [(2, 20, 30, 32), (2, 50, 64, 32), (2, 40, 41, 64), (4, 3, 261, 32), (2, 30, 20, 128)]
+
+
+@pytest.mark.parametrize("shape", WALKS)
+def test_conv_hidden_weight_gradient_walks(nn, shape):
+    """Multi-step walks along r: the next step's rows are prefetched into
+    registers while a step computes, into a ring of three r-slices."""
+    N, D0, D1, D2 = shape
     g = torch.Generator().manual_seed(6)
     x = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
     dz = _bf(torch.randn((N, D0, D1, D2, 32), generator=g))
