@@ -584,6 +584,8 @@ constexpr int kMaxD2 = 128;  // widest azimuth row of the MFMA layers
 // then go out as its partial sums.
 constexpr int kWRows = 2;                  // e-rows per column
 constexpr int kWStage = 3 * (kWRows + 2);  // x rows in the ring: 3 slices of 4
+constexpr int kWPart = 27 * C * C + C;     // a workgroup's partial sums: weights, then bias
+constexpr int kWGroups = 32;               // first-stage groups of their reduction
 
 __device__ __forceinline__ uint32_t pack_bf16x2(uint16_t lo, uint16_t hi) {
     return (uint32_t)lo | ((uint32_t)hi << 16);
@@ -595,8 +597,7 @@ __device__ __forceinline__ int ring_of(int ii) { return (ii + 3) % 3; }
 template <int D2>
 __global__ __launch_bounds__(256, D2 <= 64 ? 2 : 1) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
                                                           const uint16_t *__restrict__ dz, Dims d,
-                                                          int ilen, float *__restrict__ part,
-                                                          float *__restrict__ bpart) {
+                                                          int ilen, float *__restrict__ part) {
     extern __shared__ __attribute__((aligned(16))) uint16_t lds[];
     constexpr int sx = D2 + 24, sz = D2 + 8;  // channel-row strides (bf16 elements)
     // staging elements: an x element is two azimuths (2 pi - 2, 2 pi - 1 mod D2,
@@ -759,8 +760,8 @@ __global__ __launch_bounds__(256, D2 <= 64 ? 2 : 1) void k_conv_wgrad_tiled(cons
             }
         }
     }
-    // partial sums: part[blk][tap][o][i], bpart[blk][o]
-    float *pb = part + (int64_t)blockIdx.x * 27 * C * C;
+    // partial sums: row blk of part holds [tap][o][i], then the bias [o]
+    float *pb = part + (int64_t)blockIdx.x * kWPart;
 #pragma unroll
     for (int t = 0; t < 27; t++)
 #pragma unroll
@@ -771,7 +772,62 @@ __global__ __launch_bounds__(256, D2 <= 64 ? 2 : 1) void k_conv_wgrad_tiled(cons
     if (ct == 0) {  // lanes m, m + 16, m + 32, m + 48 hold channel 16 ot + m
         bsum += __shfl_xor(bsum, 16, 64);
         bsum += __shfl_xor(bsum, 32, 64);
-        if (kq == 0) bpart[(int64_t)blockIdx.x * C + 16 * ot + m] = bsum;
+        if (kq == 0) pb[27 * C * C + 16 * ot + m] = bsum;
+    }
+}
+
+// The weight-gradient partial rows summed in a fixed order, in two stages.
+// Stage 1: tmp[g] = the sum of rows g * per .. min(nb, (g + 1) * per) - 1, in
+// increasing order, per 16-byte column.
+__global__ __launch_bounds__(256) void k_wgrad_groups(const f32x4 *__restrict__ part, int nb,
+                                                      int per, f32x4 *__restrict__ tmp) {
+    constexpr int n4 = kWPart / 4;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n4) return;
+    const int b1 = min(nb, (int)(blockIdx.y + 1) * per);
+    int b = blockIdx.y * per;
+    f32x4 s = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (; b + 8 <= b1; b += 8) {  // eight loads in flight, added in order
+        f32x4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) v[k] = part[(int64_t)(b + k) * n4 + j];
+#pragma unroll
+        for (int k = 0; k < 8; k++) s += v[k];
+    }
+    for (; b < b1; b++) s += part[(int64_t)b * n4 + j];
+    tmp[(int64_t)blockIdx.y * n4 + j] = s;
+}
+
+// Stage 2: the kWGroups group sums of a column, in order: four threads take
+// eight groups each, then thread 0 of the four adds their sums in order.
+// Columns below 27 C C go to dw, the rest to db (skipped when db is null).
+__global__ __launch_bounds__(256) void k_wgrad_final(const f32x4 *__restrict__ tmp,
+                                                     float *__restrict__ dw,
+                                                     float *__restrict__ db) {
+    constexpr int n4 = kWPart / 4, per = kWGroups / 4;
+    const int j = blockIdx.x * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+    f32x4 s = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    if (j < n4) {
+        f32x4 v[per];
+#pragma unroll
+        for (int k = 0; k < per; k++) v[k] = tmp[(int64_t)(q * per + k) * n4 + j];
+#pragma unroll
+        for (int k = 0; k < per; k++) s += v[k];
+    }
+    f32x4 t[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) t[k][e] = __shfl(s[e], (threadIdx.x & ~3) + k, 64);
+    if (j >= n4 || q != 0) return;
+    const f32x4 r = ((t[0] + t[1]) + t[2]) + t[3];
+    const int e0 = 4 * j;  // dw and db need only 4-byte alignment
+    if (e0 < 27 * C * C) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) dw[e0 + e] = r[e];
+    } else if (db) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) db[e0 - 27 * C * C + e] = r[e];
     }
 }
 
@@ -990,10 +1046,9 @@ tspnn_status tspnn_from_bf16(const uint16_t *x, float *y, int64_t n, void *strea
 size_t tspnn_conv_workspace(int32_t N, int32_t D0, int32_t D1, int32_t D2) {
     const int64_t rows = (int64_t)N * D0 * D1;
     const int64_t wb = wgrad_blocks(rows);
-    // 32 -> 32 layers: weight partials and their group sums, then the bias
-    // partials and theirs; edge layers: partials and group sums
-    const size_t a = sizeof(float) * ((size_t)(wb + kRedGroups) * 27 * C * C +
-                                      (size_t)(wb + kRedGroups) * C);
+    // 32 -> 32 layers: partial rows (weights and bias) and their group sums;
+    // edge layers: partials and group sums
+    const size_t a = sizeof(float) * (size_t)(wb + kWGroups) * kWPart;
     const int64_t rblk = (rows + kRowsPerBlk - 1) / kRowsPerBlk;
     const size_t b = sizeof(float) * ((size_t)rblk + kRedGroups) * (27 * C + C);
     return (a > b ? a : b) + 256;
@@ -1043,6 +1098,8 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
                                    void *stream) {
     g_err.clear();
     if (!x || !dz || !dw || !work) return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_weight: NULL");
+    if ((uintptr_t)work % 16 != 0)
+        return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_weight: work must be 16-byte aligned");
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     hipStream_t st = (hipStream_t)stream;
@@ -1057,7 +1114,7 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
     const int nb = wgrad_blocks(items);
     float *part = (float *)work;
     const size_t lds = wgrad_lds_bytes(D2);
-    using wgrad_fn = void (*)(const uint16_t *, const uint16_t *, Dims, int, float *, float *);
+    using wgrad_fn = void (*)(const uint16_t *, const uint16_t *, Dims, int, float *);
     const wgrad_fn fns[4] = {k_conv_wgrad_tiled<32>, k_conv_wgrad_tiled<64>,
                              k_conv_wgrad_tiled<96>, k_conv_wgrad_tiled<128>};
     // dynamic LDS above the default needs opting in, once per device
@@ -1074,13 +1131,15 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
         }
         if (dev >= 0 && dev < 64) lds_enabled[dev] = true;
     }
-    // workspace: weight partials, their reduction's group sums, bias
-    // partials, theirs (tspnn_conv_workspace sizes it)
-    float *bpart = part + (int64_t)(nb + kRedGroups) * 27 * C * C;
-    hipLaunchKernelGGL(fns[D2 / 32 - 1], dim3(nb), dim3(256), lds, st, x, dz, d, ilen, part,
-                       bpart);
-    reduce_parts(part, nb, 27 * C * C, 27 * C * C, dw, part + (int64_t)nb * 27 * C * C, st);
-    if (db) reduce_parts(bpart, nb, C, C, db, bpart + (int64_t)nb * C, st);
+    // workspace: nb partial rows, then kWGroups group sums (tspnn_conv_workspace
+    // sizes it)
+    hipLaunchKernelGGL(fns[D2 / 32 - 1], dim3(nb), dim3(256), lds, st, x, dz, d, ilen, part);
+    float *tmp = part + (int64_t)nb * kWPart;
+    const int per = (nb + kWGroups - 1) / kWGroups;
+    hipLaunchKernelGGL(k_wgrad_groups, dim3(nblk(kWPart / 4, 256), kWGroups), dim3(256), 0, st,
+                       (const f32x4 *)part, nb, per, (f32x4 *)tmp);
+    hipLaunchKernelGGL(k_wgrad_final, dim3(nblk(kWPart / 4, 64)), dim3(256), 0, st,
+                       (const f32x4 *)tmp, dw, db);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_weight");
 }
 
