@@ -116,7 +116,10 @@ tspnn_status tspnn_conv_in_fwd(const float *x, int32_t N, int32_t D0, int32_t D1
                                const float *w, const float *b, uint16_t *y, void *stream);
 
 /* 32 -> 32 layer on MFMA: y = relu(conv(x) + b), x, y bfloat16 [..][32],
- * w bfloat16 [27][32][32] (out, in), b float32 [32].  D2 % 32 == 0, D2 <= 128. */
+ * w bfloat16 [27][32][32] (out, in), b float32 [32].  D2 % 32 == 0, D2 <= 128.
+ * The bfloat16 arrays of the 32 -> 32 layers (here and in the two backward
+ * calls below) are read and written in 8- and 16-byte pieces and must be
+ * 16-byte aligned (TSPNN_E_INVALID otherwise). */
 tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1, int32_t D2,
                             const uint16_t *w, const float *b, uint16_t *y, void *stream);
 
@@ -140,8 +143,8 @@ tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, 
 /* Weight / bias gradients of a 32 -> 32 layer on MFMA:
  * dw[t][o][i] = sum_p dz[p][o] x[p + off(t)][i], db[o] = sum_p dz[p][o].
  * dw float32 [27][32][32]; db float32 [32] (may be NULL).  D2 % 32 == 0, D2 <= 128.
- * work: tspnn_conv_workspace(N, D0, D1, D2) bytes of device memory, 16-byte
- * aligned (TSPNN_E_INVALID otherwise).  The partial sums are added up in a
+ * work: tspnn_conv_workspace(N, D0, D1, D2) bytes of device memory; work, x
+ * and dz 16-byte aligned (TSPNN_E_INVALID otherwise).  The partial sums are added up in a
  * fixed order, so equal inputs give the same bits. */
 tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_t N, int32_t D0,
                                    int32_t D1, int32_t D2, float *dw, float *db, void *work,

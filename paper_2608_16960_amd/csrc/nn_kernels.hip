@@ -409,156 +409,198 @@ __global__ __launch_bounds__(256) void k_small_wgrad(const float *xin, const uin
 
 // ---------------------------------------------------------------- 32 -> 32 on MFMA
 
+// ring slot of r-row ii (ii >= -1)
+__device__ __forceinline__ int ring_of(int ii) { return (ii + 3) % 3; }
+
 __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) {
     return *reinterpret_cast<const bf16x8 *>(p);
 }
 
-// The same layer with its inputs staged in LDS.  A workgroup of four
-// wavefronts takes two r-rows (i0, i0+1) by two e-rows (j0, j0+1) of one
-// object and up to 64 azimuths a0 .. a0+63.  It stages the 4 x 4 neighbour
-// rows those outputs read (67.6 KB, so that two workgroups share a CU and one
-// stages while the other computes: 106 -> 97 us at batch 8 of 64 x 32 x 64,
-// against tiles of 2 x 4 rows at one workgroup per CU, though each input row
-// is then fetched by 4 workgroups per output row instead of 3), each with
-// one azimuth of circular halo on both sides (66 voxels of 64 bytes; rows
-// outside the grid as zeros), then wavefront w computes row
-// (i0 + w / 2, j0 + w % 2):
-// 27 taps of 8 MFMAs with no branch between them, the
-// voxel fragments read from LDS and the weight fragments (which every
-// workgroup shares, so they stay in cache) loaded, like the voxel fragments,
-// one tap ahead.
-// A staged voxel r keeps its four 16-byte channel groups c at position
-// c ^ s(r), s(r) = ((r >> 1) ^ (r >> 3)) & 3: 8 (16) consecutive voxels then
-// cover all 32 (64) LDS banks.
-constexpr int kTileRows = 2;                             // e-rows per workgroup
-constexpr int kTileR = 2;                                // r-rows per workgroup
-constexpr int kConvThreads = 64 * kTileRows * kTileR;    // one wavefront per row
-constexpr int kStageRows = (kTileR + 2) * (kTileRows + 2);  // rows staged
-constexpr int kStageVox = 66;                    // 64 azimuths + halo
+// The same layer with its inputs staged in LDS.  A work item is a column of
+// four e-rows (j0 .. j0 + 3) of one object and up to 64 azimuths a0 ..
+// a0 + 63, walked along r over a chunk of `ilen` r-rows; wavefront w computes
+// output row (i, j0 + w) at each step i.  The x rows a step reads are the
+// 3 x 6 neighbour rows (r-rows i - 1 .. i + 1, e-rows j0 - 1 .. j0 + 4), each
+// with one azimuth of circular halo on both sides (66 voxels of 64 bytes;
+// rows outside the grid as zeros).  They sit in a ring of three r-slices of
+// six rows in LDS (76 KB, two workgroups per CU), so a step brings in one new
+// slice: the next step's slice is loaded into registers while this step's
+// MFMAs run and stored after them.  An input row is fetched by 1.5 columns
+// and (ilen + 2) / ilen steps, against 4 fetches with separately staged
+// 2 x 2 tiles.  Per step a wavefront runs 27 taps of 8 MFMAs with no branch
+// between them, the voxel fragments read from LDS and the weight fragments
+// (which every workgroup shares, so they stay in cache) loaded, like the
+// voxel fragments, one tap ahead.  Voxel q of a staged row keeps its four
+// 16-byte channel groups c at position c ^ s(q), s(q) = ((q >> 1) ^ (q >> 3))
+// & 3: 8 (16) consecutive voxels then cover all 32 (64) LDS banks, and a
+// fragment's place is a per-lane offset plus a per-wavefront row base.
+constexpr int kCols = 4;                       // e-rows per column
+constexpr int kConvThreads = 64 * kCols;       // one wavefront per e-row
+constexpr int kSliceRows = kCols + 2;          // x rows of one r-slice
+constexpr int kStageVox = 66;                  // 64 azimuths + halo
+constexpr int kConvItems = 512;                // work items a launch aims at (2 per CU)
+// word 3 of a raw buffer resource: 32-bit data format, no swizzle
+constexpr int kBufferDword3 = 0x00020000;
 
-__device__ __forceinline__ int swz_off(int r, int c) {  // bf16 elements
-    return (r * 4 + (c ^ (((r >> 1) ^ (r >> 3)) & 3))) * 8;
+// place of channel group c of voxel q within a staged row (bf16 elements)
+__device__ __forceinline__ int swz_off(int q, int c) {
+    return (q * 4 + (c ^ (((q >> 1) ^ (q >> 3)) & 3))) * 8;
 }
 
 template <int EPI, int NT>
-__device__ __forceinline__ void conv_tile(const uint16_t *__restrict__ x, const Dims &d,
+__device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const Dims &d,
                                           const uint16_t *__restrict__ w,
                                           const float *__restrict__ bias,
                                           const uint16_t *__restrict__ mask,
-                                          uint16_t *__restrict__ y, uint16_t *xs, int n, int i0,
-                                          int j0, int a0) {
+                                          uint16_t *__restrict__ y, uint16_t *xs, int n, int j0,
+                                          int a0, int i0, int i1) {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int m = lane & 15, kq = lane >> 4;
-    const int ri = wv / kTileRows, wj = wv % kTileRows;  // this wavefront's output row
     constexpr int nq = NT * 16 + 2;  // staged voxels per row
-    // Every 16-byte load of a thread is issued before the first LDS store, so
-    // that the staging waits for one memory round trip rather than one per
-    // element (a loop of load-then-store waits for each load in turn).
-    constexpr int kElems = kStageRows * nq * 4, kPer = (kElems + kConvThreads - 1) / kConvThreads;
-    // Out-of-grid rows load element 0 (always valid) and are zeroed after
-    // the loads, so that no load sits behind a branch.
-    u16x8 sv[kPer];
-    bool ok[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; u++) {
-        const int e = min(tid + u * kConvThreads, kElems - 1);
-        const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
-        const int ii = i0 - 1 + row / (kTileRows + 2), jj = j0 - 1 + row % (kTileRows + 2);
-        ok[u] = ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1;
+    constexpr int kSlice = kSliceRows * nq * 4;  // 16-byte elements of one slice
+    constexpr int KP = (kSlice + kConvThreads - 1) / kConvThreads;
+    // Element e of the slice of r-row ii.  Every load of a slice is issued
+    // before its first LDS store; an out-of-grid row loads element 0 (always
+    // valid) and is zeroed at the store, so that no load sits behind a branch.
+    auto load_el = [&](int ii, int u, u16x8 &v, bool &ok) {
+        const int e = min(tid + u * kConvThreads, kSlice - 1);
+        const int c = e & 3, q = (e >> 2) % nq, sl = (e >> 2) / nq;
+        const int jj = j0 - 1 + sl;
+        ok = ii >= 0 && ii < d.D0 && jj >= 0 && jj < d.D1;
         int a = a0 - 1 + q;
         a = a < 0 ? a + d.D2 : (a >= d.D2 ? a - d.D2 : a);
-        const int64_t p = ok[u] ? ((((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + a) * C + 8 * c
-                                : 0;
-        sv[u] = *reinterpret_cast<const u16x8 *>(x + p);
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; u++) {
-        const int e = tid + u * kConvThreads;
-        const int c = e & 3, q = (e >> 2) % nq, row = (e >> 2) / nq;
-        const u16x8 z = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        if (e < kElems)
-            *reinterpret_cast<u16x8 *>(&xs[swz_off(row * kStageVox + q, c)]) = ok[u] ? sv[u] : z;
-    }
-    const int i = i0 + ri, j = j0 + wj;
-    // weight fragments of tap 0 (output channels m and 16 + m)
-    const uint16_t *wl = w + m * C + 8 * kq;
-    bf16x8 b0[2], b1[2];
-    b0[0] = ld8(wl);
-    b1[0] = ld8(wl + 16 * C);
-    __syncthreads();
-    if (i >= d.D0 || j >= d.D1) return;  // uniform per wave; no barrier follows
-    f32x4 acc[NT][2];
-#pragma unroll
-    for (int t = 0; t < NT; t++)
-#pragma unroll
-        for (int u = 0; u < 2; u++) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-    // voxel fragments of tap k (NT tiles of 16 azimuths)
-    auto load_a = [&](int k, bf16x8 *av) {
-        const int dr = k / 9, de = (k / 3) % 3, da = k % 3;  // offsets + 1
-        const int row = (ri + dr) * (kTileRows + 2) + wj + de;
-#pragma unroll
-        for (int t = 0; t < NT; t++)
-            av[t] = *reinterpret_cast<const bf16x8 *>(
-                &xs[swz_off(row * kStageVox + 16 * t + m + da, kq)]);
+        const int64_t p = ok ? ((((int64_t)n * d.D0 + ii) * d.D1 + jj) * d.D2 + a) * C + 8 * c : 0;
+        v = *reinterpret_cast<const u16x8 *>(x + p);
     };
-    bf16x8 av[2][NT];
-    load_a(0, av[0]);
-    // both operands of the next tap are loaded while this tap's MFMAs run
+    auto store_el = [&](int ii, int u, const u16x8 &v, bool ok) {
+        const int e = tid + u * kConvThreads;
+        const int c = e & 3, q = (e >> 2) % nq, sl = (e >> 2) / nq;
+        const u16x8 z = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+        if (e < kSlice)
+            *reinterpret_cast<u16x8 *>(
+                &xs[(ring_of(ii) * kSliceRows + sl) * kStageVox * C + swz_off(q, c)]) = ok ? v : z;
+    };
+    u16x8 pv[KP];
+    bool pok[KP];
+    // first step: slices i0 - 1 .. i0 + 1
+    for (int s3 = 0; s3 < 3; s3++) {
 #pragma unroll
-    for (int tap = 0; tap < 27; tap++) {
-        const int cur = tap & 1;
-        if (tap + 1 < 27) {
-            b0[cur ^ 1] = ld8(wl + (tap + 1) * C * C);
-            b1[cur ^ 1] = ld8(wl + (tap + 1) * C * C + 16 * C);
-            load_a(tap + 1, av[cur ^ 1]);
-        }
+        for (int u = 0; u < KP; u++) load_el(i0 - 1 + s3, u, pv[u], pok[u]);
 #pragma unroll
-        for (int t = 0; t < NT; t++) {
-            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cur][t], b0[cur], acc[t][0], 0, 0, 0);
-            acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[cur][t], b1[cur], acc[t][1], 0, 0, 0);
-        }
+        for (int u = 0; u < KP; u++) store_el(i0 - 1 + s3, u, pv[u], pok[u]);
     }
-    const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2;
+    const int j = j0 + wv;
+    // weight fragments (output channels m and 16 + m) through a buffer
+    // resource: one lane offset, the tap's offset in a scalar register
+    const __amdgpu_buffer_rsrc_t wr =
+        __builtin_amdgcn_make_buffer_rsrc((void *)w, (short)0, 27 * C * C * 2, kBufferDword3);
+    const int wlo = (m * C + 8 * kq) * 2;  // bytes
+    auto ldw = [&](int tap, int half) {
+        return __builtin_bit_cast(
+            bf16x8, __builtin_amdgcn_raw_buffer_load_b128(wr, wlo + half * 16 * C * 2,
+                                                          tap * C * C * 2, 0));
+    };
+    for (int i = i0; i < i1; i++) {
+        if (i > i0) {
+            __syncthreads();  // the previous step's reads are done
 #pragma unroll
-    for (int t = 0; t < NT; t++) {
+            for (int u = 0; u < KP; u++) store_el(i + 1, u, pv[u], pok[u]);
+        }
+        bf16x8 b0[2], b1[2];
+        b0[0] = ldw(0, 0);
+        b1[0] = ldw(0, 1);
+        __syncthreads();
+        if (i + 1 < i1) {  // slice i + 2, for the next step
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
-            const int o = 16 * u + m;
+            for (int u = 0; u < KP; u++) load_el(i + 2, u, pv[u], pok[u]);
+        }
+        if (j < d.D1) {  // uniform per wave
+            f32x4 acc[NT][2];
 #pragma unroll
-            for (int e = 0; e < 4; e++) {
-                const int64_t p = ob + a0 + 16 * t + 4 * kq + e;
-                float v = acc[t][u][e];
-                if (EPI == 0) {
-                    v = fmaxf(v + bias[o], 0.0f);
-                } else {
-                    v = bf2f(mask[p * C + o]) > 0.0f ? v : 0.0f;
+            for (int t = 0; t < NT; t++)
+#pragma unroll
+                for (int u = 0; u < 2; u++) acc[t][u] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            int slot[3];  // ring slots of r-rows i - 1, i, i + 1
+#pragma unroll
+            for (int dr = 0; dr < 3; dr++) slot[dr] = ring_of(i - 1 + dr);
+            // voxel fragments of tap k (NT tiles of 16 azimuths)
+            auto load_a = [&](int k, bf16x8 *av) {
+                const int dr = k / 9, de = (k / 3) % 3, da = k % 3;  // offsets + 1
+                const uint16_t *rp = xs + (slot[dr] * kSliceRows + wv + de) * kStageVox * C;
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+                    av[t] = *reinterpret_cast<const bf16x8 *>(rp + swz_off(16 * t + m + da, kq));
+            };
+            bf16x8 av[2][NT];
+            load_a(0, av[0]);
+            // both operands of the next tap are loaded while this tap's MFMAs run
+#pragma unroll
+            for (int tap = 0; tap < 27; tap++) {
+                const int cur = tap & 1;
+                if (tap + 1 < 27) {
+                    b0[cur ^ 1] = ldw(tap + 1, 0);
+                    b1[cur ^ 1] = ldw(tap + 1, 1);
+                    load_a(tap + 1, av[cur ^ 1]);
                 }
-                y[p * C + o] = f2bf(v);
+            // weights as the A operand and voxels as B: lane (m, kq) of tile
+            // (t, u) holds output channels 16 u + 4 kq .. + 3 of voxel 16 t + m,
+            // so its epilogue reads and writes 8 contiguous bytes
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b0[cur], av[cur][t], acc[t][0], 0, 0, 0);
+                    acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1[cur], av[cur][t], acc[t][1], 0, 0, 0);
+                }
+            }
+            const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2 + a0 + m;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                if (a0 + 16 * t >= d.D2) break;  // uniform
+#pragma unroll
+                for (int u = 0; u < 2; u++) {
+                    const int o = 16 * u + 4 * kq;
+                    const int64_t p = (ob + 16 * t) * C + o;
+                    typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+                    u16x4 mk;
+                    if (EPI == 1) mk = *reinterpret_cast<const u16x4 *>(mask + p);
+                    u16x4 out;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        float v = acc[t][u][e];
+                        if (EPI == 0) {
+                            v = fmaxf(v + bias[o + e], 0.0f);
+                        } else {
+                            v = bf2f(mk[e]) > 0.0f ? v : 0.0f;
+                        }
+                        out[e] = f2bf(v);
+                    }
+                    *reinterpret_cast<u16x4 *>(y + p) = out;
+                }
             }
         }
     }
 }
 
+// Work items: (object, r-chunk, column of kCols e-rows, 64-azimuth chunk),
+// the azimuth chunk fastest; one workgroup per item.
 template <int EPI>
-__global__ __launch_bounds__(kConvThreads) void k_conv_lds(const uint16_t *__restrict__ x, Dims d,
-                                                  const uint16_t *__restrict__ w,
+__global__ __launch_bounds__(kConvThreads, 2) void k_conv_lds(const uint16_t *__restrict__ x, Dims d,
+                                                  int ilen, const uint16_t *__restrict__ w,
                                                   const float *__restrict__ bias,
                                                   const uint16_t *__restrict__ mask,
                                                   uint16_t *__restrict__ y) {
-    __shared__ __attribute__((aligned(16))) uint16_t xs[kStageRows * kStageVox * C];
-    const int nchunk = (d.D2 + 63) / 64, njb = (d.D1 + kTileRows - 1) / kTileRows;
-    const int nib = (d.D0 + kTileR - 1) / kTileR;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[3 * kSliceRows * kStageVox * C];
+    const int nchunk = (d.D2 + 63) / 64, ncol = (d.D1 + kCols - 1) / kCols;
+    const int nrch = (d.D0 + ilen - 1) / ilen;
     int64_t b = blockIdx.x;
     const int ac = (int)(b % nchunk);
     b /= nchunk;
-    const int jb = (int)(b % njb);
-    b /= njb;
-    const int ib = (int)(b % nib), n = (int)(b / nib);
-    const int a0 = ac * 64, j0 = jb * kTileRows, i0 = ib * kTileR;
-    if (d.D2 - a0 >= 64)  // uniform over the workgroup
-        conv_tile<EPI, 4>(x, d, w, bias, mask, y, xs, n, i0, j0, a0);
-    else  // D2 % 32 == 0: the last chunk holds 32 azimuths
-        conv_tile<EPI, 2>(x, d, w, bias, mask, y, xs, n, i0, j0, a0);
+    const int cj = (int)(b % ncol);
+    b /= ncol;
+    const int rc = (int)(b % nrch), n = (int)(b / nrch);
+    const int a0 = ac * 64, j0 = cj * kCols, i0 = rc * ilen, i1 = min(d.D0, i0 + ilen);
+    // D2 % 32 == 0: a last chunk of 32 azimuths runs as 64 (its halo and
+    // upper half wrap around the row) and stores its lower half
+    conv_walk<EPI, 4>(x, d, w, bias, mask, y, xs, n, j0, a0, i0, i1);
 }
 
 constexpr int kMaxD2 = 128;  // widest azimuth row of the MFMA layers
@@ -590,9 +632,6 @@ constexpr int kWGroups = 32;               // first-stage groups of their reduct
 __device__ __forceinline__ uint32_t pack_bf16x2(uint16_t lo, uint16_t hi) {
     return (uint32_t)lo | ((uint32_t)hi << 16);
 }
-
-// ring slot of r-row ii (ii >= -1)
-__device__ __forceinline__ int ring_of(int ii) { return (ii + 3) % 3; }
 
 template <int D2>
 __global__ __launch_bounds__(256, D2 <= 64 ? 2 : 1) void k_conv_wgrad_tiled(const uint16_t *__restrict__ x,
@@ -924,6 +963,8 @@ void reduce_parts(const float *part, int nb, int stride, int count, float *out, 
                        count, count, out);
 }
 
+bool aligned16(const void *p) { return (uintptr_t)p % 16 == 0; }
+
 bool dims_ok(int N, int D0, int D1, int D2) { return N > 0 && D0 > 0 && D1 > 0 && D2 > 0; }
 
 tspnn_status hipret(hipError_t e, const char *what) {
@@ -931,10 +972,18 @@ tspnn_status hipret(hipError_t e, const char *what) {
     return TSPNN_OK;
 }
 
-// workgroups of k_conv_lds: (n, block of r-rows, block of e-rows, 64-azimuth chunk)
-unsigned conv_blocks(const Dims &d) {
-    return (unsigned)((int64_t)d.N * ((d.D0 + kTileR - 1) / kTileR) *
-                      ((d.D1 + kTileRows - 1) / kTileRows) * ((d.D2 + 63) / 64));
+// work items of k_conv_lds: columns (object, e-row block, azimuth chunk) cut
+// along r into chunks of ilen r-rows, so that there are about kConvItems
+struct ConvPlan {
+    int ilen;
+    unsigned items;
+};
+ConvPlan conv_plan(const Dims &d) {
+    const int64_t cols = (int64_t)d.N * ((d.D1 + kCols - 1) / kCols) * ((d.D2 + 63) / 64);
+    const int64_t nrch =
+        std::max<int64_t>(1, std::min<int64_t>(d.D0, (kConvItems + cols - 1) / cols));
+    const int ilen = (int)((d.D0 + nrch - 1) / nrch);
+    return {ilen, (unsigned)(cols * ((d.D0 + ilen - 1) / ilen))};
 }
 
 tspnn_status mfma_dims(int N, int D0, int D1, int D2) {
@@ -1069,12 +1118,14 @@ tspnn_status tspnn_conv_fwd(const uint16_t *x, int32_t N, int32_t D0, int32_t D1
                             const uint16_t *w, const float *b, uint16_t *y, void *stream) {
     g_err.clear();
     if (!x || !w || !b || !y) return fail(TSPNN_E_INVALID, "tspnn_conv_fwd: NULL argument");
+    if (!aligned16(x) || !aligned16(w) || !aligned16(y))
+        return fail(TSPNN_E_INVALID, "tspnn_conv_fwd: bfloat16 arrays must be 16-byte aligned");
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    hipLaunchKernelGGL(k_conv_lds<0>, dim3(conv_blocks(d)), dim3(kConvThreads), 0,
-                       (hipStream_t)stream,
-                       x, d, w, b, (const uint16_t *)nullptr, y);
+    const ConvPlan pl = conv_plan(d);
+    hipLaunchKernelGGL(k_conv_lds<0>, dim3(pl.items), dim3(kConvThreads), 0, (hipStream_t)stream,
+                       x, d, pl.ilen, w, b, (const uint16_t *)nullptr, y);
     return hipret(hipGetLastError(), "tspnn_conv_fwd");
 }
 
@@ -1084,12 +1135,15 @@ tspnn_status tspnn_conv_bwd_data(const uint16_t *dz_out, int32_t N, int32_t D0, 
     g_err.clear();
     if (!dz_out || !w || !act_in || !dz_in)
         return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_data: NULL argument");
+    if (!aligned16(dz_out) || !aligned16(w) || !aligned16(act_in) || !aligned16(dz_in))
+        return fail(TSPNN_E_INVALID,
+                    "tspnn_conv_bwd_data: bfloat16 arrays must be 16-byte aligned");
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     Dims d{N, D0, D1, D2};
-    hipLaunchKernelGGL(k_conv_lds<1>, dim3(conv_blocks(d)), dim3(kConvThreads), 0,
-                       (hipStream_t)stream,
-                       dz_out, d, w, (const float *)nullptr, act_in, dz_in);
+    const ConvPlan pl = conv_plan(d);
+    hipLaunchKernelGGL(k_conv_lds<1>, dim3(pl.items), dim3(kConvThreads), 0, (hipStream_t)stream,
+                       dz_out, d, pl.ilen, w, (const float *)nullptr, act_in, dz_in);
     return hipret(hipGetLastError(), "tspnn_conv_bwd_data");
 }
 
@@ -1098,8 +1152,9 @@ tspnn_status tspnn_conv_bwd_weight(const uint16_t *x, const uint16_t *dz, int32_
                                    void *stream) {
     g_err.clear();
     if (!x || !dz || !dw || !work) return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_weight: NULL");
-    if ((uintptr_t)work % 16 != 0)
-        return fail(TSPNN_E_INVALID, "tspnn_conv_bwd_weight: work must be 16-byte aligned");
+    if (!aligned16(work) || !aligned16(x) || !aligned16(dz))
+        return fail(TSPNN_E_INVALID,
+                    "tspnn_conv_bwd_weight: x, dz and work must be 16-byte aligned");
     tspnn_status s = mfma_dims(N, D0, D1, D2);
     if (s != TSPNN_OK) return s;
     hipStream_t st = (hipStream_t)stream;

@@ -397,3 +397,24 @@ def test_checkpoint_resume_is_bitwise(nn, tmp_path):
         assert torch.equal(a, b)
     for a, b in zip(opt.m + opt.v, opt2.m + opt2.v):
         assert torch.equal(a, b)
+
+
+def test_conv_rejects_misaligned_arrays(nn):
+    """The 32 -> 32 layers move bfloat16 data in 8- and 16-byte pieces; an
+    array that is not 16-byte aligned is refused before any launch."""
+    N, D0, D1, D2 = 1, 3, 4, 32
+    x = torch.zeros(N * D0 * D1 * D2 * 32 + 8, dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros_like(x)
+    w = torch.zeros(27 * 32 * 32, dtype=torch.bfloat16, device="cuda")
+    b = torch.zeros(32, device="cuda")
+    ws = torch.empty(int(nn.lib.tspnn_conv_workspace(N, D0, D1, D2)) // 4 + 8, device="cuda")
+    dw = torch.empty((27, 32, 32), device="cuda")
+    off = nn._p(x[1:])  # 2 bytes past an aligned start
+    assert nn.lib.tspnn_conv_fwd(off, N, D0, D1, D2, nn._p(w), nn._p(b), nn._p(y), nn._s()) == 1
+    assert nn.lib.tspnn_conv_bwd_data(nn._p(x), N, D0, D1, D2, nn._p(w), off, nn._p(y),
+                                      nn._s()) == 1
+    assert nn.lib.tspnn_conv_bwd_weight(nn._p(x), nn._p(x), N, D0, D1, D2, nn._p(dw), None,
+                                        nn._p(ws[1:]), nn._s()) == 1
+    # aligned arrays pass
+    nn.check(nn.lib.tspnn_conv_fwd(nn._p(x), N, D0, D1, D2, nn._p(w), nn._p(b), nn._p(y), nn._s()))
+    torch.cuda.synchronize()
