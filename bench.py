@@ -271,9 +271,10 @@ def extra_cnn(reps=20):
 
 def extra_large_onthefly():
     """Large workload on the fly, batch 4: count pass (steps 1-3 without
-    storage), forward and atomic adjoint per launch; and the deterministic
-    adjoint, traced chunk by chunk within each call (second call timed, the
-    first one allocates its working memory)."""
+    storage), forward and atomic adjoint per launch; the fixed-point
+    (reproducible) adjoint per launch; and the deterministic adjoint, traced
+    chunk by chunk within each call (second call timed, the first one
+    allocates its working memory)."""
     import torch
 
     from paper_2608_16960_amd import workloads as W
@@ -291,6 +292,7 @@ def extra_large_onthefly():
     x = torch.empty_like(rho)
     f_ms = _time_ms(lambda: P.forward(rho, out=y), 3)
     a_ms = _time_ms(lambda: P.backproject(y, "atomic", out=x), 2)
+    fx_ms = _time_ms(lambda: P.backproject(y, "fixedpoint", out=x), 2)
     P.backproject(y, "deterministic", out=x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -309,7 +311,7 @@ def extra_large_onthefly():
     return {"workload": f"large: grid {P.shape}, {w.views.n_views} cone views "
                         f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch {B}",
             "count_s": count_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
-            "deterministic_adjoint_s": det_s,
+            "deterministic_adjoint_s": det_s, "fixedpoint_adjoint_ms": fx_ms,
             "forward_rays_per_s": B * R / f_ms * 1e3, "forward_segments_per_s": B * S / f_ms * 1e3,
             "adjoint_rays_per_s": B * R / a_ms * 1e3, "adjoint_segments_per_s": B * S / a_ms * 1e3,
             "forward_hbm_frac": alg / f_ms / 1e6 / HBM_PEAK_GBS,

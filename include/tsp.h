@@ -84,6 +84,7 @@ typedef enum tsp_status {
 /* tsp_backproject methods */
 #define TSP_ADJ_DETERMINISTIC 1 /* voxel-major store, fixed summation order, bitwise reproducible */
 #define TSP_ADJ_ATOMIC 2        /* ray-major scatter with float atomics (order varies run to run) */
+#define TSP_ADJ_FIXEDPOINT 3    /* traced on the fly, sums in 64-bit fixed point, bitwise reproducible */
 
 /* Grid boundaries (Sec. 2.2, Sec. 4.1).  Host pointers, read during
  * tsp_geometry_create only. */
@@ -229,8 +230,8 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
  * x[b][f][v] = sum over all segments in voxel v of rays of views in
  * object frame f of len * y[b][ray].
  * y: device float32 [batch][R]; x: device float32 [batch][F][V], overwritten.
- * method TSP_ADJ_DETERMINISTIC (bitwise reproducible) or TSP_ADJ_ATOMIC.
- * The deterministic adjoint reads the transposed store when the geometry was
+ * method TSP_ADJ_DETERMINISTIC (bitwise reproducible), TSP_ADJ_ATOMIC or
+ * TSP_ADJ_FIXEDPOINT (below).  The deterministic adjoint reads the transposed store when the geometry was
  * traced in CSR mode with it.  Otherwise (on the fly, or TSP_TRACE_NO_CSC) it
  * is traced within the call: the views (explicit rays: runs of whole 256-ray
  * windows) are cut into ceil(S / C) chunks of about equal segment counts
@@ -245,6 +246,17 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
  * kind on one geometry are serialised.  Bitwise reproducible for a given
  * geometry and C; with one chunk it equals the stored deterministic adjoint
  * bit for bit.
+ * method TSP_ADJ_FIXEDPOINT (any traced geometry, stored lists or not): the
+ * rays are traced within the call, as on the fly, and each term len * y is
+ * rounded to an integer multiple of 2^q_b and added in 64-bit integers, so
+ * that the sums do not depend on the order of addition: bitwise reproducible
+ * without transposed lists or chunking, and one pass.  q_b = ilogb(M_b) + 1
+ * - 62 with M_b = max |y_b| * 4 * R * r_out (R rays, r_out the outer radius),
+ * which bounds every voxel's sum of |terms| by half of M_b, so no partial sum
+ * overflows; a term's rounding error is at most 2^(q_b - 1), about 1e-19 M_b.
+ * The result is the exact sum of the rounded terms, converted to float once;
+ * it differs from TSP_ADJ_DETERMINISTIC's float sums in the last bits.
+ * Allocates 8 * V * (1 or 4) bytes stream-ordered (TSP_E_NOMEM otherwise).
  */
 tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch, float *x,
                            int32_t method, void *stream);

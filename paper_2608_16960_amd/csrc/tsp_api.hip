@@ -1228,10 +1228,20 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
     if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
     if (!x || !y) return fail(TSP_E_INVALID, "y or x is NULL");
     if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
-    if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC)
-        return fail(TSP_E_INVALID, "method must be TSP_ADJ_DETERMINISTIC or TSP_ADJ_ATOMIC");
+    if (method != TSP_ADJ_DETERMINISTIC && method != TSP_ADJ_ATOMIC &&
+        method != TSP_ADJ_FIXEDPOINT)
+        return fail(TSP_E_INVALID,
+                    "method must be TSP_ADJ_DETERMINISTIC, TSP_ADJ_ATOMIC or TSP_ADJ_FIXEDPOINT");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject before tsp_trace");
     DeviceGuard dg(g->device);
+    if (method == TSP_ADJ_FIXEDPOINT) {
+        const hipError_t e = launch_otf_adjoint_fixed(g->T, g->d_tab, g->rd, y, batch, g->V,
+                                                      g->r_out, x, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return fail(e == hipErrorOutOfMemory ? TSP_E_NOMEM : TSP_E_HIP,
+                        std::string("adjoint: ") + hipGetErrorString(e));
+        return TSP_OK;
+    }
     if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
         return chunked_adjoint(g, y, batch, x, (hipStream_t)stream);
     const hipError_t e = adjoint_dispatch(g, y, batch, x, method, (hipStream_t)stream);

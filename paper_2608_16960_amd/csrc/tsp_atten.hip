@@ -277,6 +277,11 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
 
 }  // namespace
 
+hipError_t launch_absmax(const float *a, int64_t n, unsigned *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_absmax, dim3(256), dim3(256), 0, st, a, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_atten_s(const float *sigma, const float *rho, int64_t V, int B, float *s,
                           hipStream_t st) {
     const int64_t n = V * B;

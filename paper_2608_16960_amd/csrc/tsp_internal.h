@@ -248,7 +248,15 @@ hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc
                               const float *rho, int B, int64_t vf, float *y, hipStream_t st);
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *y, int B, int64_t vf, float *x, hipStream_t st);
+// The on-the-fly adjoint with reproducible sums in 64-bit fixed point
+// (allocates its accumulators stream-ordered); r_out: outer radius.
+hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const RayDesc &rd,
+                                    const float *y, int B, int64_t vf, double r_out, float *x,
+                                    hipStream_t st);
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st);
+
+// *out = max |a[i]| over n floats, as float bits (atomicMax: *out zeroed first)
+hipError_t launch_absmax(const float *a, int64_t n, unsigned *out, hipStream_t st);
 
 // ---- launchers (tsp_sort.hip) ----
 hipError_t launch_window_sort(const RayDesc &rd, const int32_t *cnt_nat, int32_t *perm,

@@ -32,6 +32,7 @@
 // kernels, which re-trace the same ray, evaluate identical arithmetic.
 
 #include <cmath>
+#include <type_traits>
 
 #include "tsp_internal.h"
 #include "tsp_trace_core.h"
@@ -251,11 +252,24 @@ __global__ __launch_bounds__(256) void k_otf_forward(TabDesc D, const double *ta
         if (b < nb) y[b * rd.R + ray] = vis.acc[b];
 }
 
+// Value of lane l + K in lane l (row_shl:K within rows of 16; 0 past the row).
+template <int K>
+__device__ __forceinline__ float dpp_from_up(float x) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x100 + K, 0xf, 0xf, false));
+}
+template <int K>
+__device__ __forceinline__ long long dpp_from_up(long long x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(x & 0xffffffffll), 0x100 + K, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), 0x100 + K, 0xf, 0xf, false);
+    return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // Lanes l and l + K (bit K of l clear, K <= 8: both in one row of 16) that
 // hold the same voxel (v >= 0) add their values in lane l; lane l + K drops
 // out (v = -1).  Every lane of the wavefront must be active.
-template <int K, int NB>
-__device__ __forceinline__ void merge_pairs(int &v, float *val, int lane) {
+template <int K, int NB, class T>
+__device__ __forceinline__ void merge_pairs(int &v, T *val, int lane) {
     const int up = __builtin_amdgcn_update_dpp(-1, v, 0x100 + K, 0xf, 0xf, false);  // row_shl:K
     const int dn = __builtin_amdgcn_update_dpp(-1, v, 0x110 + K, 0xf, 0xf, false);  // row_shr:K
     const bool low = (lane & K) == 0;
@@ -263,8 +277,7 @@ __device__ __forceinline__ void merge_pairs(int &v, float *val, int lane) {
     const bool give = !low && v >= 0 && dn == v;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
-        const float t = __int_as_float(
-            __builtin_amdgcn_update_dpp(0, __float_as_int(val[b]), 0x100 + K, 0xf, 0xf, false));
+        const T t = dpp_from_up<K>(val[b]);
         if (take) val[b] += t;
     }
     if (give) v = -1;
@@ -288,42 +301,74 @@ __device__ __forceinline__ void merge_pairs(int &v, float *val, int lane) {
 // correctness.
 constexpr int kOtfEvents = 16;
 constexpr int kOtfProbes = 8;
-template <int NB> struct OtfHash {
-    static constexpr int kSize = NB == 1 ? 2048 : 1024;  // power of two
-    static constexpr size_t kBytes = (size_t)kSize * (1 + NB) * 4;
+// FIX: values are 64-bit fixed-point integers (the reproducible variant below)
+template <int NB, bool FIX = false> struct OtfHash {
+    using Val = typename std::conditional<FIX, long long, float>::type;
+    static constexpr int kSize = FIX ? (NB == 1 ? 1024 : 512) : (NB == 1 ? 2048 : 1024);  // power of two
+    static constexpr size_t kBytes = (size_t)kSize * (4 + NB * sizeof(Val));
     static_assert(kBytes <= kOtfHashBytes, "hash table exceeds its LDS reserve");
 };
+
+// Reproducible sums in fixed point.  Object b's terms len * y are rounded to
+// integer multiples of 2^q_b (round to nearest even) and added as 64-bit
+// integers, so that every order of addition gives the same sum.  q_b follows
+// from M_b = max |y_b| * lsum, lsum = 2 * (rays) * (diameter of the outer
+// sphere) >= twice the summed lengths of all rays, which bounds every voxel's
+// sum of |terms|: q_b = ilogb(M_b) + 1 - 62 keeps it, and so every partial
+// sum, below 2^62 quanta.
+__device__ __forceinline__ int fix_exponent(unsigned ybits, double lsum) {
+    return ilogb(fmax((double)__uint_as_float(ybits), 1e-30) * lsum) + 1 - 62;
+}
 
 // The batch-4 kernel allocates 96 VGPRs, five wavefronts per SIMD; one
 // fewer wavefront to hide the LDS atomics behind costs about 6%.  (Asking
 // for five with amdgpu_waves_per_eu now makes the compiler spill instead.)
-template <int NB>
+__device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
+__device__ __forceinline__ void lds_add(long long *p, long long v) {
+    atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
+}
+__device__ __forceinline__ void global_add(float *x, unsigned long long *, int64_t i, float v) {
+    atomicAdd(x + i, v);
+}
+__device__ __forceinline__ void global_add(float *, unsigned long long *acc, int64_t i,
+                                           long long v) {
+    atomicAdd(acc + i, (unsigned long long)v);
+}
+
+// FIX: the sums go in 64-bit fixed point (fix_exponent) into acc_out (same
+// layout as x_out) instead of float atomics into x_out; ybits[b] holds
+// max |y| of object b as float bits.
+template <int NB, bool FIX>
 __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *tab, RayDesc rd,
                                                       const float *y, int nb, int64_t V,
-                                                      float *x_out) {
-    constexpr int HS = OtfHash<NB>::kSize;
+                                                      float *x_out, unsigned long long *acc_out,
+                                                      const unsigned *ybits, double lsum) {
+    using Val = typename OtfHash<NB, FIX>::Val;
+    constexpr int HS = OtfHash<NB, FIX>::kSize;
     extern __shared__ double lds[];  // grid tables, then the hash keys and values
     __shared__ int fill;
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
     int *hkey = reinterpret_cast<int *>(lds + D.n_tab);
-    float *hval = reinterpret_cast<float *>(hkey + HS);  // [NB][HS]
+    Val *hval = reinterpret_cast<Val *>(hkey + HS);  // [NB][HS]
     const int64_t win = xcd_window(rd.n_slots / kWindow);
     if (win >= rd.n_slots / kWindow) return;  // whole padding blocks of the remapped grid
     for (int i = threadIdx.x; i < HS; i += 256) {
         hkey[i] = -1;
 #pragma unroll
-        for (int b = 0; b < NB; b++) hval[b * HS + i] = 0.0f;
+        for (int b = 0; b < NB; b++) hval[b * HS + i] = (Val)0;
     }
     if (threadIdx.x == 0) fill = 0;
     const int64_t slot = win * kWindow + threadIdx.x;
     const int32_t ray = natural_ray(rd, slot);
     float yv[NB];
+    double sc[NB];  // FIX: 2^-q_b
     bool any = false;
 #pragma unroll
     for (int b = 0; b < NB; b++) {
         yv[b] = (ray >= 0 && b < nb) ? y[b * rd.R + ray] : 0.0f;
         any |= (yv[b] != 0.0f);
+        sc[b] = FIX ? ldexp(1.0, -fix_exponent(ybits[b < nb ? b : 0], lsum)) : 1.0;
     }
     Walker w;
     bool alive = false;
@@ -352,9 +397,14 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                     lf = (float)l;
                 }
             }
-            float val[NB];
+            Val val[NB];
 #pragma unroll
-            for (int b = 0; b < NB; b++) val[b] = lf * yv[b];
+            for (int b = 0; b < NB; b++) {
+                if (FIX)  // the product of two floats is exact in double
+                    val[b] = (Val)rint((double)lf * (double)yv[b] * sc[b]);
+                else
+                    val[b] = (Val)(lf * yv[b]);
+            }
             merge_pairs<1, NB>(v, val, lane);
             merge_pairs<2, NB>(v, val, lane);
             merge_pairs<4, NB>(v, val, lane);
@@ -372,7 +422,7 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                     }
                     if (key == -1 || key == v) {
 #pragma unroll
-                        for (int b = 0; b < NB; b++) atomicAdd(hval + b * HS + h, val[b]);
+                        for (int b = 0; b < NB; b++) lds_add(hval + b * HS + h, val[b]);
                         done = true;
                         break;
                     }
@@ -381,7 +431,7 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                 if (!done) {
 #pragma unroll
                     for (int b = 0; b < NB; b++)
-                        if (b < nb) atomicAdd(x_out + (int64_t)v * NB + b, val[b]);
+                        if (b < nb) global_add(x_out, acc_out, (int64_t)v * NB + b, val[b]);
                 }
             }
             // one add to the fill count per wavefront, not one per claim on a
@@ -398,8 +448,8 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                 if (key < 0) continue;
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    if (b < nb) atomicAdd(x_out + (int64_t)key * NB + b, hval[b * HS + i]);
-                    hval[b * HS + i] = 0.0f;
+                    if (b < nb) global_add(x_out, acc_out, (int64_t)key * NB + b, hval[b * HS + i]);
+                    hval[b * HS + i] = (Val)0;
                 }
                 hkey[i] = -1;
             }
@@ -408,6 +458,23 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
         }
         if (!more) break;
     }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// x[b][v] = the fixed-point sum acc[v * NB + b] times 2^q_b, rounded to float
+// (through double); b < nb.
+__global__ void k_fix_to_float(const unsigned long long *acc, int NB, int nb, int64_t V,
+                               const unsigned *ybits, double lsum, float *x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nb * V) return;
+    const int b = (int)(i / V);
+    const int64_t v = i - (int64_t)b * V;
+    const long long a = (long long)acc[v * NB + b];
+    x[i] = (float)ldexp((double)a, fix_exponent(ybits[b], lsum));
 }
 
 __global__ void k_rays(RayDesc rd, double *starts, double *dirs) {
@@ -509,7 +576,8 @@ hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc
     const size_t sh = T.n_tab * sizeof(double) + (B == 1 ? OtfHash<1>::kBytes : OtfHash<4>::kBytes);
     const dim3 grid(remapped_grid(rd.n_slots));
     if (B == 1) {
-        hipLaunchKernelGGL(k_otf_adjoint<1>, grid, dim3(256), sh, st, T, tab, rd, y, 1, V, x);
+        hipLaunchKernelGGL((k_otf_adjoint<1, false>), grid, dim3(256), sh, st, T, tab, rd, y, 1, V,
+                           x, (unsigned long long *)nullptr, (const unsigned *)nullptr, 0.0);
         return hipGetLastError();
     }
     float *vm = nullptr;
@@ -521,13 +589,54 @@ hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc
         float *xx = x + (int64_t)b0 * V;
         hipLaunchKernelGGL(k_zero4, dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st, vm,
                            4 * V);
-        hipLaunchKernelGGL(k_otf_adjoint<4>, grid, dim3(256), sh, st, T, tab, rd, yy, nb, V, vm);
+        hipLaunchKernelGGL((k_otf_adjoint<4, false>), grid, dim3(256), sh, st, T, tab, rd, yy, nb,
+                           V, vm, (unsigned long long *)nullptr, (const unsigned *)nullptr, 0.0);
         hipLaunchKernelGGL(k_from_vmajor, dim3((unsigned)((nb * V + 255) / 256)), dim3(256), 0, st,
                            vm, nb, V, xx);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipFreeAsync(vm, st);
+}
+
+hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const RayDesc &rd,
+                                    const float *y, int B, int64_t vf, double r_out, float *x,
+                                    hipStream_t st) {
+    const int64_t V = vf * rd.n_obj_frames;
+    const int NB = B == 1 ? 1 : 4;
+    const double lsum = 2.0 * (double)rd.R * (2.0 * r_out);
+    const size_t sh = T.n_tab * sizeof(double) +
+                      (B == 1 ? OtfHash<1, true>::kBytes : OtfHash<4, true>::kBytes);
+    const dim3 grid(remapped_grid(rd.n_slots));
+    // the sums, then four words of max |y|
+    const int64_t words = V * NB + 2;
+    unsigned long long *acc = nullptr;
+    hipError_t e = hipMallocAsync((void **)&acc, (size_t)words * 8, st);
+    if (e != hipSuccess) return e;
+    unsigned *bits = reinterpret_cast<unsigned *>(acc + V * NB);
+    for (int b0 = 0; b0 < B; b0 += 4) {
+        const int nb = (B - b0 < 4) ? (B - b0) : 4;
+        const float *yy = y + (int64_t)b0 * rd.R;
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                           acc, words);
+        for (int b = 0; b < nb; b++) {
+            e = launch_absmax(yy + (int64_t)b * rd.R, rd.R, bits + b, st);
+            if (e != hipSuccess) break;
+        }
+        if (e != hipSuccess) break;
+        if (B == 1)
+            hipLaunchKernelGGL((k_otf_adjoint<1, true>), grid, dim3(256), sh, st, T, tab, rd, yy, 1,
+                               V, (float *)nullptr, acc, bits, lsum);
+        else
+            hipLaunchKernelGGL((k_otf_adjoint<4, true>), grid, dim3(256), sh, st, T, tab, rd, yy, nb,
+                               V, (float *)nullptr, acc, bits, lsum);
+        hipLaunchKernelGGL(k_fix_to_float, dim3((unsigned)((nb * V + 255) / 256)), dim3(256), 0, st,
+                           acc, NB, nb, V, bits, lsum, x + (int64_t)b0 * V);
+        e = hipGetLastError();
+        if (e != hipSuccess) break;
+    }
+    const hipError_t ef = hipFreeAsync(acc, st);
+    return e != hipSuccess ? e : ef;
 }
 
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st) {

@@ -16,6 +16,7 @@ TSP_MODE_ONTHEFLY = 2
 TSP_TRACE_NO_CSC = 0x10
 TSP_ADJ_DETERMINISTIC = 1
 TSP_ADJ_ATOMIC = 2
+TSP_ADJ_FIXEDPOINT = 3
 
 STATUS_NAMES = {0: "TSP_OK", 1: "TSP_E_INVALID", 2: "TSP_E_NOMEM", 3: "TSP_E_HIP",
                 4: "TSP_E_STATE", 5: "TSP_E_UNSUPPORTED"}

@@ -17,7 +17,8 @@ import torch
 from . import native as N
 
 MODES = {"csr": N.TSP_MODE_CSR, "onthefly": N.TSP_MODE_ONTHEFLY}
-ADJ = {"deterministic": N.TSP_ADJ_DETERMINISTIC, "atomic": N.TSP_ADJ_ATOMIC}
+ADJ = {"deterministic": N.TSP_ADJ_DETERMINISTIC, "atomic": N.TSP_ADJ_ATOMIC,
+       "fixedpoint": N.TSP_ADJ_FIXEDPOINT}
 
 
 def _grid_arrays(grid):
@@ -174,8 +175,10 @@ class Projector:
 
         method: "deterministic" (bitwise reproducible; from the voxel-major
         store when the lists are stored with it, else traced chunk by chunk
-        within the call, which costs a full trace), "atomic", or None: the
-        stored deterministic adjoint when there is one, else the atomic one."""
+        within the call, which costs a full trace), "atomic", "fixedpoint"
+        (bitwise reproducible: traced within the call, sums in 64-bit fixed
+        point, one pass), or None: the stored deterministic adjoint when there
+        is one, else the atomic one."""
         y = self._dev_f32(y, "y")
         k = len(self.out_shape)
         if tuple(y.shape[y.dim() - k:]) != self.out_shape:
