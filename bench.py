@@ -303,11 +303,13 @@ def extra_large_onthefly():
     P.close()
     from paper_2608_16960_amd.profiling import read_valu
     fp64 = {}
-    for k, kern in (("forward", "k_otf_forward<4>"), ("adjoint", "k_otf_adjoint<4>")):
+    for k, kern in (("forward", "k_otf_forward<4>"), ("adjoint", "k_otf_adjoint<4, false>"),
+                    ("fixedpoint_adjoint", "k_otf_adjoint<4, true>")):
         r = read_valu(os.path.join(ROOT, "profiles", "otf_large_fp64.txt"), kern)
         fp64[k] = None if r is None else {
             "flops_per_launch": r[0], "frac_of_fp64_peak": r[1],
-            "tflops_live": r[0] / ((f_ms if k == "forward" else a_ms) * 1e9)}
+            "tflops_live": r[0] / ({"forward": f_ms, "adjoint": a_ms,
+                                    "fixedpoint_adjoint": fx_ms}[k] * 1e9)}
     return {"workload": f"large: grid {P.shape}, {w.views.n_views} cone views "
                         f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch {B}",
             "count_s": count_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
@@ -587,7 +589,7 @@ def main():
     traffic = d["traffic_bytes"]
     occ = {k: read_occupancy(os.path.join(prof, "occupancy.md"), k)
            for k in ("k_fwd_sell<1>", "k_tile_y<1>", "k_adj_csc<1>", "k_otf_forward<4>",
-                     "k_otf_adjoint<4>")}
+                     "k_otf_adjoint<4, false>", "k_otf_adjoint<4, true>")}
     line = {
         "metric": "rays/s & segments/s fwd+adjoint (%HBM roofline); projector calls to residual",
         "value": R / (ms_step / 1e3),

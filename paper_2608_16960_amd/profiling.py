@@ -24,7 +24,9 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = {"k_fwd_sell<1>": "csrc/tsp_apply.hip", "k_adj_csc<1>": "csrc/tsp_apply.hip",
                   "k_tile_y<1>": "csrc/tsp_apply.hip",
-                  "k_otf_forward<4>": "csrc/tsp_trace.hip", "k_otf_adjoint<4>": "csrc/tsp_trace.hip"}
+                  "k_otf_forward<4>": "csrc/tsp_trace.hip",
+                  "k_otf_adjoint<4, false>": "csrc/tsp_trace.hip",
+                  "k_otf_adjoint<4, true>": "csrc/tsp_trace.hip"}
 FP64_PEAK_TFLOPS = 78.6  # MI355X vector FP64, published
 COPY_KIB = 1 << 20  # the calibration copy moves 1 GiB each way
 
@@ -40,6 +42,11 @@ def source_sha(kernel):
         with open(os.path.join(PKG, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:12]
+
+
+def _tok(kernel):
+    """A kernel name as one token of a machine-readable line ("k_x<4, true>" -> "k_x<4,true>")."""
+    return kernel.replace(" ", "")
 
 
 def _match(name, kernel):
@@ -66,7 +73,8 @@ def _mean_ns(stats_dir, kernel):
     return None
 
 
-def summarise_valu(pmc_dir, stats_dir, kernels=("k_otf_forward<4>", "k_otf_adjoint<4>")):
+def summarise_valu(pmc_dir, stats_dir, kernels=("k_otf_forward<4>", "k_otf_adjoint<4, false>",
+                                                 "k_otf_adjoint<4, true>")):
     """FP64 work per dispatch from SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 (wave
     instructions; x64 lanes, FMA counts 2 flops) and the kernel's mean duration
     from a --kernel-trace --stats run of the same command."""
@@ -91,7 +99,7 @@ def read_valu(txt_path, kernel):
         return None
     for line in open(txt_path):
         parts = line.split()
-        if len(parts) == 5 and parts[0] == "valu" and parts[1] == kernel:
+        if len(parts) == 5 and parts[0] == "valu" and parts[1] == _tok(kernel):
             return (float(parts[2]), float(parts[3])) if parts[4] == source_sha(kernel) else None
     return None
 
@@ -103,7 +111,7 @@ def _counter(dirname):
         name = r["Kernel_Name"]
         key = None
         for k in KERNEL_SOURCES:
-            if k.split("<")[0] in name:
+            if _match(name, k):
                 key = k
         if "copyBuffer" in name and float(r["Counter_Value"]) > 1e5:
             key = "copy"
@@ -131,7 +139,7 @@ def read_traffic(txt_path, kernel):
         return None
     for line in open(txt_path):
         parts = line.split()
-        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == kernel:
+        if len(parts) == 4 and parts[0] == "traffic" and parts[1] == _tok(kernel):
             return float(parts[2]) if parts[3] == source_sha(kernel) else None
     return None
 
@@ -143,7 +151,7 @@ def main_valu(argv):
         f.write("\n# machine-readable: valu <kernel> <FP64 flops per dispatch> <fraction of "
                 f"{FP64_PEAK_TFLOPS} TFLOP/s> <source sha1>\n")
         for k, v in s.items():
-            f.write(f"valu {k} {v['fp64_flops']:.0f} {v['frac']:.4f} {v['sha1']}\n")
+            f.write(f"valu {_tok(k)} {v['fp64_flops']:.0f} {v['frac']:.4f} {v['sha1']}\n")
             cs = ", ".join(f"{n} {x:.4g}" for n, x in sorted(v["counters"].items()))
             f.write(f"# {k}: {v['ns'] / 1e6:.2f} ms, {v['tflops']:.2f} TFLOP/s FP64; {cs}\n")
 
@@ -192,7 +200,7 @@ def main_occupancy(argv):
         for k in kernels:
             c = _per_dispatch(pmc_dir, k)
             if c and k in KERNEL_SOURCES:
-                f.write(f"occupancy {k} {c.get('MeanOccupancyPerCU', float('nan')):.2f} "
+                f.write(f"occupancy {_tok(k)} {c.get('MeanOccupancyPerCU', float('nan')):.2f} "
                         f"{source_sha(k)}\n")
 
 
@@ -204,7 +212,7 @@ def read_occupancy(path, kernel):
         return None
     for line in open(path):
         parts = line.split()
-        if len(parts) == 4 and parts[0] == "occupancy" and parts[1] == kernel:
+        if len(parts) == 4 and parts[0] == "occupancy" and parts[1] == _tok(kernel):
             return float(parts[2]) if parts[3] == source_sha(kernel) else None
     return None
 
@@ -258,7 +266,7 @@ def main(argv):
     with open(out_txt, "a") as f:
         f.write("\n# machine-readable: traffic <kernel> <bytes per dispatch> <source sha1>\n")
         for k, v in s.items():
-            f.write(f"traffic {k} {v['bytes']:.0f} {v['sha1']}\n")
+            f.write(f"traffic {_tok(k)} {v['bytes']:.0f} {v['sha1']}\n")
             if k in algo:
                 f.write(f"# {k}: fetch {v['fetch_kib']:.0f} KiB x {v['fetch_scale']:.3f}, write "
                         f"{v['write_kib']:.0f} KiB x {v['write_scale']:.3f}; algorithmic "
