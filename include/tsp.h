@@ -334,11 +334,13 @@ tsp_status tsp_atten_forward(const tsp_geometry *g, const tsp_geometry *g_sun, c
  *   TSP_ADJ_ATOMIC: the line-of-sight terms are scattered with float atomic
  *     adds (merged per voxel across a wavefront first); the summation order,
  *     and so the last bits, vary from run to run.
- *   TSP_ADJ_DETERMINISTIC: the same merged terms are added as exact
- *     fixed-point integers (three 32-bit limbs of a 96-bit value with a
- *     scale from a bound on the terms, in 64-bit integer atomics), so every
- *     voxel's sum is exact up to terms below 2^-95 of that bound and the
- *     result is bitwise reproducible; F_sun^T uses the sunward geometry's
+ *   TSP_ADJ_DETERMINISTIC: the same merged terms are rounded to integer
+ *     multiples of 2^q and added as 64-bit integers (integer atomics), with
+ *     q = ilogb(M) + 1 - 62 from M = 2 max|gy| R 2 r_out (1 + 2 r_out
+ *     max|rho|), which bounds twice any voxel's sum of |terms|: no partial
+ *     sum overflows, every order of addition gives the same sum, and the
+ *     result is bitwise reproducible (each term's rounding is at most 2^-63
+ *     of M); F_sun^T uses the sunward geometry's
  *     deterministic adjoint, which must have its voxel-major store
  *     (TSP_E_STATE otherwise).
  * rho, sigma as for tsp_atten_forward; tau1: [batch][V] from

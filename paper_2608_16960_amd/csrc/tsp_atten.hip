@@ -109,34 +109,28 @@ __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ p
     y[ray] = acc;
 }
 
-// Add v (exact) into the three limb accumulators acc[0..2][i] of stride V:
-// |v| / 2^qe = l2 2^64 + l1 2^32 + l0 with 0 <= l < 2^32, signed by v.
-__device__ __forceinline__ void fixed_add(unsigned long long *acc, int64_t V, int64_t i, float v,
-                                          int qe) {
-    if (v == 0.0f) return;
-    const double a = ldexp(fabs((double)v), -qe);  // exact: a power-of-two scaling
-    const double l2 = floor(ldexp(a, -64));
-    const double r = a - ldexp(l2, 64);              // exact
-    const double l1 = floor(ldexp(r, -32));
-    const double l0 = floor(r - ldexp(l1, 32));      // truncates below 2^qe
-    const int64_t sg = (v < 0.0f) ? -1 : 1;
-    // a zero limb adds nothing: most values lie far below the bound, and
-    // their top limb (and often the middle one) is zero
-    if (l0 != 0.0) atomicAdd(acc + i, (unsigned long long)(sg * (int64_t)l0));
-    if (l1 != 0.0) atomicAdd(acc + V + i, (unsigned long long)(sg * (int64_t)l1));
-    if (l2 != 0.0) atomicAdd(acc + 2 * V + i, (unsigned long long)(sg * (int64_t)l2));
+// Add v into the 64-bit fixed-point accumulator acc[i]: v rounded to an
+// integer multiple of 2^qe (nearest, ties to even; the scaling by a power
+// of two is exact).
+__device__ __forceinline__ void fixed_add(unsigned long long *acc, int64_t i, float v, int qe) {
+    const long long q = (long long)rint(ldexp((double)v, -qe));
+    if (q != 0) atomicAdd(acc + i, (unsigned long long)q);
 }
 
-// Scale exponent of the fixed-point sums: M = 64 max|g| 2 R (1 + 2 R max|w|)
-// bounds any merged contribution of either gradient term (64 lanes, a
-// length below the outer sphere's diameter 2 R, exp(-T) <= 1, and a suffix
-// sum below 2 R max|w|); bits[0], bits[1] hold max|g| and max|w| as float
-// bits (non-negative floats order like their bit patterns).
-__device__ __forceinline__ int fixed_exponent(const unsigned *bits, double two_r) {
+// Scale exponent of the fixed-point sums.  Every line of sight adds to a
+// voxel at most max|g| len (the w-gradient: exp(-T) <= 1) and max|g| len
+// 2R max|w| (the s-gradient: a suffix sum stays below the outer sphere's
+// diameter 2R times max|w|), and its lengths add up to at most 2R, so
+// M = 2 max|g| nrays 2R (1 + 2R max|w|) bounds twice any voxel's sum of
+// |terms| (the factor 2 covers the float rounding of merged terms and
+// lengths); q = ilogb(M) + 1 - 62 keeps every partial sum below 2^62 quanta.
+// bits[0], bits[1] hold max|g| and max|w| as float bits (non-negative
+// floats order like their bit patterns).
+__device__ __forceinline__ int fixed_exponent(const unsigned *bits, double two_r, double nrays) {
     const double mg = (double)__uint_as_float(bits[0]);
     const double mw = (double)__uint_as_float(bits[1]);
-    const double M = 64.0 * fmax(mg, 1e-30) * two_r * (1.0 + two_r * mw);
-    return ilogb(M) + 1 - 95;
+    const double M = 2.0 * fmax(mg, 1e-30) * nrays * two_r * (1.0 + two_r * mw);
+    return ilogb(M) + 1 - 62;
 }
 
 // out[0] = max |a| over n floats, as float bits, by atomicMax (out zeroed first)
@@ -150,21 +144,13 @@ __global__ void k_absmax(const float *__restrict__ a, int64_t n, unsigned *out) 
     if ((threadIdx.x & 63) == 0) atomicMax(out, m);
 }
 
-// x[i] = the float of the exact sum held in the limbs, times 2^qe: the limbs
-// are carried into canonical form first, then converted once to double
-// (rounded) and to float.
+// x[i] = the fixed-point sum acc[i] times 2^qe, converted once (through
+// double) to float.
 __global__ void k_fixed_to_float(const unsigned long long *acc, int64_t V,
-                                 const unsigned *bits, double two_r, float *x) {
+                                 const unsigned *bits, double two_r, double nrays, float *x) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= V) return;
-    const int qe = fixed_exponent(bits, two_r);
-    int64_t a0 = (int64_t)acc[i], a1 = (int64_t)acc[V + i], a2 = (int64_t)acc[2 * V + i];
-    a1 += a0 >> 32;  // arithmetic shifts: floor division by 2^32
-    const uint64_t r0 = (uint64_t)a0 & 0xffffffffull;
-    a2 += a1 >> 32;
-    const uint64_t r1 = (uint64_t)a1 & 0xffffffffull;
-    const double lo = (double)((r1 << 32) | r0);
-    x[i] = (float)ldexp(ldexp((double)a2, 64) + lo, qe);
+    x[i] = (float)ldexp((double)(long long)acc[i], fixed_exponent(bits, two_r, nrays));
 }
 
 template <bool FIXED>
@@ -179,11 +165,12 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                                                     const float *__restrict__ gy, int na,
                                                     int nena, float *gw, float *gs,
                                                     unsigned long long *acc, int64_t V,
-                                                    const unsigned *bits, double two_r) {
-    // FIXED: acc holds the limbs of gw ([3][V]) then of gs ([3][V])
+                                                    const unsigned *bits, double two_r,
+                                                    double nrays) {
+    // FIXED: acc holds the fixed-point sums of gw ([V]) then of gs ([V])
     const int64_t slot = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (slot >= n_slots) return;  // n_slots is a multiple of 256: whole wavefronts
-    const int qe = FIXED ? fixed_exponent(bits, two_r) : 0;
+    const int qe = FIXED ? fixed_exponent(bits, two_r, nrays) : 0;
     const int lane = (int)(slot & 63);
     const int32_t ray = perm[slot];
     const int c = (ray >= 0) ? cnt_sorted[slot] : 0;
@@ -268,8 +255,8 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
                 }
             }
             if (FIXED && mv >= 0) {
-                fixed_add(acc, V, mv, ma, qe);
-                fixed_add(acc + 3 * V, V, mv, mb, qe);
+                fixed_add(acc, mv, ma, qe);
+                fixed_add(acc + V, mv, mb, qe);
             }
         }
     }
@@ -330,28 +317,30 @@ hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
                             const uint8_t *code, const float *len, const float *s, const float *w,
                             const float *gy, int B, int64_t V, int na, int nena, double r_out,
                             float *gw, float *gs, void *ws, hipStream_t st) {
-    const double two_r = 2.0 * r_out;
+    const double two_r = 2.0 * r_out, nrays = (double)rd.R;
     for (int b = 0; b < B; b++) {
         const unsigned grid = blocks_for(rd.n_slots, 256);
         if (!ws) {
             hipLaunchKernelGGL(k_bwd_atten<false>, dim3(grid), dim3(256), 0, st, perm, cnt_sorted,
                                slice_ptr, slice_len, code, len, rd.n_slots, s + b * V, w + b * V,
                                gy + b * rd.R, na, nena, gw + b * V, gs + b * V, nullptr, V,
-                               nullptr, two_r);
+                               nullptr, two_r, nrays);
         } else {
             unsigned long long *acc = (unsigned long long *)ws;
-            unsigned *bits = (unsigned *)(acc + 6 * V);
-            hipError_t e = hipMemsetAsync(ws, 0, atten_fixed_ws_bytes(V), st);
+            unsigned *bits = (unsigned *)(acc + 2 * V);
+            // cleared by a kernel (not a memset node, should a caller capture this)
+            hipError_t e = launch_zero_u64(acc, 2 * V + 1, st);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_absmax, dim3(256), dim3(256), 0, st, gy + b * rd.R, rd.R, bits);
             hipLaunchKernelGGL(k_absmax, dim3(256), dim3(256), 0, st, w + b * V, V, bits + 1);
             hipLaunchKernelGGL(k_bwd_atten<true>, dim3(grid), dim3(256), 0, st, perm, cnt_sorted,
                                slice_ptr, slice_len, code, len, rd.n_slots, s + b * V, w + b * V,
-                               gy + b * rd.R, na, nena, nullptr, nullptr, acc, V, bits, two_r);
+                               gy + b * rd.R, na, nena, nullptr, nullptr, acc, V, bits, two_r,
+                               nrays);
             hipLaunchKernelGGL(k_fixed_to_float, dim3(blocks_for(V, 256)), dim3(256), 0, st, acc,
-                               V, bits, two_r, gw + b * V);
+                               V, bits, two_r, nrays, gw + b * V);
             hipLaunchKernelGGL(k_fixed_to_float, dim3(blocks_for(V, 256)), dim3(256), 0, st,
-                               acc + 3 * V, V, bits, two_r, gs + b * V);
+                               acc + V, V, bits, two_r, nrays, gs + b * V);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -359,6 +348,6 @@ hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
     return hipSuccess;
 }
 
-size_t atten_fixed_ws_bytes(int64_t V) { return (size_t)V * 48 + 64; }
+size_t atten_fixed_ws_bytes(int64_t V) { return (size_t)V * 16 + 64; }
 
 }  // namespace tsp

@@ -255,6 +255,8 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
                                     hipStream_t st);
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st);
 
+// p[0 .. n) = 0 (64-bit words), by a kernel
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st);
 // *out = max |a[i]| over n floats, as float bits (atomicMax: *out zeroed first)
 hipError_t launch_absmax(const float *a, int64_t n, unsigned *out, hipStream_t st);
 
@@ -346,8 +348,8 @@ hipError_t launch_fwd_atten(const RayDesc &rd, const int32_t *perm, const int32_
                             const uint8_t *code, const float *len, const float *s, const float *w,
                             int B, int64_t V, int na, int nena, float *y, hipStream_t st);
 // gw, gs overwritten (zeroed by the caller when ws is null: float atomics);
-// ws non-null: atten_fixed_ws_bytes(V) bytes for the exact fixed-point sums
-// of the deterministic backward.  r_out: the grid's outer radius.
+// ws non-null: atten_fixed_ws_bytes(V) bytes for the fixed-point sums of the
+// deterministic backward.  r_out: the grid's outer radius.
 hipError_t launch_bwd_atten(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
                             const uint8_t *code, const float *len, const float *s, const float *w,

@@ -639,6 +639,12 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
     return e != hipSuccess ? e : ef;
 }
 
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
+    if (n > 0)
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_rays(const RayDesc &rd, double *starts, double *dirs, hipStream_t st) {
     hipLaunchKernelGGL(k_rays, dim3((unsigned)((rd.R + 255) / 256)), dim3(256), 0, st, rd, starts,
                        dirs);
