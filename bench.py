@@ -59,15 +59,23 @@ def _args():
 
 
 def _host():
-    """CPU model (lscpu, else /proc/cpuinfo), logical CPUs, and the CPUs this
-    process may run on."""
+    """CPU model (lscpu, else /proc/cpuinfo) with lscpu's vendor, family,
+    model, stepping, clock and cache lines where it prints them (a virtual
+    machine may name the CPU only by its brand), logical CPUs, and the CPUs
+    this process may run on."""
     import subprocess
     model = None
+    lscpu = {}
+    keys = ("Vendor ID", "CPU family", "Model", "Stepping", "CPU max MHz", "BogoMIPS",
+            "L2 cache", "L3 cache", "Hypervisor vendor")
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
         for line in out.splitlines():
-            if line.startswith("Model name:"):
-                model = line.split(":", 1)[1].strip()
+            k, _, v = line.partition(":")
+            if k.strip() == "Model name":
+                model = v.strip()
+            elif k.strip() in keys:
+                lscpu[k.strip()] = v.strip()
     except (OSError, subprocess.SubprocessError):
         pass
     if model is None:
@@ -78,7 +86,8 @@ def _host():
                     break
         except OSError:
             model = platform.processor() or platform.machine()
-    return {"model": model, "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    return {"model": model, "lscpu": lscpu, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(w, n_views, large_views=6, diff_views=10, full=False):
