@@ -144,3 +144,32 @@ def test_medium_against_stored(dev):
         rhs = float((xr[b].double() * x[b].double()).sum())
         scale = float((Fx[b].abs() * yr[b].double().abs()).sum())
         assert abs(lhs - rhs) <= 1e-6 * scale, b
+
+
+def test_wide_dynamic_range(ora, dev):
+    """One measurement 2^60 times the others: the quantum follows max |y|, so
+    the small terms are rounded to multiples of 2^q and may vanish, but every
+    voxel stays within the documented bound: the terms' roundings (at most
+    2^(q-1) each, q = ilogb(max|y| 4 R r_out) + 1 - 62) plus one float
+    rounding of the result, and nothing overflows."""
+    w = W.tiny()
+    v = w.views
+    s, d = ora.cone_rays(v.pos, v.look, v.up, v.fov_deg, v.H, v.W)
+    P = _P()(w.grid, views=v, mode="onthefly")
+    tr = ora.trace(w.grid.arrays(), s, d)
+    R, V = len(tr["counts"]), w.grid.size
+    yy = np.random.default_rng(71).normal(size=R).astype(np.float32)
+    big = int(np.argmax(tr["counts"]))
+    yy[big] = np.float32(2.0 ** 60)
+    x = P.backproject(torch.from_numpy(yy).to(dev).reshape(1, *P.out_shape), "fixedpoint")
+    x = x.reshape(V).cpu().numpy().astype(np.float64)
+    xo = ora.adjoint(tr, yy[None].astype(np.float64), V)[0]
+    r_out = float(w.grid.arrays()[0][-1])
+    q = int(np.frexp(2.0 ** 60 * 4.0 * R * r_out)[1]) - 1 + 1 - 62  # ilogb(M) + 1 - 62
+    nterms = np.bincount(tr["vox"], minlength=V)
+    tol = nterms * 2.0 ** (q - 1) + 2.0 ** -24 * np.abs(xo) + TIGHT * _abs_adjoint(tr, yy.astype(np.float64), V)
+    assert np.all(np.isfinite(x))
+    assert np.all(np.abs(x - xo) <= tol)
+    # the big ray's voxels carry its terms to float precision
+    hit = np.unique(tr["vox"][tr["row_ptr"][big]:tr["row_ptr"][big + 1]])
+    assert np.all(np.abs(x[hit] - xo[hit]) <= 1e-6 * np.abs(xo[hit]))
