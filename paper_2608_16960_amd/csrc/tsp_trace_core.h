@@ -403,29 +403,23 @@ struct Walker {
             tm = t_a;
             fam = 2;
         }
-        bool emitted = false;
-        if (tm > tcur) {
-            const bool valid =
-                (ir >= 0) && (ir < nr) && (ie >= 0) && (ie < ne) && (ia >= 0) && (ia < na);
-            if (valid) {
-                const int v = (ir * ne + ie) * na + ia;
-                if (v == pv && !gap) {
-                    plen += tm - tcur;
-                } else {
-                    if (pv >= 0) {
-                        vout = pv;
-                        lout = plen;
-                        emitted = true;
-                    }
-                    pv = v;
-                    plen = tm - tcur;
-                }
-                gap = false;
-            } else {
-                gap = true;
-            }
-            tcur = tm;
-        }
+        // the piece [tcur, tm] joins the pending segment or completes it;
+        // written with selects rather than branches (every lane takes the
+        // same path, and the wavefront skips the mask bookkeeping)
+        const bool adv = tm > tcur;
+        const bool valid =
+            (ir >= 0) && (ir < nr) && (ie >= 0) && (ie < ne) && (ia >= 0) && (ia < na);
+        const int v = (ir * ne + ie) * na + ia;
+        const double d = tm - tcur;
+        const bool take = adv && valid;
+        const bool same = v == pv && !gap;
+        const bool emitted = take && !same && pv >= 0;
+        vout = pv;  // meaningful only when a segment is emitted
+        lout = plen;
+        plen = take ? (same ? plen + d : d) : plen;
+        pv = (take && !same) ? v : pv;
+        gap = adv ? !valid : gap;
+        tcur = adv ? tm : tcur;
         if (fam == 0) {
             if (rstage == 2) {
                 finished = true;
