@@ -295,10 +295,10 @@ __device__ __forceinline__ void merge_pairs(int &v, T *val, int lane) {
 // same voxel in the same event add their values in registers (pairs at lane
 // distance 1, 2, 4, 8 through DPP row shifts), which removes about half of
 // the LDS atomics and most of their same-address serialisation; a slot is
-// first looked up with a plain LDS read and claimed with a CAS only when
-// empty.  An insertion that finds no slot within kOtfProbes probes goes
-// straight to a global atomic, so a crowded table costs speed, never
-// correctness.
+// claimed (or found taken) by one compare-and-swap per probe, and the adds
+// follow the probe loop.  An insertion that finds no slot within kOtfProbes
+// probes goes straight to a global atomic, so a crowded table costs speed,
+// never correctness.
 constexpr int kOtfEvents = 16;
 constexpr int kOtfProbes = 8;
 // FIX: values are 64-bit fixed-point integers (the reproducible variant below)
@@ -410,29 +410,29 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
             merge_pairs<4, NB>(v, val, lane);
             merge_pairs<8, NB>(v, val, lane);
             bool claimed = false;
+            int hs = -1;  // the voxel's table slot, once found
             if (v >= 0) {
                 unsigned h = ((unsigned)v * 2654435761u) >> (32 - __builtin_ctz(HS));
-                bool done = false;
                 for (int p = 0; p < kOtfProbes; p++) {
-                    int key = __hip_atomic_load(hkey + h, __ATOMIC_RELAXED,
-                                                __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (key == -1) {
-                        key = atomicCAS(hkey + h, -1, v);
-                        claimed = key == -1;
-                    }
+                    // claim an empty slot, or learn whose it is
+                    const int key = atomicCAS(hkey + h, -1, v);
+                    claimed = key == -1;
                     if (key == -1 || key == v) {
-#pragma unroll
-                        for (int b = 0; b < NB; b++) lds_add(hval + b * HS + h, val[b]);
-                        done = true;
+                        hs = (int)h;
                         break;
                     }
                     h = (h + 1) & (HS - 1);
                 }
-                if (!done) {
+            }
+            // the adds after the probe loop: one set of LDS adds per
+            // wavefront step, whatever the lanes' probe counts
+            if (hs >= 0) {
 #pragma unroll
-                    for (int b = 0; b < NB; b++)
-                        if (b < nb) global_add(x_out, acc_out, (int64_t)v * NB + b, val[b]);
-                }
+                for (int b = 0; b < NB; b++) lds_add(hval + b * HS + hs, val[b]);
+            } else if (v >= 0) {
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    if (b < nb) global_add(x_out, acc_out, (int64_t)v * NB + b, val[b]);
             }
             // one add to the fill count per wavefront, not one per claim on a
             // single LDS word (every lane is active here)
