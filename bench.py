@@ -469,7 +469,7 @@ def extra_explicit_medium(reps=10):
             "adjoint_ms": a_ms, "rays_per_s": R / (f_ms + a_ms) * 1e3}
 
 
-def extra_learned(epochs=6):
+def extra_learned(epochs=12):
     import numpy as np
     import torch
 
