@@ -12,10 +12,13 @@ namespace tsp {
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kWindow = 256;  // ray slots per window: one 16x16 detector tile
 constexpr int kTile = 16;
-// Boundary tables (doubles) are staged in LDS next to at most kOtfHashBytes
-// of the on-the-fly adjoint's hash table, within 64 KiB per workgroup.
-constexpr int kOtfHashBytes = 20480;
-constexpr int kMaxTabDoubles = (65536 - kOtfHashBytes) / 8;
+// Boundary tables (doubles) are staged in LDS: at most kMaxTabDoubles, so
+// that they fit in 64 KiB per workgroup beside a 20 KiB hash table.  The
+// on-the-fly adjoint's hash table takes at most kOtfHashBytes, and its
+// launches ask for more than 64 KiB of LDS where a grid needs it (gfx950
+// has 160 KiB per compute unit).
+constexpr int kOtfHashBytes = 36864;
+constexpr int kMaxTabDoubles = (65536 - 20480) / 8;
 
 // Packed FP64 boundary tables, staged into LDS by every trace kernel.
 //   rb[nr+1]    radii

@@ -304,7 +304,7 @@ constexpr int kOtfProbes = 8;
 // FIX: values are 64-bit fixed-point integers (the reproducible variant below)
 template <int NB, bool FIX = false> struct OtfHash {
     using Val = typename std::conditional<FIX, long long, float>::type;
-    static constexpr int kSize = FIX ? (NB == 1 ? 1024 : 512) : (NB == 1 ? 2048 : 1024);  // power of two
+    static constexpr int kSize = FIX ? 1024 : (NB == 1 ? 2048 : 1024);  // power of two
     static constexpr size_t kBytes = (size_t)kSize * (4 + NB * sizeof(Val));
     static_assert(kBytes <= kOtfHashBytes, "hash table exceeds its LDS reserve");
 };
@@ -320,9 +320,9 @@ __device__ __forceinline__ int fix_exponent(unsigned ybits, double lsum) {
     return ilogb(fmax((double)__uint_as_float(ybits), 1e-30) * lsum) + 1 - 62;
 }
 
-// The batch-4 kernel allocates 96 VGPRs, five wavefronts per SIMD; one
-// fewer wavefront to hide the LDS atomics behind costs about 6%.  (Asking
-// for five with amdgpu_waves_per_eu now makes the compiler spill instead.)
+// The batch-4 kernel allocates 96 VGPRs, five wavefronts per SIMD, with the
+// measurements in LDS (99 and four wavefronts with them in registers, about
+// 3% slower; asking for five with amdgpu_waves_per_eu spills instead).
 __device__ __forceinline__ void lds_add(float *p, float v) { atomicAdd(p, v); }
 __device__ __forceinline__ void lds_add(long long *p, long long v) {
     atomicAdd(reinterpret_cast<unsigned long long *>(p), (unsigned long long)v);
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
                                                       const unsigned *ybits, double lsum) {
     using Val = typename OtfHash<NB, FIX>::Val;
     constexpr int HS = OtfHash<NB, FIX>::kSize;
-    extern __shared__ double lds[];  // grid tables, then the hash keys and values
+    extern __shared__ double lds[];  // grid tables, hash keys and values, measurements
     __shared__ int fill;
     stage_tables(D, tab, lds);
     const Tab T = make_tab(D, lds);
@@ -370,6 +370,12 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
         any |= (yv[b] != 0.0f);
         sc[b] = FIX ? ldexp(1.0, -fix_exponent(ybits[b < nb ? b : 0], lsum)) : 1.0;
     }
+    // the ray's measurements wait in LDS, read back at every event, rather
+    // than in registers: four fewer VGPRs hold the batch-4 kernel at 96,
+    // five wavefronts per SIMD instead of four
+    float *ysh = reinterpret_cast<float *>(hval + NB * HS) + threadIdx.x * NB;
+#pragma unroll
+    for (int b = 0; b < NB; b++) ysh[b] = yv[b];
     Walker w;
     bool alive = false;
     int32_t fb = 0;  // object frame of this ray, in voxels
@@ -401,9 +407,9 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
 #pragma unroll
             for (int b = 0; b < NB; b++) {
                 if (FIX)  // the product of two floats is exact in double
-                    val[b] = (Val)rint((double)lf * (double)yv[b] * sc[b]);
+                    val[b] = (Val)rint((double)lf * (double)ysh[b] * sc[b]);
                 else
-                    val[b] = (Val)(lf * yv[b]);
+                    val[b] = (Val)(lf * ysh[b]);
             }
             merge_pairs<1, NB>(v, val, lane);
             merge_pairs<2, NB>(v, val, lane);
@@ -569,11 +575,25 @@ hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc
     return vm ? hipFreeAsync(vm, st) : hipSuccess;
 }
 
+// LDS of one adjoint workgroup: the grid tables, the hash table and the
+// window's measurements.  Above 64 KiB (grids with large tables) a kernel
+// must be allowed the size first.
+template <int NB, bool FIX>
+hipError_t otf_adjoint_lds(const TabDesc &T, size_t *sh) {
+    *sh = (size_t)T.n_tab * sizeof(double) + OtfHash<NB, FIX>::kBytes +
+          (size_t)kWindow * NB * sizeof(float);
+    if (*sh <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void *)k_otf_adjoint<NB, FIX>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)*sh);
+}
+
 // x must be zero on entry for B == 1 (the caller clears it).
 hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc &rd,
                               const float *y, int B, int64_t vf, float *x, hipStream_t st) {
     const int64_t V = vf * rd.n_obj_frames;  // voxels of all object frames
-    const size_t sh = T.n_tab * sizeof(double) + (B == 1 ? OtfHash<1>::kBytes : OtfHash<4>::kBytes);
+    size_t sh = 0;
+    hipError_t e = B == 1 ? otf_adjoint_lds<1, false>(T, &sh) : otf_adjoint_lds<4, false>(T, &sh);
+    if (e != hipSuccess) return e;
     const dim3 grid(remapped_grid(rd.n_slots));
     if (B == 1) {
         hipLaunchKernelGGL((k_otf_adjoint<1, false>), grid, dim3(256), sh, st, T, tab, rd, y, 1, V,
@@ -581,7 +601,7 @@ hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc
         return hipGetLastError();
     }
     float *vm = nullptr;
-    hipError_t e = hipMallocAsync((void **)&vm, (size_t)V * 4 * sizeof(float), st);
+    e = hipMallocAsync((void **)&vm, (size_t)V * 4 * sizeof(float), st);
     if (e != hipSuccess) return e;
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
@@ -605,13 +625,14 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
     const int64_t V = vf * rd.n_obj_frames;
     const int NB = B == 1 ? 1 : 4;
     const double lsum = 2.0 * (double)rd.R * (2.0 * r_out);
-    const size_t sh = T.n_tab * sizeof(double) +
-                      (B == 1 ? OtfHash<1, true>::kBytes : OtfHash<4, true>::kBytes);
+    size_t sh = 0;
+    hipError_t e = B == 1 ? otf_adjoint_lds<1, true>(T, &sh) : otf_adjoint_lds<4, true>(T, &sh);
+    if (e != hipSuccess) return e;
     const dim3 grid(remapped_grid(rd.n_slots));
     // the sums, then four words of max |y|
     const int64_t words = V * NB + 2;
     unsigned long long *acc = nullptr;
-    hipError_t e = hipMallocAsync((void **)&acc, (size_t)words * 8, st);
+    e = hipMallocAsync((void **)&acc, (size_t)words * 8, st);
     if (e != hipSuccess) return e;
     unsigned *bits = reinterpret_cast<unsigned *>(acc + V * NB);
     for (int b0 = 0; b0 < B; b0 += 4) {

@@ -89,3 +89,49 @@ def test_one_ray(ora, dev):
                 np.add.at(tol, tr["vox"], np.abs(yy[b][seg]) * tr["len"])
                 assert np.all(np.abs(xg[b] - xo[b]) <= 1e-5 * tol + 1e-7), (mode, m, b)
     assert torch.equal(xs["onthefly", "deterministic"], xs["csr", "deterministic"])
+
+
+def _half_quantum(yb, R, r_out):
+    M = max(float(np.abs(np.float32(yb)).max()), 1e-30) * 4.0 * R * r_out
+    return 2.0 ** (int(np.frexp(M)[1]) - 1 + 1 - 62 - 1)
+
+
+def test_finest_boundary_tables(ora, dev):
+    """A grid at the boundary-table limit (nr + ne + 3 na = 5620 of 5627,
+    45 KB of FP64 tables): the on-the-fly adjoints' workgroups then need
+    more than 64 KiB of LDS, which their launches request.  600 explicit
+    rays, on the fly: forward, atomic and fixed-point adjoints at batch 1
+    and 4 against the oracle, at the static bars (1e-5 of the absolute
+    integrand + 1e-7; fixed point 2e-7 of it plus one float rounding plus
+    half a quantum per term, 2^(q-1) with q = ilogb(max|y| 4 R r_out) + 1 - 62)."""
+    g = W.uniform_grid((20, 20, 1860), r=(1.0, 5.0))
+    s, d = W.random_rays(600, np.random.default_rng(52), r_start=(8.0, 12.0), aim=3.0)
+    tr = ora.trace(g.arrays(), s, d)
+    R, V = len(s), g.size
+    assert tr["counts"].sum() > 50_000
+    seg = np.repeat(np.arange(R), tr["counts"])
+    nterms = np.bincount(tr["vox"], minlength=V)
+    P = _P()(g, rays=(s, d), mode="onthefly")
+    rng = np.random.default_rng(53)
+    for B in (1, 4):
+        rho = rng.uniform(0, 1, (B, V)).astype(np.float32)
+        yo = ora.forward(tr, rho.astype(np.float64))
+        y = P.forward(torch.from_numpy(rho).reshape(B, *g.shape).to(dev))
+        y = y.reshape(B, R).cpu().numpy().astype(np.float64)
+        for b in range(B):
+            tol = np.zeros(R)
+            np.add.at(tol, seg, np.abs(rho[b][tr["vox"]]) * tr["len"])
+            assert np.all(np.abs(y[b] - yo[b]) <= 1e-5 * tol + 1e-7), (B, b)
+        yy = rng.normal(size=(B, R)).astype(np.float32)
+        xo = ora.adjoint(tr, yy.astype(np.float64), V)
+        y_t = torch.from_numpy(yy).to(dev)
+        for m in ("atomic", "fixedpoint"):
+            xg = P.backproject(y_t, m).reshape(B, V).cpu().numpy().astype(np.float64)
+            for b in range(B):
+                absx = np.zeros(V)
+                np.add.at(absx, tr["vox"], np.abs(yy[b][seg]) * tr["len"])
+                tol = (1e-5 * absx + 1e-7 if m == "atomic"
+                       else 2e-7 * absx + 2.0 ** -24 * np.abs(xo[b]) + 1e-30
+                       + nterms * _half_quantum(yy[b], R, float(g.r_b[-1])))
+                assert np.all(np.abs(xg[b] - xo[b]) <= tol), (B, m, b)
+    P.close()

@@ -7,10 +7,12 @@ bitwise repeatable and every object of a batch equals its adjoint alone bit
 for bit, whichever kernel variant (batch 1 or batches of 4) ran it.  Bars
 against the oracle (FP64 lists of the same rays): each voxel within 2e-7 of
 the oracle's sum of |y| len, plus one float rounding of the voxel's value
-(2^-24 |x|): the kernels' lengths are FP32, so a term carries up to 2^-24 of
-relative error, and nothing else is rounded before the final conversion
-(the 2^(q-1) rounding of each term is below 1e-18 of the bound).  That is
-50 times tighter than the float-sum adjoints' 1e-5.
+(2^-24 |x|), plus half a quantum 2^(q-1) per term: the kernels' lengths are
+FP32, so a term carries up to 2^-24 of relative error, each term is rounded
+to a multiple of 2^q (q = ilogb(max|y| 4 R r_out) + 1 - 62, below 1e-18 of
+the largest possible voxel sum, but not of a voxel that only a few short
+segments reach), and nothing else is rounded before the final conversion.
+That is 50 times tighter than the float-sum adjoints' 1e-5.
 """
 import numpy as np
 import pytest
@@ -43,6 +45,13 @@ def _abs_adjoint(tr, y, V):
     return out
 
 
+def half_quantum(yb, R, r_out):
+    """2^(q-1), the largest rounding of one term: q = ilogb(M) + 1 - 62 with
+    M = max|y| (as float) 4 R r_out."""
+    M = max(float(np.abs(np.float32(yb)).max()), 1e-30) * 4.0 * R * r_out
+    return 2.0 ** (int(np.frexp(M)[1]) - 1 + 1 - 62 - 1)
+
+
 def _check(ora, grid, P, s, d, B, seed):
     tr = ora.trace(grid.arrays(), s, d)
     R, V = len(tr["counts"]), grid.size
@@ -54,8 +63,10 @@ def _check(ora, grid, P, s, d, B, seed):
         assert torch.equal(x[b:b + 1], P.backproject(y_t[b:b + 1], "fixedpoint")), b
     xo = ora.adjoint(tr, yy.astype(np.float64), V)
     xg = x.reshape(B, V).cpu().numpy().astype(np.float64)
+    nterms = np.bincount(tr["vox"], minlength=V)
     for b in range(B):
-        tol = TIGHT * _abs_adjoint(tr, yy[b].astype(np.float64), V) + 2.0 ** -24 * np.abs(xo[b])
+        tol = (TIGHT * _abs_adjoint(tr, yy[b].astype(np.float64), V) + 2.0 ** -24 * np.abs(xo[b])
+               + nterms * half_quantum(yy[b], R, float(grid.r_b[-1])))
         err = np.abs(xg[b] - xo[b])
         assert np.all(err <= tol + 1e-30), f"b={b}: worst voxel {np.argmax(err - tol)}"
 
@@ -100,8 +111,11 @@ def test_frames_and_mixed_views(ora, dev):
     assert torch.equal(x, P.backproject(y_t, "fixedpoint"))
     x = x.reshape(2, F, V).cpu().numpy().astype(np.float64)
     xo = D.adjoint_frames(tr, yy.astype(np.float64), fr, F, V)
+    seg_fr = np.repeat(fr, tr["counts"])
+    nterms = np.bincount(seg_fr * V + tr["vox"], minlength=F * V).reshape(F, V)
     for b in range(2):
-        tol = TIGHT * D.adjoint_frames(tr, np.abs(yy[b]).astype(np.float64), fr, F, V)
+        tol = (TIGHT * D.adjoint_frames(tr, np.abs(yy[b]).astype(np.float64), fr, F, V)
+               + nterms * half_quantum(yy[b], len(fr), float(w.grid.r_b[-1])))
         assert np.all(np.abs(x[b] - xo[b]) <= tol + 2.0 ** -24 * np.abs(xo[b]) + 1e-30), b
 
 
