@@ -22,16 +22,14 @@
 // atomic adjoint.  The chain rule through w and tau_1 (F_1^T) and the
 // elementwise combination run as separate small kernels.
 //
-// Deterministic backward: the merged contributions are added as exact
-// fixed-point integers instead of floats.  Each value v becomes the signed
-// integer round-toward-zero(v / 2^qe), a 96-bit magnitude held in three
-// 32-bit limbs, and each limb goes into its own 64-bit accumulator of the
-// voxel with an integer atomic add.  Integer addition is exact and
-// associative, so the sums (and the float each voxel finally gets) do not
-// depend on the order in which the atomics land: bitwise reproducible.  qe
-// comes from a bound M on any merged value, M < 2^95 2^qe, so no limb sum
-// can overflow for fewer than 2^31 contributions per voxel; values below
-// 2^qe (about 2^-95 M) are truncated.
+// Deterministic backward: the merged contributions are added as fixed-point
+// integers instead of floats.  Each merged value v is rounded to an integer
+// multiple of 2^qe and added to the voxel's signed 64-bit accumulator with
+// one integer atomic add.  Integer addition is exact and associative, so the
+// sums (and the float each voxel finally gets) do not depend on the order in
+// which the atomics land: bitwise reproducible.  qe comes from a bound on
+// every voxel's sum of |terms| (fixed_exponent), which keeps every partial
+// sum below 2^62 quanta; each value's rounding is at most 2^(qe-1).
 
 #include "tsp_internal.h"
 
