@@ -179,26 +179,27 @@ __global__ void k_tv_value(const float *part, int nblk, int B, float *value) {
 
 __global__ void k_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float b1,
                        float b2, float eps, float wd, float c1, float c2, uint16_t *pb) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i] + wd * p[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    p[i] = pi;
-    if (pb) pb[i] = f2bf(pi);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i] + wd * p[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] = pi;
+        if (pb) pb[i] = f2bf(pi);
+    }
 }
 
 __global__ void k_to_bf16(const float *x, uint16_t *y, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f2bf(x[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) y[i] = f2bf(x[i]);
 }
 
 __global__ void k_from_bf16(const uint16_t *x, float *y, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = bf2f(x[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) y[i] = bf2f(x[i]);
 }
 
 // ---------------------------------------------------------------- edge layers (VALU)
@@ -882,6 +883,13 @@ __global__ void k_flip(const uint16_t *w, uint16_t *wt) {
 }
 
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+// Elementwise kernels over caller-sized arrays stride over their items and
+// take at most 2^23 workgroups of 256: one dispatch holds fewer than 2^32
+// work-items.
+inline unsigned nblk_strided(int64_t n) {
+    const int64_t b = (n + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > ((int64_t)1 << 23) ? ((int64_t)1 << 23) : b));
+}
 
 // ------------------------------------------------ per-object vector kernels
 //
@@ -926,15 +934,14 @@ __global__ void k_store_masked(const float *sums, const int32_t *active, int B, 
 // x[o][i] += alpha * a[o][i] for active o
 __global__ void k_axpy(float *x, const float *a, float alpha, int64_t n, int64_t total,
                        const int32_t *active) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    if (active && !active[i / n]) return;
-    x[i] = fmaf(alpha, a[i], x[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (!active || active[i / n]) x[i] = fmaf(alpha, a[i], x[i]);
 }
 
 __global__ void k_scale(const float *src, float alpha, int64_t n, float *dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = alpha * src[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) dst[i] = alpha * src[i];
 }
 
 
@@ -1070,8 +1077,8 @@ tspnn_status tspnn_adam(float *p, const float *g, float *m, float *v, int64_t n,
         return fail(TSPNN_E_INVALID, "tspnn_adam: bad arguments");
     if (n == 0) return TSPNN_OK;
     const float c1 = 1.0f - powf(beta1, (float)step), c2 = 1.0f - powf(beta2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, n,
-                       lr, beta1, beta2, eps, weight_decay, c1, c2, p_bf16);
+    hipLaunchKernelGGL(k_adam, dim3(nblk_strided(n)), dim3(256), 0, (hipStream_t)stream, p, g, m,
+                       v, n, lr, beta1, beta2, eps, weight_decay, c1, c2, p_bf16);
     return hipret(hipGetLastError(), "tspnn_adam");
 }
 
@@ -1079,7 +1086,8 @@ tspnn_status tspnn_to_bf16(const float *x, uint16_t *y, int64_t n, void *stream)
     g_err.clear();
     if (!x || !y || n < 0) return fail(TSPNN_E_INVALID, "tspnn_to_bf16: bad arguments");
     if (n == 0) return TSPNN_OK;
-    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y, n);
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk_strided(n)), dim3(256), 0, (hipStream_t)stream, x, y,
+                       n);
     return hipret(hipGetLastError(), "tspnn_to_bf16");
 }
 
@@ -1087,7 +1095,7 @@ tspnn_status tspnn_from_bf16(const uint16_t *x, float *y, int64_t n, void *strea
     g_err.clear();
     if (!x || !y || n < 0) return fail(TSPNN_E_INVALID, "tspnn_from_bf16: bad arguments");
     if (n == 0) return TSPNN_OK;
-    hipLaunchKernelGGL(k_from_bf16, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, x, y,
+    hipLaunchKernelGGL(k_from_bf16, dim3(nblk_strided(n)), dim3(256), 0, (hipStream_t)stream, x, y,
                        n);
     return hipret(hipGetLastError(), "tspnn_from_bf16");
 }
@@ -1307,7 +1315,7 @@ tspnn_status tspnn_axpy(float *x, const float *a, float alpha, int32_t B, int64_
     g_err.clear();
     if (!x || !a || B < 1 || n < 1) return fail(TSPNN_E_INVALID, "tspnn_axpy: bad arguments");
     const int64_t total = (int64_t)B * n;
-    hipLaunchKernelGGL(k_axpy, dim3(nblk(total, 256)), dim3(256), 0, (hipStream_t)stream, x, a,
+    hipLaunchKernelGGL(k_axpy, dim3(nblk_strided(total)), dim3(256), 0, (hipStream_t)stream, x, a,
                        alpha, n, total, active);
     return hipret(hipGetLastError(), "tspnn_axpy");
 }
@@ -1315,8 +1323,8 @@ tspnn_status tspnn_axpy(float *x, const float *a, float alpha, int32_t B, int64_
 tspnn_status tspnn_scale(const float *src, float alpha, int64_t n, float *dst, void *stream) {
     g_err.clear();
     if (!src || !dst || n < 1) return fail(TSPNN_E_INVALID, "tspnn_scale: bad arguments");
-    hipLaunchKernelGGL(k_scale, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, src, alpha,
-                       n, dst);
+    hipLaunchKernelGGL(k_scale, dim3(nblk_strided(n)), dim3(256), 0, (hipStream_t)stream, src,
+                       alpha, n, dst);
     return hipret(hipGetLastError(), "tspnn_scale");
 }
 

@@ -227,37 +227,41 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
     const int64_t bx = blockIdx.x, q = bx / 8;
     const int64_t lb = (bx < full) ? ((q / kChunk) * 8 + bx % 8) * kChunk + q % kChunk : bx;
     // the key is uniform over the wavefront: keep it (and the list bounds,
-    // the loop and the running slot) in scalar registers
-    const int64_t key = lb * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    // the loop and the running slot) in scalar registers.  A wavefront takes
+    // more than one key only when the grid is capped (more than 2^25 keys).
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    if (key >= FV) return;
-    const int64_t base = col_base[key];
-    const int nrow = (int)((col_base[key + 1] - base) >> 6);
-    const int64_t f = key / V;
-    const int64_t v = f * V + store_voxel(key - f * V, nr, ne, na);
-    const uint8_t *cp = code + base + lane;
-    const float *lp = len + base + lane;
-    const uint32_t smax = (uint32_t)(n_slots - 1);
-    float acc[NB];
+    for (int64_t kb = lb; kb * 4 < FV; kb += nbk) {
+        const int64_t key = kb * 4 + wv;
+        if (key >= FV) break;
+        const int64_t base = col_base[key];
+        const int nrow = (int)((col_base[key + 1] - base) >> 6);
+        const int64_t f = key / V;
+        const int64_t v = f * V + store_voxel(key - f * V, nr, ne, na);
+        const uint8_t *cp = code + base + lane;
+        const float *lp = len + base + lane;
+        const uint32_t smax = (uint32_t)(n_slots - 1);
+        float acc[NB];
 #pragma unroll
-    for (int b = 0; b < NB; b++) acc[b] = 0.0f;
-    uint32_t run = 0;
-    int r = 0;
-    for (; r + UNR <= nrow; r += UNR)
-        adj_rows<NB, UNR>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt, run,
-                          acc);
-    for (; r < nrow; r++)
-        adj_rows<NB, 1>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt, run,
-                        acc);
+        for (int b = 0; b < NB; b++) acc[b] = 0.0f;
+        uint32_t run = 0;
+        int r = 0;
+        for (; r + UNR <= nrow; r += UNR)
+            adj_rows<NB, UNR>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt,
+                              run, acc);
+        for (; r < nrow; r++)
+            adj_rows<NB, 1>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt,
+                            run, acc);
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
+        for (int b = 0; b < NB; b++) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) acc[b] += __shfl_xor(acc[b], o, kWave);
-    }
-    if (lane == 0) {
+            for (int o = 32; o > 0; o >>= 1) acc[b] += __shfl_xor(acc[b], o, kWave);
+        }
+        if (lane == 0) {
 #pragma unroll
-        for (int b = 0; b < NB; b++)
-            if (b < nb) x[b * FV + v] = acc[b];
+            for (int b = 0; b < NB; b++)
+                if (b < nb) x[b * FV + v] = acc[b];
+        }
     }
 }
 
@@ -330,13 +334,13 @@ __global__ __launch_bounds__(256) void k_adj_atomic(const int32_t *__restrict__ 
 }
 
 __global__ void k_zero(float *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
 
 __global__ void k_copy_i64(const int64_t *s, int64_t *d, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) d[i] = s[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
 inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
@@ -405,7 +409,7 @@ static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_base, cons
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     hipLaunchKernelGGL(k_tile_y<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, y,
                        nb, (T *)yt);
-    hipLaunchKernelGGL(k_adj_csc<NB>, dim3(blocks_for(FV * kWave, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_adj_csc<NB>, dim3(strided_blocks(FV * kWave)), dim3(256), 0, st,
                        col_base, code, len, nr, ne, na, rd.n_obj_frames, rd.n_slots,
                        (const T *)yt, nb, x);
     return hipGetLastError();
@@ -474,13 +478,13 @@ hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
 
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    hipLaunchKernelGGL(k_zero, dim3(strided_blocks(n)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_i64(const int64_t *src, int64_t *dst, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_i64, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, dst, n);
+    hipLaunchKernelGGL(k_copy_i64, dim3(strided_blocks(n)), dim3(256), 0, st, src, dst, n);
     return hipGetLastError();
 }
 

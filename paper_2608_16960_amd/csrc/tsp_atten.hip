@@ -42,28 +42,29 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // s[b][v] = sigma[v] * rho[b][v]
 __global__ void k_atten_s(const float *sigma, const float *rho, int64_t V, int64_t n, float *s) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) s[i] = sigma[i % V] * rho[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) s[i] = sigma[i % V] * rho[i];
 }
 
 // w = exp(-tau1) * rho
 __global__ void k_atten_w(const float *tau1, const float *rho, int64_t n, float *w) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) w[i] = expf(-tau1[i]) * rho[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) w[i] = expf(-tau1[i]) * rho[i];
 }
 
 // out = -w * gw  (gradient reaching tau_1)
 __global__ void k_atten_gtau(const float *w, const float *gw, int64_t n, float *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = -w[i] * gw[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) out[i] = -w[i] * gw[i];
 }
 
 // grad = exp(-tau1) * gw + sigma * (gs + gs_sun)
 __global__ void k_atten_grad(const float *tau1, const float *sigma, const float *gw,
                              const float *gs, const float *gs_sun, int64_t V, int64_t n,
                              float *grad) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) grad[i] = expf(-tau1[i]) * gw[i] + sigma[i % V] * (gs[i] + gs_sun[i]);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        grad[i] = expf(-tau1[i]) * gw[i] + sigma[i % V] * (gs[i] + gs_sun[i]);
 }
 
 // One lane per ray slot of the ray-major store (see tsp_apply.hip for the
@@ -270,20 +271,20 @@ hipError_t launch_absmax(const float *a, int64_t n, unsigned *out, hipStream_t s
 hipError_t launch_atten_s(const float *sigma, const float *rho, int64_t V, int B, float *s,
                           hipStream_t st) {
     const int64_t n = V * B;
-    hipLaunchKernelGGL(k_atten_s, dim3(blocks_for(n, 256)), dim3(256), 0, st, sigma, rho, V, n,
+    hipLaunchKernelGGL(k_atten_s, dim3(strided_blocks(n)), dim3(256), 0, st, sigma, rho, V, n,
                        s);
     return hipGetLastError();
 }
 
 hipError_t launch_atten_w(const float *tau1, const float *rho, int64_t n, float *w,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_atten_w, dim3(blocks_for(n, 256)), dim3(256), 0, st, tau1, rho, n, w);
+    hipLaunchKernelGGL(k_atten_w, dim3(strided_blocks(n)), dim3(256), 0, st, tau1, rho, n, w);
     return hipGetLastError();
 }
 
 hipError_t launch_atten_gtau(const float *w, const float *gw, int64_t n, float *out,
                              hipStream_t st) {
-    hipLaunchKernelGGL(k_atten_gtau, dim3(blocks_for(n, 256)), dim3(256), 0, st, w, gw, n, out);
+    hipLaunchKernelGGL(k_atten_gtau, dim3(strided_blocks(n)), dim3(256), 0, st, w, gw, n, out);
     return hipGetLastError();
 }
 
@@ -291,7 +292,7 @@ hipError_t launch_atten_grad(const float *tau1, const float *sigma, const float 
                              const float *gs, const float *gs_sun, int64_t V, int B, float *grad,
                              hipStream_t st) {
     const int64_t n = V * B;
-    hipLaunchKernelGGL(k_atten_grad, dim3(blocks_for(n, 256)), dim3(256), 0, st, tau1, sigma, gw,
+    hipLaunchKernelGGL(k_atten_grad, dim3(strided_blocks(n)), dim3(256), 0, st, tau1, sigma, gw,
                        gs, gs_sun, V, n, grad);
     return hipGetLastError();
 }

@@ -12,6 +12,17 @@ namespace tsp {
 constexpr int kWave = 64;     // CDNA wavefront
 constexpr int kWindow = 256;  // ray slots per window: one 16x16 detector tile
 constexpr int kTile = 16;
+// One dispatch holds fewer than 2^32 work-items, and near the 2^31-voxel
+// limit some launches have more items than that (four objects voxel-major,
+// 64 lanes per voxel).  Those kernels take at most kMaxBlocks workgroups of
+// 256 (2^31 work-items) and stride over the rest; smaller launches are
+// unchanged.
+constexpr int64_t kMaxBlocks = (int64_t)1 << 23;
+inline unsigned strided_blocks(int64_t items) {
+    const int64_t b = (items + 255) / 256;
+    return (unsigned)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
+}
+
 // Boundary tables (doubles) are staged in LDS: at most kMaxTabDoubles, so
 // that they fit in 64 KiB per workgroup beside a 20 KiB hash table.  The
 // on-the-fly adjoint's hash table takes at most kOtfHashBytes, and its

@@ -366,76 +366,77 @@ __device__ __forceinline__ bool needs_escape(int64_t i, int64_t lo, uint32_t slo
 // Rows of 64 entries that each key's packed list takes (escapes included).
 __global__ __launch_bounds__(256) void k_pack_count(const int64_t *col_ptr, const uint64_t *ent,
                                                      int64_t nkeys, int32_t *rows) {
-    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (key >= nkeys) return;  // uniform over the wavefront
-    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
-    int64_t n = 0;
-    for (int64_t i = lo + lane; i < hi; i += kWave) {
-        const uint32_t slot = (uint32_t)ent[i];
-        const uint32_t prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
-        n += needs_escape(i, lo, slot, prev) ? 2 : 1;
-    }
+    // one key per wavefront; more only when the grid is capped
+    for (int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; key < nkeys;
+         key += (int64_t)gridDim.x * 4) {
+        const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+        int64_t n = 0;
+        for (int64_t i = lo + lane; i < hi; i += kWave) {
+            const uint32_t slot = (uint32_t)ent[i];
+            const uint32_t prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
+            n += needs_escape(i, lo, slot, prev) ? 2 : 1;
+        }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, kWave);
-    if (lane == 0) rows[key] = (int32_t)((n + kWave - 1) / kWave);
+        for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, kWave);
+        if (lane == 0) rows[key] = (int32_t)((n + kWave - 1) / kWave);
+    }
 }
-
-// The packed list of each key at base[key] ... base[key + 1], padded with
-// code 0, length 0.  Entries are taken 64 at a time; an entry's position is
-// its index plus the escapes written up to it (ballot and popcount).
 __global__ __launch_bounds__(256) void k_pack_fill(const int64_t *col_ptr, const uint64_t *ent,
                                                     int64_t nkeys, const int64_t *base,
                                                     uint8_t *code, float *len) {
-    const int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (key >= nkeys) return;  // uniform over the wavefront
-    const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
-    const int64_t p0 = base[key], p1 = base[key + 1];
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t written = 0;
-    for (int64_t c = lo; c < hi; c += kWave) {  // uniform over the wavefront
-        const int64_t i = c + lane;
-        const bool valid = i < hi;
-        uint32_t slot = 0, prev = 0;
-        float l = 0.0f;
-        if (valid) {
-            const uint64_t e = ent[i];
-            slot = (uint32_t)e;
-            l = __uint_as_float((uint32_t)(e >> 32));
-            prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
+    // one key per wavefront; more only when the grid is capped
+    for (int64_t key = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6; key < nkeys;
+         key += (int64_t)gridDim.x * 4) {
+        const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
+        const int64_t p0 = base[key], p1 = base[key + 1];
+        int64_t written = 0;
+        for (int64_t c = lo; c < hi; c += kWave) {  // uniform over the wavefront
+            const int64_t i = c + lane;
+            const bool valid = i < hi;
+            uint32_t slot = 0, prev = 0;
+            float l = 0.0f;
+            if (valid) {
+                const uint64_t e = ent[i];
+                slot = (uint32_t)e;
+                l = __uint_as_float((uint32_t)(e >> 32));
+                prev = (i > lo) ? (uint32_t)ent[i - 1] : 0u;
+            }
+            const bool esc = valid && needs_escape(i, lo, slot, prev);
+            const uint64_t eb = __ballot(esc);
+            const int64_t p = p0 + written + lane + __popcll(eb & below) + (esc ? 1 : 0);
+            if (esc) {
+                code[p - 1] = (uint8_t)kSlotEsc;
+                len[p - 1] = __uint_as_float(slot - prev);
+            }
+            if (valid) {
+                code[p] = esc ? (uint8_t)0 : (uint8_t)(slot - prev);
+                len[p] = l;
+            }
+            written += __popcll(__ballot(valid)) + __popcll(eb);
         }
-        const bool esc = valid && needs_escape(i, lo, slot, prev);
-        const uint64_t eb = __ballot(esc);
-        const int64_t p = p0 + written + lane + __popcll(eb & below) + (esc ? 1 : 0);
-        if (esc) {
-            code[p - 1] = (uint8_t)kSlotEsc;
-            len[p - 1] = __uint_as_float(slot - prev);
+        for (int64_t q = p0 + written + lane; q < p1; q += kWave) {
+            code[q] = 0;
+            len[q] = 0.0f;
         }
-        if (valid) {
-            code[p] = esc ? (uint8_t)0 : (uint8_t)(slot - prev);
-            len[p] = l;
-        }
-        written += __popcll(__ballot(valid)) + __popcll(eb);
-    }
-    for (int64_t q = p0 + written + lane; q < p1; q += kWave) {
-        code[q] = 0;
-        len[q] = 0.0f;
     }
 }
 
 // x += a
 __global__ void k_add(const float *a, float *x, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] += a[i];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) x[i] += a[i];
 }
 
 // dst[b][i] = src[b * stride + i], i < n, b < B
 __global__ void k_copy_rows(const float *src, int64_t stride, float *dst, int64_t n, int B) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n * B) return;
-    const int64_t b = i / n, k = i - b * n;
-    dst[i] = src[b * stride + k];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * B;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = i / n, k = i - b * n;
+        dst[i] = src[b * stride + k];
+    }
 }
 
 // ------------------------------------------------------------ radix sort
@@ -746,7 +747,7 @@ hipError_t launch_col_ptr_range(const int32_t *sorted_keys, int64_t n, int64_t k
 hipError_t launch_pack_count(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
                              int32_t *m, hipStream_t st) {
     if (nkeys <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_count, dim3(blocks_for(nkeys * kWave, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_pack_count, dim3(strided_blocks(nkeys * kWave)), dim3(256), 0, st,
                        col_ptr, ent, nkeys, m);
     return hipGetLastError();
 }
@@ -754,21 +755,21 @@ hipError_t launch_pack_count(const int64_t *col_ptr, const uint64_t *ent, int64_
 hipError_t launch_pack_fill(const int64_t *col_ptr, const uint64_t *ent, int64_t nkeys,
                             const int64_t *base, uint8_t *code, float *len, hipStream_t st) {
     if (nkeys <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_fill, dim3(blocks_for(nkeys * kWave, 256)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_pack_fill, dim3(strided_blocks(nkeys * kWave)), dim3(256), 0, st,
                        col_ptr, ent, nkeys, base, code, len);
     return hipGetLastError();
 }
 
 hipError_t launch_add_f32(const float *a, float *x, int64_t n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, x, n);
+    hipLaunchKernelGGL(k_add, dim3(strided_blocks(n)), dim3(256), 0, st, a, x, n);
     return hipGetLastError();
 }
 
 hipError_t launch_copy_rows(const float *src, int64_t stride, float *dst, int64_t n, int B,
                             hipStream_t st) {
     if (n <= 0 || B <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_rows, dim3(blocks_for(n * B, 256)), dim3(256), 0, st, src, stride,
+    hipLaunchKernelGGL(k_copy_rows, dim3(strided_blocks(n * B)), dim3(256), 0, st, src, stride,
                        dst, n, B);
     return hipGetLastError();
 }

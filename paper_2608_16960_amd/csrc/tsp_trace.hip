@@ -467,20 +467,21 @@ __global__ __launch_bounds__(256) void k_otf_adjoint(TabDesc D, const double *ta
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) p[i] = 0ull;
 }
 
 // x[b][v] = the fixed-point sum acc[v * NB + b] times 2^q_b, rounded to float
 // (through double); b < nb.
 __global__ void k_fix_to_float(const unsigned long long *acc, int NB, int nb, int64_t V,
                                const unsigned *ybits, double lsum, float *x) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)nb * V) return;
-    const int b = (int)(i / V);
-    const int64_t v = i - (int64_t)b * V;
-    const long long a = (long long)acc[v * NB + b];
-    x[i] = (float)ldexp((double)a, fix_exponent(ybits[b], lsum));
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)nb * V;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i / V);
+        const int64_t v = i - (int64_t)b * V;
+        const long long a = (long long)acc[v * NB + b];
+        x[i] = (float)ldexp((double)a, fix_exponent(ybits[b], lsum));
+    }
 }
 
 __global__ void k_rays(RayDesc rd, double *starts, double *dirs) {
@@ -523,23 +524,25 @@ hipError_t launch_fill(const TabDesc &T, const double *tab, const RayDesc &rd,
 
 // [B][V] <-> voxel-major [V][4] for batch chunks of up to 4 objects
 __global__ void k_to_vmajor(const float *src, int nb, int64_t V, float *dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V * 4) return;
-    const int b = (int)(i & 3);
-    dst[i] = (b < nb) ? src[(int64_t)b * V + (i >> 2)] : 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V * 4;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int b = (int)(i & 3);
+        dst[i] = (b < nb) ? src[(int64_t)b * V + (i >> 2)] : 0.0f;
+    }
 }
 
 __global__ void k_from_vmajor(const float *src, int nb, int64_t V, float *dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V * nb) return;
-    const int64_t v = i % V;
-    const int b = (int)(i / V);
-    dst[i] = src[v * 4 + b];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < V * nb;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = i % V;
+        const int b = (int)(i / V);
+        dst[i] = src[v * 4 + b];
+    }
 }
 
 __global__ void k_zero4(float *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.0f;
 }
 
 inline unsigned remapped_grid(int64_t n_slots) {  // windows, padded to a multiple of 8
@@ -564,7 +567,7 @@ hipError_t launch_otf_forward(const TabDesc &T, const double *tab, const RayDesc
         if (B == 1) {
             hipLaunchKernelGGL(k_otf_forward<1>, grid, dim3(256), sh, st, T, tab, rd, r, nb, V, yy);
         } else {
-            hipLaunchKernelGGL(k_to_vmajor, dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st,
+            hipLaunchKernelGGL(k_to_vmajor, dim3(strided_blocks(4 * V)), dim3(256), 0, st,
                                r, nb, V, vm);
             hipLaunchKernelGGL(k_otf_forward<4>, grid, dim3(256), sh, st, T, tab, rd, vm, nb, V,
                                yy);
@@ -607,11 +610,11 @@ hipError_t launch_otf_adjoint(const TabDesc &T, const double *tab, const RayDesc
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
         float *xx = x + (int64_t)b0 * V;
-        hipLaunchKernelGGL(k_zero4, dim3((unsigned)((4 * V + 255) / 256)), dim3(256), 0, st, vm,
+        hipLaunchKernelGGL(k_zero4, dim3(strided_blocks(4 * V)), dim3(256), 0, st, vm,
                            4 * V);
         hipLaunchKernelGGL((k_otf_adjoint<4, false>), grid, dim3(256), sh, st, T, tab, rd, yy, nb,
                            V, vm, (unsigned long long *)nullptr, (const unsigned *)nullptr, 0.0);
-        hipLaunchKernelGGL(k_from_vmajor, dim3((unsigned)((nb * V + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_from_vmajor, dim3(strided_blocks(nb * V)), dim3(256), 0, st,
                            vm, nb, V, xx);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -638,7 +641,7 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
     for (int b0 = 0; b0 < B; b0 += 4) {
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
-        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_zero_u64, dim3(strided_blocks(words)), dim3(256), 0, st,
                            acc, words);
         for (int b = 0; b < nb; b++) {
             e = launch_absmax(yy + (int64_t)b * rd.R, rd.R, bits + b, st);
@@ -651,7 +654,7 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
         else
             hipLaunchKernelGGL((k_otf_adjoint<4, true>), grid, dim3(256), sh, st, T, tab, rd, yy, nb,
                                V, (float *)nullptr, acc, bits, lsum);
-        hipLaunchKernelGGL(k_fix_to_float, dim3((unsigned)((nb * V + 255) / 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_fix_to_float, dim3(strided_blocks(nb * V)), dim3(256), 0, st,
                            acc, NB, nb, V, bits, lsum, x + (int64_t)b0 * V);
         e = hipGetLastError();
         if (e != hipSuccess) break;
@@ -662,7 +665,7 @@ hipError_t launch_otf_adjoint_fixed(const TabDesc &T, const double *tab, const R
 
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t st) {
     if (n > 0)
-        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+        hipLaunchKernelGGL(k_zero_u64, dim3(strided_blocks(n)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -135,3 +135,57 @@ def test_finest_boundary_tables(ora, dev):
                        + nterms * _half_quantum(yy[b], R, float(g.r_b[-1])))
                 assert np.all(np.abs(xg[b] - xo[b]) <= tol), (B, m, b)
     P.close()
+
+
+def test_four_objects_past_2p32_elements(ora, dev):
+    """1500 x 1500 x 500 voxels (1.125e9): four objects voxel-major hold
+    4.5e9 floats and the fixed-point sums 4.5e9 words, more than one dispatch
+    has work-items, so the staging, clearing and conversion kernels stride
+    over capped grids.  300 explicit rays on the fly, batch 4: forward,
+    atomic and fixed-point adjoints against the oracle at the static bars,
+    on the traced voxels (the oracle runs on the voxels the rays reach,
+    renumbered), and every other voxel exactly 0.  With 1500 shells and 1500
+    cones many segments are very short, so the fixed-point bar also carries
+    each length's FP64 root error, at the walker's length bars (1e-10 r_max,
+    1e-7 r_max on rays the oracle marks length-sensitive) times |y|."""
+    g = W.uniform_grid((1500, 1500, 500), r=(1.0, 5.0))
+    V, B = g.size, 4
+    assert 4 * V > 2 ** 32
+    s, d = W.random_rays(300, np.random.default_rng(54), r_start=(8.0, 12.0), aim=3.0)
+    tr = ora.trace(g.arrays(), s, d)
+    R = len(s)
+    uv, inv = np.unique(tr["vox"], return_inverse=True)
+    trc = dict(tr, vox=inv.astype(np.int32))  # the same lists on the reached voxels only
+    seg = np.repeat(np.arange(R), tr["counts"])
+    P = _P()(g, rays=(s, d), mode="onthefly")
+    gen = torch.Generator(device=dev).manual_seed(55)
+    rho = torch.rand((B, *g.shape), device=dev, generator=gen)
+    idx = torch.from_numpy(uv.astype(np.int64)).to(dev)
+    rho_c = rho.reshape(B, V)[:, idx].cpu().numpy().astype(np.float64)
+    y = P.forward(rho).reshape(B, R).cpu().numpy().astype(np.float64)
+    yo = ora.forward(trc, rho_c)
+    for b in range(B):
+        tol = np.zeros(R)
+        np.add.at(tol, seg, np.abs(rho_c[b][inv]) * tr["len"])
+        assert np.all(np.abs(y[b] - yo[b]) <= 1e-5 * tol + 1e-7), b
+    del rho
+    yy = np.random.default_rng(56).normal(size=(B, R)).astype(np.float32)
+    xo = ora.adjoint(trc, yy.astype(np.float64), len(uv))
+    nterms = np.bincount(inv, minlength=len(uv))
+    dl = np.where(tr["sensitive"][seg], 1e-7, 1e-10) * float(g.r_b[-1])
+    for m in ("atomic", "fixedpoint"):
+        x = P.backproject(torch.from_numpy(yy).to(dev), m).reshape(B, V)
+        assert int(torch.count_nonzero(x)) <= B * len(uv), m
+        xg = x[:, idx].cpu().numpy().astype(np.float64)
+        del x
+        for b in range(B):
+            absx, lerr = np.zeros(len(uv)), np.zeros(len(uv))
+            np.add.at(absx, inv, np.abs(yy[b][seg]) * tr["len"])
+            np.add.at(lerr, inv, np.abs(yy[b][seg]) * dl)
+            tol = (1e-5 * absx + 1e-7 if m == "atomic"
+                   else 2e-7 * absx + 2.0 ** -24 * np.abs(xo[b]) + lerr + 1e-30
+                   + nterms * _half_quantum(yy[b], R, float(g.r_b[-1])))
+            err = np.abs(xg[b] - xo[b])
+            k = int(np.argmax(err - tol))
+            assert np.all(err <= tol), (m, b, k, xg[b][k], xo[b][k], absx[k], lerr[k], nterms[k])
+    P.close()
