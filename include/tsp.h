@@ -56,6 +56,13 @@
  *   Every call returns a tsp_status; no C++ exception crosses the ABI.  On
  *   failure tsp_last_error() returns a message for the calling thread.
  *   Arguments are validated on the host before any launch.
+ *
+ * Launch grids
+ *   One dispatch holds fewer than 2^32 work-items.  Kernels whose items can
+ *   outnumber that near the size limits (4 V staged values, 64 lanes per
+ *   voxel, B V elements) stride over grids of at most 2^23 workgroups; the
+ *   environment variable TSP_MAX_BLOCKS (read once per process) lowers that
+ *   cap, for tests of the striding.
  */
 #ifndef TSP_H
 #define TSP_H

@@ -31,6 +31,10 @@
  * every call returns TSPNN_OK or an error code, with a message from
  * tspnn_last_error().  Reductions (weight and bias gradients, TV value) sum
  * per-block partials in a fixed order: results are bitwise reproducible.
+ * The elementwise calls (Adam, bfloat16 conversions, axpy, scale) take
+ * arrays of any length: they stride over grids of at most 2^23 workgroups
+ * (one dispatch holds fewer than 2^32 work-items), a cap that the
+ * environment variable TSP_MAX_BLOCKS lowers for tests.
  */
 #ifndef TSPNN_H
 #define TSPNN_H

@@ -21,6 +21,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <string>
 
 #include "tspnn.h"
@@ -884,11 +885,17 @@ __global__ void k_flip(const uint16_t *w, uint16_t *wt) {
 
 inline unsigned nblk(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 // Elementwise kernels over caller-sized arrays stride over their items and
-// take at most 2^23 workgroups of 256: one dispatch holds fewer than 2^32
-// work-items.
+// take at most 2^23 workgroups of 256 (one dispatch holds fewer than 2^32
+// work-items), or fewer from the environment variable TSP_MAX_BLOCKS (read
+// once per process), so that tests can make the striding run at small sizes.
 inline unsigned nblk_strided(int64_t n) {
+    static const int64_t cap = [] {
+        const char *s = std::getenv("TSP_MAX_BLOCKS");
+        const long long v = s ? std::atoll(s) : 0;
+        return (v > 0 && v < ((int64_t)1 << 23)) ? (int64_t)v : ((int64_t)1 << 23);
+    }();
     const int64_t b = (n + 255) / 256;
-    return (unsigned)(b < 1 ? 1 : (b > ((int64_t)1 << 23) ? ((int64_t)1 << 23) : b));
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 // ------------------------------------------------ per-object vector kernels

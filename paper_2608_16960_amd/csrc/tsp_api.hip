@@ -65,6 +65,15 @@ int64_t device_cap() {
 
 }  // namespace
 
+int64_t tsp::max_blocks() {
+    static const int64_t cap = [] {
+        const char *s = std::getenv("TSP_MAX_BLOCKS");
+        const long long v = s ? std::atoll(s) : 0;
+        return (v > 0 && v < kMaxBlocks) ? (int64_t)v : kMaxBlocks;
+    }();
+    return cap;
+}
+
 struct tsp_geometry {
     int device = 0;
     TabDesc T{};

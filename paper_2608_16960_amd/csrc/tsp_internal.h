@@ -16,11 +16,14 @@ constexpr int kTile = 16;
 // limit some launches have more items than that (four objects voxel-major,
 // 64 lanes per voxel).  Those kernels take at most kMaxBlocks workgroups of
 // 256 (2^31 work-items) and stride over the rest; smaller launches are
-// unchanged.
+// unchanged.  max_blocks() is kMaxBlocks, or a smaller cap from the
+// environment variable TSP_MAX_BLOCKS (read once per process), so that
+// tests can make the striding run at small sizes.
 constexpr int64_t kMaxBlocks = (int64_t)1 << 23;
+int64_t max_blocks();
 inline unsigned strided_blocks(int64_t items) {
-    const int64_t b = (items + 255) / 256;
-    return (unsigned)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
+    const int64_t b = (items + 255) / 256, cap = max_blocks();
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 // Boundary tables (doubles) are staged in LDS: at most kMaxTabDoubles, so
