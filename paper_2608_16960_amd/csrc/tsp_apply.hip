@@ -164,20 +164,13 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
     return x;
 }
 
-// N rows of a packed voxel-major list (lane l: entry l of each row) into
-// the lane sums; `run` is the slot before the first row.
+// N rows of a packed voxel-major list (lane l: entry l of each row, its
+// code and length loaded) into the lane sums; `run` is the slot before the
+// first row.
 template <int NB, int N>
-__device__ __forceinline__ void adj_rows(const uint8_t *__restrict__ cp,
-                                         const float *__restrict__ lp, int lane, uint32_t smax,
-                                         const typename YVec<NB>::T *__restrict__ yt,
-                                         uint32_t &run, float *acc) {
-    int cd[N];
-    float l[N];
-#pragma unroll
-    for (int u = 0; u < N; u++) {
-        cd[u] = __builtin_nontemporal_load(cp + u * kWave);
-        l[u] = __builtin_nontemporal_load(lp + u * kWave);
-    }
+__device__ __forceinline__ void adj_sum(const int *cd, const float *l, uint32_t smax,
+                                        const typename YVec<NB>::T *__restrict__ yt,
+                                        uint32_t &run, float *acc) {
     uint32_t sl[N];
 #pragma unroll
     for (int u = 0; u < N; u++)
@@ -201,12 +194,48 @@ __device__ __forceinline__ void adj_rows(const uint8_t *__restrict__ cp,
     }
 }
 
+// G groups of four interleaved rows: lane l's codes of the group's rows in
+// one 4-byte word and its lengths in one 16-byte load (cg, lg: the group's
+// first entry).
+template <int NB, int G>
+__device__ __forceinline__ void adj_groups(const uint8_t *__restrict__ cg,
+                                           const float *__restrict__ lg, int lane, uint32_t smax,
+                                           const typename YVec<NB>::T *__restrict__ yt,
+                                           uint32_t &run, float *acc) {
+    int cd[4 * G];
+    float l[4 * G];
+#pragma unroll
+    for (int g = 0; g < G; g++) {
+        const uint32_t w =
+            __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(cg + g * 4 * kWave) + lane);
+        const v4f v = ld_nt(reinterpret_cast<const v4f *>(lg + g * 4 * kWave) + lane);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            cd[4 * g + k] = (int)((w >> (8 * k)) & 255u);
+            l[4 * g + k] = v[k];
+        }
+    }
+    adj_sum<NB, 4 * G>(cd, l, smax, yt, run, acc);
+}
+
+// One row of the row-major tail (cp, lp: lane l's entry of the row).
+template <int NB>
+__device__ __forceinline__ void adj_row(const uint8_t *__restrict__ cp, const float *__restrict__ lp,
+                                        uint32_t smax, const typename YVec<NB>::T *__restrict__ yt,
+                                        uint32_t &run, float *acc) {
+    const int cd = __builtin_nontemporal_load(cp);
+    const float l = __builtin_nontemporal_load(lp);
+    adj_sum<NB, 1>(&cd, &l, smax, yt, run, acc);
+}
+
 // Keys run over object frames, then voxels in store-key order; x is
 // [nf][V] per object (nf = 1 for a static object).  One wavefront per key
 // takes the key's packed list a row of 64 entries at a time (lane l entry
 // l), eight rows in flight: each lane's slot is the running slot before the
 // row plus the prefix sum of the row's increases (escapes carry theirs in
-// the length slot).  A fixed butterfly adds the 64 lane sums, so the order
+// the length slot).  The rows sit in groups of four, interleaved so that a
+// lane's four codes are one 4-byte word and its four lengths 16 contiguous
+// bytes; rows past the last whole group stay row-major.  A fixed butterfly adds the 64 lane sums, so the order
 // never depends on timing: x is bitwise reproducible.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col_base,
@@ -238,20 +267,24 @@ __global__ __launch_bounds__(256) void k_adj_csc(const int64_t *__restrict__ col
         const int nrow = (int)((col_base[key + 1] - base) >> 6);
         const int64_t f = key / V;
         const int64_t v = f * V + store_voxel(key - f * V, nr, ne, na);
-        const uint8_t *cp = code + base + lane;
-        const float *lp = len + base + lane;
+        const uint8_t *cb = code + base;
+        const float *lb = len + base;
         const uint32_t smax = (uint32_t)(n_slots - 1);
         float acc[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) acc[b] = 0.0f;
         uint32_t run = 0;
+        const int nrow4 = nrow & ~3;  // rows in interleaved groups of four
         int r = 0;
-        for (; r + UNR <= nrow; r += UNR)
-            adj_rows<NB, UNR>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt,
+        for (; r + UNR <= nrow4; r += UNR)
+            adj_groups<NB, UNR / 4>(cb + (int64_t)r * kWave, lb + (int64_t)r * kWave, lane, smax,
+                                    yt, run, acc);
+        for (; r < nrow4; r += 4)
+            adj_groups<NB, 1>(cb + (int64_t)r * kWave, lb + (int64_t)r * kWave, lane, smax, yt,
                               run, acc);
         for (; r < nrow; r++)
-            adj_rows<NB, 1>(cp + (int64_t)r * kWave, lp + (int64_t)r * kWave, lane, smax, yt,
-                            run, acc);
+            adj_row<NB>(cb + (int64_t)r * kWave + lane, lb + (int64_t)r * kWave + lane, smax, yt,
+                        run, acc);
 #pragma unroll
         for (int b = 0; b < NB; b++) {
 #pragma unroll

@@ -392,6 +392,13 @@ __global__ __launch_bounds__(256) void k_pack_fill(const int64_t *col_ptr, const
          key += (int64_t)gridDim.x * 4) {
         const int64_t lo = col_ptr[key], hi = col_ptr[key + 1];
         const int64_t p0 = base[key], p1 = base[key + 1];
+        // entry q of the list (row q / 64, lane q % 64) is stored at p0 +
+        // at(q): rows in groups of four interleaved (lane l's four entries
+        // of a group contiguous), rows past the last whole group row-major
+        const int64_t nq4 = ((p1 - p0) >> 8) << 8;
+        auto at = [nq4](int64_t q) {
+            return q < nq4 ? (q & ~(int64_t)255) + ((q & 63) << 2) + ((q >> 6) & 3) : q;
+        };
         int64_t written = 0;
         for (int64_t c = lo; c < hi; c += kWave) {  // uniform over the wavefront
             const int64_t i = c + lane;
@@ -408,18 +415,20 @@ __global__ __launch_bounds__(256) void k_pack_fill(const int64_t *col_ptr, const
             const uint64_t eb = __ballot(esc);
             const int64_t p = p0 + written + lane + __popcll(eb & below) + (esc ? 1 : 0);
             if (esc) {
-                code[p - 1] = (uint8_t)kSlotEsc;
-                len[p - 1] = __uint_as_float(slot - prev);
+                const int64_t pe = p0 + at(p - 1 - p0);
+                code[pe] = (uint8_t)kSlotEsc;
+                len[pe] = __uint_as_float(slot - prev);
             }
             if (valid) {
-                code[p] = esc ? (uint8_t)0 : (uint8_t)(slot - prev);
-                len[p] = l;
+                const int64_t pv = p0 + at(p - p0);
+                code[pv] = esc ? (uint8_t)0 : (uint8_t)(slot - prev);
+                len[pv] = l;
             }
             written += __popcll(__ballot(valid)) + __popcll(eb);
         }
-        for (int64_t q = p0 + written + lane; q < p1; q += kWave) {
-            code[q] = 0;
-            len[q] = 0.0f;
+        for (int64_t q = written + lane; q < p1 - p0; q += kWave) {
+            code[p0 + at(q)] = 0;
+            len[p0 + at(q)] = 0.0f;
         }
     }
 }
