@@ -169,11 +169,20 @@ __host__ __device__ __forceinline__ int step_code(int32_t dv, int na, int nena) 
     return kCodeEsc;
 }
 // One decoding step: updates the running voxel v, returns the segment length
-// the entry carries (0 for an escape or padding).
+// the entry carries (0 for an escape or padding).  The same deltas as
+// step_delta, written as a chain of selects so that the decoder stays one
+// branch-free run of instructions per entry (the compiler otherwise turns
+// the range tests into branches around the gathers).
 __device__ __forceinline__ float decode_entry(int c, float l, int32_t &v, int na, int nena) {
     const bool esc = c == kCodeEsc;
-    v = esc ? __float_as_int(l) : v + step_delta(c, na, nena);
-    return esc ? 0.0f : l;
+    int32_t mag = c >= 3 ? na : 1;
+    mag = c >= 5 ? nena : mag;
+    mag = c >= 7 ? na - 1 : mag;
+    mag = (c == 0 || esc) ? 0 : mag;
+    const int32_t delta = (c & 1) ? mag : -mag;
+    const int32_t m = -(int32_t)esc;  // all ones for an escape
+    v = (__float_as_int(l) & m) | ((v + delta) & ~m);
+    return __int_as_float(__float_as_int(l) & ~m);
 }
 
 // Voxel-major store entries: a float32 length and a one-byte code.  Each
