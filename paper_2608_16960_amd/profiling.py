@@ -32,10 +32,10 @@ COPY_KIB = 1 << 20  # the calibration copy moves 1 GiB each way
 
 
 def source_sha(kernel):
-    """SHA-1 of the kernel's source file (and, for the tracing kernels, of the
-    shared tracer header)."""
+    """SHA-1 of the kernel's source file and the shared internal header (and,
+    for the tracing kernels, of the tracer header)."""
     h = hashlib.sha1()
-    paths = [KERNEL_SOURCES[kernel]]
+    paths = [KERNEL_SOURCES[kernel], "csrc/tsp_internal.h"]
     if "otf" in kernel:
         paths.append("csrc/tsp_trace_core.h")
     for p in paths:
