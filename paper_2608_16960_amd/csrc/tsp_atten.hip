@@ -95,12 +95,12 @@ __global__ __launch_bounds__(256) void k_fwd_atten(const int32_t *__restrict__ p
         const uint32_t cw = __builtin_nontemporal_load(cp + (int64_t)q * kWave);
         const v4f lq = __builtin_nontemporal_load(lp + (int64_t)q * kWave);
         const float la[4] = {lq[0], lq[1], lq[2], lq[3]};
+        // escapes and the padding past the ray's last entry carry length 0,
+        // which leaves T and the sum as they are: no branch per entry
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            if (4 * q + e >= c) break;
             const int cd = (cw >> (8 * e)) & 255;
             const float l = decode_entry(cd, la[e], v, na, nena);
-            if (cd == kCodeEsc) continue;
             T = fmaf(s[v], l, T);
             acc = fmaf(w[v] * expf(-T), l, acc);
         }
@@ -186,11 +186,9 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
         const v4f lq = lp[(int64_t)q * kWave];
         const float la[4] = {lq[0], lq[1], lq[2], lq[3]};
 #pragma unroll
-        for (int e = 0; e < 4; e++) {
-            if (4 * q + e >= c) break;
+        for (int e = 0; e < 4; e++) {  // escapes and padding: length 0, no change
             const int cd = (cw >> (8 * e)) & 255;
             const float l = decode_entry(cd, la[e], vr, na, nena);
-            if (cd == kCodeEsc) continue;
             T = fmaf(s[vr], l, T);
             yr = fmaf(w[vr] * expf(-T), l, yr);
         }
