@@ -202,21 +202,17 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
         const v4f lq = lp[(int64_t)q * kWave];
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-            int v = -1;
-            float a = 0.0f, bterm = 0.0f, l = 0.0f;
-            if (4 * q + e < c) {
-                const int cd = (cw >> (8 * e)) & 255;
-                l = decode_entry(cd, lq[e], vr, na, nena);
-                if (cd != kCodeEsc) v = vr;
-            }
-            if (v >= 0) {
-                T = fmaf(s[v], l, T);
-                const float E = expf(-T);
-                const float ck = w[v] * E * l;
-                a = g * E * l;
-                bterm = -g * l * (yr - prefix);
-                prefix += ck;
-            }
+            // escapes and padding carry length 0: T, the prefix and both
+            // terms stay as they are, with no branch per entry
+            const int cd = (cw >> (8 * e)) & 255;
+            const float l = decode_entry(cd, lq[e], vr, na, nena);
+            const int v = (4 * q + e < c && cd != kCodeEsc) ? vr : -1;
+            T = fmaf(s[vr], l, T);
+            const float E = expf(-T);
+            const float ck = w[vr] * E * l;
+            const float a = g * E * l;
+            const float bterm = -g * l * (yr - prefix);
+            prefix += ck;
             uint64_t pend = __ballot(v >= 0);
             // uniform over the wavefront: every lane is active.  The merged
             // sums stay with their leader lanes (mv, ma, mb); the fixed-point
