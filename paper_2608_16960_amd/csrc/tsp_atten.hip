@@ -152,6 +152,64 @@ __global__ void k_fixed_to_float(const unsigned long long *acc, int64_t V,
     x[i] = (float)ldexp((double)(long long)acc[i], fixed_exponent(bits, two_r, nrays));
 }
 
+// One step of the backward's scatter: the lanes of a wavefront that hold
+// the same voxel add their two terms in LDS and one lane per voxel adds the
+// sums to the voxel's gradients.  Each active lane writes its lane id into a
+// slot of a per-wavefront table chosen by a hash of its voxel, then reads the
+// slot back: the lane found there (the last writer) owns the voxel when it
+// holds the same voxel, and the lanes of the voxel add into the owner's pair
+// of accumulators; a lane whose slot went to another voxel adds directly.
+// The owners then take their sums (and reset them) and add them globally.
+// LDS operations of one wavefront execute in order, so each phase sees the
+// previous one; the fences keep the compiler from reordering the phases.
+// FIXED: terms are rounded to multiples of 2^qe one by one and summed as
+// 64-bit integers (order-independent); else float LDS adds and atomics.
+constexpr int kMergeSlots = 256;
+template <bool FIXED, class Acc>
+__device__ __forceinline__ void merge_step(int v, float a, float bterm, int lane, int *tb,
+                                           Acc *sa, Acc *sb, float *gw, float *gs,
+                                           unsigned long long *acc, int64_t V, int qe) {
+    const bool act = v >= 0;
+    const int h = (int)(((unsigned)v * 2654435761u) >> 24);  // 8 bits: kMergeSlots
+    if (act) __hip_atomic_store(tb + h, lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int owner = act ? __hip_atomic_load(tb + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)
+                          : lane;
+    const int ov = __shfl(v, owner, kWave);
+    Acc ta, tbv;
+    if (FIXED) {
+        ta = (Acc)(long long)rint(ldexp((double)a, -qe));
+        tbv = (Acc)(long long)rint(ldexp((double)bterm, -qe));
+    } else {
+        ta = (Acc)a;
+        tbv = (Acc)bterm;
+    }
+    if (act && ov == v) {
+        atomicAdd(sa + owner, ta);
+        atomicAdd(sb + owner, tbv);
+    } else if (act) {  // the slot went to another voxel
+        if (FIXED) {
+            if (ta) atomicAdd(acc + v, (unsigned long long)ta);
+            if (tbv) atomicAdd(acc + V + v, (unsigned long long)tbv);
+        } else {
+            atomicAdd(gw + v, (float)ta);
+            atomicAdd(gs + v, (float)tbv);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (act && owner == lane) {
+        const Acc xa = atomicExch(sa + lane, (Acc)0), xb = atomicExch(sb + lane, (Acc)0);
+        if (FIXED) {
+            if (xa) atomicAdd(acc + v, (unsigned long long)xa);
+            if (xb) atomicAdd(acc + V + v, (unsigned long long)xb);
+        } else {
+            atomicAdd(gw + v, (float)xa);
+            atomicAdd(gs + v, (float)xb);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
 template <bool FIXED>
 __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ perm,
                                                     const int32_t *__restrict__ cnt_sorted,
@@ -176,6 +234,15 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
     const int m = slice_len[slot >> 6];
     const int64_t base = slice_ptr[slot >> 6];
     const float g = (ray >= 0) ? gy[ray] : 0.0f;
+    // per wavefront: the voxel table and one pair of accumulators per lane
+    using Acc = typename std::conditional<FIXED, unsigned long long, float>::type;
+    __shared__ int tbl[4][kMergeSlots];
+    __shared__ Acc accs[4][2][kWave];
+    const int wv = threadIdx.x >> 6;
+    int *tb = tbl[wv];
+    Acc *sa = accs[wv][0], *sb = accs[wv][1];
+    sa[lane] = (Acc)0;
+    sb[lane] = (Acc)0;
     // pass 1: the ray's measurement (the total that the suffix sums start from)
     const uint32_t *cp = (const uint32_t *)(code + base) + lane;
     const v4f *lp = (const v4f *)(len + base) + lane;
@@ -213,43 +280,29 @@ __global__ __launch_bounds__(256) void k_bwd_atten(const int32_t *__restrict__ p
             const float a = g * E * l;
             const float bterm = -g * l * (yr - prefix);
             prefix += ck;
-            uint64_t pend = __ballot(v >= 0);
-            // uniform over the wavefront: every lane is active.  The merged
-            // sums stay with their leader lanes (mv, ma, mb); the fixed-point
-            // path then converts and adds them on all those lanes at once.
-            int mv = -1;
-            float ma = 0.0f, mb = 0.0f;
-            for (int it = 0; pend && it < kMaxMerges; it++) {
-                const int leader = __ffsll((unsigned long long)pend) - 1;
-                const int v0 = __builtin_amdgcn_readlane(v, leader);
-                const bool mine = (v == v0);
-                const float sa = wave_sum_f32(mine ? a : 0.0f);
-                const float sb = wave_sum_f32(mine ? bterm : 0.0f);
-                if (lane == leader) {
-                    if (FIXED) {
-                        mv = v0;
-                        ma = sa;
-                        mb = sb;
-                    } else {
-                        atomicAdd(gw + v0, sa);
-                        atomicAdd(gs + v0, sb);
+            if (FIXED) {
+                merge_step<FIXED>(v, a, bterm, lane, tb, sa, sb, gw, gs, acc, V, qe);
+            } else {
+                // the float path merges by leaders (one wavefront sum per
+                // distinct voxel, at most kMaxMerges): float LDS adds under
+                // the table merge ran 3.7 ms against 2.6 ms at Medium
+                uint64_t pend = __ballot(v >= 0);  // uniform: every lane is active
+                for (int it = 0; pend && it < kMaxMerges; it++) {
+                    const int leader = __ffsll((unsigned long long)pend) - 1;
+                    const int v0 = __builtin_amdgcn_readlane(v, leader);
+                    const bool mine = (v == v0);
+                    const float sa0 = wave_sum_f32(mine ? a : 0.0f);
+                    const float sb0 = wave_sum_f32(mine ? bterm : 0.0f);
+                    if (lane == leader) {
+                        atomicAdd(gw + v0, sa0);
+                        atomicAdd(gs + v0, sb0);
                     }
+                    pend &= ~__ballot(mine);
                 }
-                pend &= ~__ballot(mine);
-            }
-            if ((pend >> lane) & 1ull) {  // past the merge limit
-                if (FIXED) {
-                    mv = v;
-                    ma = a;
-                    mb = bterm;
-                } else {
+                if ((pend >> lane) & 1ull) {  // past the merge limit
                     atomicAdd(gw + v, a);
                     atomicAdd(gs + v, bterm);
                 }
-            }
-            if (FIXED && mv >= 0) {
-                fixed_add(acc, mv, ma, qe);
-                fixed_add(acc + V, mv, mb, qe);
             }
         }
     }
