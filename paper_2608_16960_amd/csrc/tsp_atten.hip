@@ -22,14 +22,15 @@
 // atomic adjoint.  The chain rule through w and tau_1 (F_1^T) and the
 // elementwise combination run as separate small kernels.
 //
-// Deterministic backward: the merged contributions are added as fixed-point
-// integers instead of floats.  Each merged value v is rounded to an integer
-// multiple of 2^qe and added to the voxel's signed 64-bit accumulator with
-// one integer atomic add.  Integer addition is exact and associative, so the
-// sums (and the float each voxel finally gets) do not depend on the order in
-// which the atomics land: bitwise reproducible.  qe comes from a bound on
-// every voxel's sum of |terms| (fixed_exponent), which keeps every partial
-// sum below 2^62 quanta; each value's rounding is at most 2^(qe-1).
+// Deterministic backward: the contributions are added as fixed-point
+// integers instead of floats.  Each term is rounded to an integer multiple
+// of 2^qe; the terms of a step's lanes that share a voxel are summed in LDS
+// (merge_step) and the sum goes to the voxel's signed 64-bit accumulator
+// with one integer atomic add.  Integer addition is exact and associative,
+// so the sums (and the float each voxel finally gets) do not depend on the
+// order in which the adds land: bitwise reproducible.  qe comes from a bound
+// on every voxel's sum of |terms| (fixed_exponent), which keeps every
+// partial sum below 2^62 quanta; each term's rounding is at most 2^(qe-1).
 
 #include "tsp_internal.h"
 
