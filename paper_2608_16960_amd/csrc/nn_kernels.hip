@@ -517,6 +517,21 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
             for (int u = 0; u < KP; u++) load_el(i + 2, u, pv[u], pok[u]);
         }
         if (j < d.D1) {  // uniform per wave
+            const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2 + a0 + m;
+            typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+            // input gradient: the ReLU mask of this step's outputs, loaded
+            // before the taps so that it arrives while the MFMAs run
+            u16x4 mkv[NT][2];
+            if (EPI == 1) {
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+#pragma unroll
+                    for (int u = 0; u < 2; u++)
+                        mkv[t][u] = (a0 + 16 * t < d.D2)
+                                        ? *reinterpret_cast<const u16x4 *>(
+                                              mask + (ob + 16 * t) * C + 16 * u + 4 * kq)
+                                        : u16x4{0, 0, 0, 0};
+            }
             f32x4 acc[NT][2];
 #pragma unroll
             for (int t = 0; t < NT; t++)
@@ -553,7 +568,6 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
                     acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b1[cur], av[cur][t], acc[t][1], 0, 0, 0);
                 }
             }
-            const int64_t ob = (((int64_t)n * d.D0 + i) * d.D1 + j) * d.D2 + a0 + m;
 #pragma unroll
             for (int t = 0; t < NT; t++) {
                 if (a0 + 16 * t >= d.D2) break;  // uniform
@@ -561,9 +575,6 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
                 for (int u = 0; u < 2; u++) {
                     const int o = 16 * u + 4 * kq;
                     const int64_t p = (ob + 16 * t) * C + o;
-                    typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
-                    u16x4 mk;
-                    if (EPI == 1) mk = *reinterpret_cast<const u16x4 *>(mask + p);
                     u16x4 out;
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
@@ -571,7 +582,7 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
                         if (EPI == 0) {
                             v = fmaxf(v + bias[o + e], 0.0f);
                         } else {
-                            v = bf2f(mk[e]) > 0.0f ? v : 0.0f;
+                            v = bf2f(mkv[t][u][e]) > 0.0f ? v : 0.0f;
                         }
                         out[e] = f2bf(v);
                     }
