@@ -502,6 +502,13 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
             bf16x8, __builtin_amdgcn_raw_buffer_load_b128(wr, wlo + half * 16 * C * 2,
                                                           tap * C * C * 2, 0));
     };
+    // forward: this lane's eight biases (output channels 16 u + 4 kq .. + 3),
+    // loaded once for the whole walk
+    float bv[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; u++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) bv[u][e] = EPI == 0 ? bias[16 * u + 4 * kq + e] : 0.0f;
     for (int i = i0; i < i1; i++) {
         if (i > i0) {
             __syncthreads();  // the previous step's reads are done
@@ -580,7 +587,7 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
                     for (int e = 0; e < 4; e++) {
                         float v = acc[t][u][e];
                         if (EPI == 0) {
-                            v = fmaxf(v + bias[o + e], 0.0f);
+                            v = fmaxf(v + bv[u][e], 0.0f);
                         } else {
                             v = bf2f(mkv[t][u][e]) > 0.0f ? v : 0.0f;
                         }
