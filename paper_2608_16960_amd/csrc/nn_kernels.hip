@@ -509,6 +509,13 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
     for (int u = 0; u < 2; u++)
 #pragma unroll
         for (int e = 0; e < 4; e++) bv[u][e] = EPI == 0 ? bias[16 * u + 4 * kq + e] : 0.0f;
+    // input gradient: tap 0's weight fragments, the same at every step, held
+    // for the walk (about 4% faster; the forward ran no faster with them)
+    bf16x8 w00 = {}, w01 = {};
+    if (EPI == 1) {
+        w00 = ldw(0, 0);
+        w01 = ldw(0, 1);
+    }
     for (int i = i0; i < i1; i++) {
         if (i > i0) {
             __syncthreads();  // the previous step's reads are done
@@ -516,8 +523,8 @@ __device__ __forceinline__ void conv_walk(const uint16_t *__restrict__ x, const 
             for (int u = 0; u < KP; u++) store_el(i + 1, u, pv[u], pok[u]);
         }
         bf16x8 b0[2], b1[2];
-        b0[0] = ldw(0, 0);
-        b1[0] = ldw(0, 1);
+        b0[0] = EPI == 1 ? w00 : ldw(0, 0);
+        b1[0] = EPI == 1 ? w01 : ldw(0, 1);
         __syncthreads();
         if (i + 1 < i1) {  // slice i + 2, for the next step
 #pragma unroll
