@@ -192,6 +192,9 @@ __device__ __forceinline__ float decode_entry(int c, float l, int32_t &v, int na
 // nothing.  Every list opens with an escape (increase from slot 0) and is
 // padded to whole rows of 64 entries with code 0, length 0; a wavefront takes
 // a row at a time, lane l entry l, and rebuilds the slots by a prefix sum.
+// In memory the rows sit in groups of four, interleaved (lane l's entries of
+// a group adjacent: one 4-byte code word and one 16-byte length load per
+// lane and group); rows past the last whole group stay row-major.
 constexpr int kSlotEsc = 255;
 constexpr int kSlotMaxStep = 254;
 
