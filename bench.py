@@ -511,7 +511,7 @@ def extra_learned(epochs=12):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+        print(f"bench.py measures one GPU only (asked for --gpus {a.gpus}); "
               "the projector shards by views across GPUs by design but no multi-GPU path "
               "is built.", file=sys.stderr)
         sys.exit(2)

@@ -2,7 +2,7 @@
 
 A small 3-D CNN on the (r, e, a) grid (nn.CNN) maps a few-iteration plain
 gradient-descent reconstruction x_in to a starting point for the same plain
-gradient descent.  The plain solve stays the judge: the CNN output is used
+gradient descent.  The plain solve stays the arbiter: the CNN output is used
 only if its data residual ||y - F rho||^2 is below that of x_in (fallback),
 and the solve then runs until it reaches the residual R* that plain GD
 reaches after K iterations from zero.  Every projector call is counted,
