@@ -515,6 +515,10 @@ def main():
               "the projector shards by views across GPUs by design but no multi-GPU path "
               "is built.", file=sys.stderr)
         sys.exit(2)
+    if a.steps < 2 and not a.large_only:
+        print("bench.py needs --steps 2 or more: alternate steps time the forward's and the "
+              "adjoint's kernels", file=sys.stderr)
+        sys.exit(2)
     import numpy as np
     import torch
 
@@ -547,34 +551,45 @@ def main():
     for _ in range(a.warmup):
         step()
     K = a.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+    # The library records a pair of HIP events just before and just after a
+    # call's main kernel, on the call's stream (tsp_set_timing_events): even
+    # steps time the forward's kernel, odd steps the adjoint's, so each step
+    # carries two event records (each adds a few microseconds between
+    # launches).  The events are created by a first record before the timed
+    # region.
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(K)]
+    for e in ev:
+        for t in e:
+            t.record()
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(K):
-        e0, e1, e2 = ev[k]
-        e0.record()
+        s0, s1 = ev[k]
+        if k % 2 == 0:
+            P.set_timing_events(s0, s1)
         P.forward(rho, out=y)
-        e1.record()
+        if k % 2 == 1:
+            P.set_timing_events(s0, s1)
         P.backproject(y, "deterministic", out=x)
-        e2.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    fwd_t = sorted(e[0].elapsed_time(e[1]) for e in ev)
-    adj_t = sorted(e[1].elapsed_time(e[2]) for e in ev)
-    fwd_ms, adj_ms = sum(fwd_t) / K, sum(adj_t) / K
+    fwd_t = sorted(ev[k][0].elapsed_time(ev[k][1]) for k in range(0, K, 2))
+    adj_t = sorted(ev[k][0].elapsed_time(ev[k][1]) for k in range(1, K, 2))
+    fwd_ms, adj_ms = sum(fwd_t) / len(fwd_t), sum(adj_t) / len(adj_t)
     ms_step = wall / K * 1e3
-
     # algorithmic bytes per launch (4-byte index + 4-byte length per segment,
     # 8 bytes of row / column bookkeeping, object and measurements once)
     fwd_bytes = 8 * S + 8 * R + 4 * B * R + 4 * B * V
     adj_bytes = 8 * S + 8 * V + 4 * B * V + 4 * B * R
+    # the kernels' own mean durations (the adjoint's call also runs
+    # k_tile_y<1>, the slot-ordered copy of y, which its time leaves out)
     kern = {
         "forward": {"kernel": "k_fwd_sell<1>", "ms": fwd_ms, "min_ms": fwd_t[0],
-                    "median_ms": fwd_t[K // 2], "bytes": fwd_bytes,
-                    "GBps": fwd_bytes / fwd_ms / 1e6},
+                    "median_ms": fwd_t[len(fwd_t) // 2], "launches_timed": len(fwd_t),
+                    "bytes": fwd_bytes, "GBps": fwd_bytes / fwd_ms / 1e6},
         "adjoint": {"kernel": "k_adj_csc<1>", "ms": adj_ms, "min_ms": adj_t[0],
-                    "median_ms": adj_t[K // 2], "bytes": adj_bytes,
-                    "GBps": adj_bytes / adj_ms / 1e6},
+                    "median_ms": adj_t[len(adj_t) // 2], "launches_timed": len(adj_t),
+                    "bytes": adj_bytes, "GBps": adj_bytes / adj_ms / 1e6},
     }
     # the measured alternative: the atomic adjoint from the ray-major store
     # (outside the timed step; its sums depend on the order atomics land in)
@@ -612,8 +627,9 @@ def main():
         "segments_per_s": S / (ms_step / 1e3),
         "roofline": {"bound": "hbm", "achieved": d["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": d["GBps"] / HBM_PEAK_GBS, "traffic": traffic, "kernel": d["kernel"],
-                     "timed_unit": "the whole call (k_tile_y<1> then k_adj_csc<1>)"
-                     if dom == "adjoint" else "the kernel",
+                     "timed_unit": "the kernel's own launches (every other timed step): "
+                                   "HIP events the library records around it on the "
+                                   "call's stream",
                      # bytes the counters saw moved, over the same time: the
                      # physical fraction (the stores hold ~5 B per segment, not 8)
                      "traffic_frac": None if traffic is None

@@ -375,6 +375,27 @@ tsp_status tsp_segments(const tsp_geometry *g, int64_t *row_ptr, int32_t *vox, f
  * float64 [R][3] each; either pointer may be NULL. */
 tsp_status tsp_rays(const tsp_geometry *g, double *starts, double *dirs, void *stream);
 
+/*
+ * Measurement hook (not part of the method): the next tsp_forward or
+ * tsp_backproject call on g records `start` on its stream just before the
+ * operation's main kernel and `stop` just after it, so that the caller's
+ * hipEventElapsedTime(start, stop) is that kernel's own duration, without
+ * the call's other launches.  The main kernel is the gather-sum of the
+ * stored forward (Sec. 3.4) and the voxel-major sum of the deterministic
+ * adjoint (the slot-ordered copy of y before it is left out); for batches
+ * above four, from the first group's main kernel to the end of the last's.
+ * On every other path (on the fly, atomic, fixed point, the adjoint traced
+ * in chunks) the events bracket the whole operation.  One-shot: the call
+ * that records them clears the setting; start = stop = NULL clears it too.
+ * The events are hipEvent_t handles created by the caller on g's device
+ * (with timing, i.e. without hipEventDisableTiming) and stay the caller's.
+ * Setting events and calling from several threads at once on one geometry
+ * leaves it open which call records them.
+ * Errors: TSP_E_INVALID (g NULL, exactly one of start and stop NULL); a
+ * failed record makes the forward or adjoint call return TSP_E_HIP.
+ */
+tsp_status tsp_set_timing_events(tsp_geometry *g, void *start, void *stop);
+
 /* Sizes and state; valid at any time after creation. */
 tsp_status tsp_query(const tsp_geometry *g, tsp_info *info);
 

@@ -117,6 +117,9 @@ struct tsp_geometry {
     std::vector<int32_t> win_segs;
     // serialises that adjoint's use of chunk_arena across threads
     mutable std::mutex chunk_mu;
+    // events for the next forward or adjoint call (tsp_set_timing_events)
+    mutable std::mutex timing_mu;
+    mutable KernelEvents timing;
 };
 
 namespace {
@@ -267,29 +270,53 @@ tsp_status sync_stream(hipStream_t st) {
 
 namespace {
 
-// y = F rho on a traced geometry (either mode).
+// The timing events set for g's next call, cleared (see tsp_set_timing_events).
+KernelEvents take_timing(const tsp_geometry *g) {
+    std::lock_guard<std::mutex> lk(g->timing_mu);
+    const KernelEvents ke = g->timing;
+    g->timing = KernelEvents();
+    return ke;
+}
+
+// Runs f (a sequence of launches on st) between the records of ke's events,
+// when ke holds any.
+template <class F> hipError_t bracketed(const KernelEvents *ke, hipStream_t st, F f) {
+    hipError_t e = (ke && ke->start) ? hipEventRecord(ke->start, st) : hipSuccess;
+    if (e == hipSuccess) e = f();
+    if (e == hipSuccess && ke && ke->stop) e = hipEventRecord(ke->stop, st);
+    return e;
+}
+
+// y = F rho on a traced geometry (either mode); ke: events around the main
+// kernel (the stored gather-sum) or, on the fly, the whole launch.
 hipError_t forward_dispatch(const tsp_geometry *g, const float *rho, int batch, float *y,
-                            hipStream_t st) {
+                            hipStream_t st, const KernelEvents *ke = nullptr) {
     if (g->mode == TSP_MODE_CSR)
         return launch_forward_sell(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
                                    g->d_slice_len, g->d_code, g->d_len, rho, batch, g->V,
-                                   g->T.na, g->T.ne * g->T.na, y, st);
-    return launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
+                                   g->T.na, g->T.ne * g->T.na, y, st, ke);
+    return bracketed(ke, st, [&] {
+        return launch_otf_forward(g->T, g->d_tab, g->rd, rho, batch, g->V, y, st);
+    });
 }
 
-// x = F^T y; TSP_ADJ_DETERMINISTIC needs the transposed store (checked by callers).
+// x = F^T y; TSP_ADJ_DETERMINISTIC needs the transposed store (checked by
+// callers).  ke: events around the voxel-major sum of the deterministic
+// adjoint, or around the whole operation on the atomic paths.
 hipError_t adjoint_dispatch(const tsp_geometry *g, const float *y, int batch, float *x,
-                            int method, hipStream_t st) {
+                            int method, hipStream_t st, const KernelEvents *ke = nullptr) {
     if (method == TSP_ADJ_DETERMINISTIC)
         return launch_adjoint_csc(g->rd, g->d_col_ptr, g->d_col_code, g->d_col_len, g->T.nr,
-                                  g->T.ne, g->T.na, y, batch, x, nullptr, st);
-    hipError_t e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
-    if (e != hipSuccess) return e;
-    if (g->mode == TSP_MODE_CSR)
-        return launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
-                                     g->d_slice_len, g->d_code, g->d_len, y, batch, g->V,
-                                     g->T.na, g->T.ne * g->T.na, x, st);
-    return launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+                                  g->T.ne, g->T.na, y, batch, x, nullptr, st, ke);
+    return bracketed(ke, st, [&] {
+        hipError_t e = launch_zero_f32(x, (int64_t)batch * g->FV(), st);
+        if (e != hipSuccess) return e;
+        if (g->mode == TSP_MODE_CSR)
+            return launch_adjoint_atomic(g->rd, g->d_perm, g->d_cnt_sorted, g->d_slice_ptr,
+                                         g->d_slice_len, g->d_code, g->d_len, y, batch, g->V,
+                                         g->T.na, g->T.ne * g->T.na, x, st);
+        return launch_otf_adjoint(g->T, g->d_tab, g->rd, y, batch, g->V, x, st);
+    });
 }
 
 // Device address of `scratch` on device `dev` (the current device), looked
@@ -1226,7 +1253,8 @@ tsp_status tsp_forward(const tsp_geometry *g, const float *rho, int32_t batch, f
     if (batch < 1) return fail(TSP_E_INVALID, "batch < 1");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_forward before tsp_trace");
     DeviceGuard dg(g->device);
-    const hipError_t e = forward_dispatch(g, rho, batch, y, (hipStream_t)stream);
+    const KernelEvents ke = take_timing(g);
+    const hipError_t e = forward_dispatch(g, rho, batch, y, (hipStream_t)stream, &ke);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("forward: ") + hipGetErrorString(e));
     return TSP_OK;
 }
@@ -1243,18 +1271,39 @@ tsp_status tsp_backproject(const tsp_geometry *g, const float *y, int32_t batch,
                     "method must be TSP_ADJ_DETERMINISTIC, TSP_ADJ_ATOMIC or TSP_ADJ_FIXEDPOINT");
     if (g->mode == 0) return fail(TSP_E_STATE, "tsp_backproject before tsp_trace");
     DeviceGuard dg(g->device);
+    const KernelEvents ke = take_timing(g);
+    hipStream_t st = (hipStream_t)stream;
     if (method == TSP_ADJ_FIXEDPOINT) {
-        const hipError_t e = launch_otf_adjoint_fixed(g->T, g->d_tab, g->rd, y, batch, g->V,
-                                                      g->r_out, x, (hipStream_t)stream);
+        const hipError_t e = bracketed(&ke, st, [&] {
+            return launch_otf_adjoint_fixed(g->T, g->d_tab, g->rd, y, batch, g->V, g->r_out, x,
+                                            st);
+        });
         if (e != hipSuccess)
             return fail(e == hipErrorOutOfMemory ? TSP_E_NOMEM : TSP_E_HIP,
                         std::string("adjoint: ") + hipGetErrorString(e));
         return TSP_OK;
     }
-    if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr))
-        return chunked_adjoint(g, y, batch, x, (hipStream_t)stream);
-    const hipError_t e = adjoint_dispatch(g, y, batch, x, method, (hipStream_t)stream);
+    if (method == TSP_ADJ_DETERMINISTIC && (g->mode != TSP_MODE_CSR || !g->d_col_ptr)) {
+        if (ke.start && hipEventRecord(ke.start, st) != hipSuccess)
+            return fail(TSP_E_HIP, "adjoint: recording the start event failed");
+        const tsp_status s = chunked_adjoint(g, y, batch, x, st);
+        if (s == TSP_OK && ke.stop && hipEventRecord(ke.stop, st) != hipSuccess)
+            return fail(TSP_E_HIP, "adjoint: recording the stop event failed");
+        return s;
+    }
+    const hipError_t e = adjoint_dispatch(g, y, batch, x, method, st, &ke);
     if (e != hipSuccess) return fail(TSP_E_HIP, std::string("adjoint: ") + hipGetErrorString(e));
+    return TSP_OK;
+}
+
+tsp_status tsp_set_timing_events(tsp_geometry *g, void *start, void *stop) {
+    g_err.clear();
+    if (!g) return fail(TSP_E_INVALID, "geometry is NULL");
+    if ((start == nullptr) != (stop == nullptr))
+        return fail(TSP_E_INVALID, "start and stop must both be set or both be NULL");
+    std::lock_guard<std::mutex> lk(g->timing_mu);
+    g->timing.start = (hipEvent_t)start;
+    g->timing.stop = (hipEvent_t)stop;
     return TSP_OK;
 }
 

@@ -380,12 +380,17 @@ inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1)
 
 }  // namespace
 
+// Records ev on st when it is set (the timing events around a main kernel).
+static hipError_t record_if(hipEvent_t ev, hipStream_t st) {
+    return ev ? hipEventRecord(ev, st) : hipSuccess;
+}
+
 template <int NB>
 static hipError_t fwd_chunk(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                             const int64_t *slice_ptr, const int32_t *slice_len,
                             const uint8_t *code, const float *len, const float *rho, int nb,
                             int64_t vf, int64_t FV, int na, int nena, float *y, void *packed,
-                            hipStream_t st) {
+                            hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
     using T = typename YVec<NB>::T;
     const T *r = (const T *)rho;
     if (NB > 1) {
@@ -393,16 +398,20 @@ static hipError_t fwd_chunk(const RayDesc &rd, const int32_t *perm, const int32_
                            (T *)packed);
         r = (const T *)packed;
     }
+    hipError_t e = record_if(ev_start, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_fwd_sell<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, perm,
                        cnt_sorted, slice_ptr, slice_len, code, len, rd.n_slots, r, nb, rd.R, y,
                        rd.obj_frame, (int64_t)rd.H * rd.W, vf, na, nena);
-    return hipGetLastError();
+    e = hipGetLastError();
+    return e != hipSuccess ? e : record_if(ev_stop, st);
 }
 
 hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
                                const uint8_t *code, const float *len, const float *rho, int B,
-                               int64_t vf, int na, int nena, float *y, hipStream_t st) {
+                               int64_t vf, int na, int nena, float *y, hipStream_t st,
+                               const KernelEvents *ke) {
     // batches: objects packed voxel-major (4, 8 or 16 bytes per voxel) so that
     // one gather per segment serves every object of a group of up to four
     const int64_t FV = vf * rd.n_obj_frames;
@@ -417,15 +426,18 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *r = rho + (int64_t)b0 * FV;
         float *yy = y + (int64_t)b0 * rd.R;
+        // the timing events go round the first group's kernel to the last's
+        const hipEvent_t es = (ke && b0 == 0) ? ke->start : nullptr;
+        const hipEvent_t ee = (ke && b0 + 4 >= B) ? ke->stop : nullptr;
         if (nb == 1)
             e = fwd_chunk<1>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
-                             FV, na, nena, yy, packed, st);
+                             FV, na, nena, yy, packed, st, es, ee);
         else if (nb == 2)
             e = fwd_chunk<2>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
-                             FV, na, nena, yy, packed, st);
+                             FV, na, nena, yy, packed, st, es, ee);
         else
             e = fwd_chunk<4>(rd, perm, cnt_sorted, slice_ptr, slice_len, code, len, r, nb, vf,
-                             FV, na, nena, yy, packed, st);
+                             FV, na, nena, yy, packed, st, es, ee);
     }
     if (packed) {
         const hipError_t f = hipFreeAsync(packed, st);
@@ -437,15 +449,19 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
 template <int NB>
 static hipError_t adj_csc_chunk(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
                                 const float *len, int nr, int ne, int na, const float *y,
-                                int nb, float *x, void *yt, hipStream_t st) {
+                                int nb, float *x, void *yt, hipStream_t st, hipEvent_t ev_start,
+                                hipEvent_t ev_stop) {
     using T = typename YVec<NB>::T;
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     hipLaunchKernelGGL(k_tile_y<NB>, dim3(blocks_for(rd.n_slots, 256)), dim3(256), 0, st, rd, y,
                        nb, (T *)yt);
+    hipError_t e = record_if(ev_start, st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_csc<NB>, dim3(strided_blocks(FV * kWave)), dim3(256), 0, st,
                        col_base, code, len, nr, ne, na, rd.n_obj_frames, rd.n_slots,
                        (const T *)yt, nb, x);
-    return hipGetLastError();
+    e = hipGetLastError();
+    return e != hipSuccess ? e : record_if(ev_stop, st);
 }
 
 size_t adjoint_csc_ws_bytes(const RayDesc &rd, int B) {
@@ -455,7 +471,7 @@ size_t adjoint_csc_ws_bytes(const RayDesc &rd, int B) {
 
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
                               const float *len, int nr, int ne, int na, const float *y, int B,
-                              float *x, void *ws, hipStream_t st) {
+                              float *x, void *ws, hipStream_t st, const KernelEvents *ke) {
     const int64_t FV = (int64_t)nr * ne * na * rd.n_obj_frames;
     void *yt = ws;
     hipError_t e = hipSuccess;
@@ -467,12 +483,14 @@ hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const 
         const int nb = (B - b0 < 4) ? (B - b0) : 4;
         const float *yy = y + (int64_t)b0 * rd.R;
         float *xx = x + (int64_t)b0 * FV;
+        const hipEvent_t es = (ke && b0 == 0) ? ke->start : nullptr;
+        const hipEvent_t ee = (ke && b0 + 4 >= B) ? ke->stop : nullptr;
         if (nb == 1)
-            e = adj_csc_chunk<1>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<1>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st, es, ee);
         else if (nb == 2)
-            e = adj_csc_chunk<2>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<2>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st, es, ee);
         else
-            e = adj_csc_chunk<4>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st);
+            e = adj_csc_chunk<4>(rd, col_base, code, len, nr, ne, na, yy, nb, xx, yt, st, es, ee);
     }
     if (ws) return e;
     const hipError_t f = hipFreeAsync(yt, st);

@@ -259,6 +259,12 @@ __host__ __device__ __forceinline__ int32_t store_voxel(int64_t k, int nr, int n
     return (ir * ne + te * T + rem2 / ha) * na + ta * T + rem2 % ha;
 }
 
+// Events a launcher records on its stream around its main kernel (null:
+// none); see tsp_set_timing_events.
+struct KernelEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 // ---- launchers (tsp_trace.hip) ----
 // win_seg (may be null, zeroed by the caller): canonical segments per window
 // of kWindow natural slots
@@ -343,7 +349,8 @@ hipError_t launch_pack_fill(const int64_t *col_ptr, const uint64_t *ent, int64_t
 hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int32_t *cnt_sorted,
                                const int64_t *slice_ptr, const int32_t *slice_len,
                                const uint8_t *code, const float *len, const float *rho, int B,
-                               int64_t vf, int na, int nena, float *y, hipStream_t st);
+                               int64_t vf, int na, int nena, float *y, hipStream_t st,
+                               const KernelEvents *ke = nullptr);
 // col_base is indexed by object frame, then the voxel's store key: the
 // packed voxel-major store (codes and lengths, see kSlotEsc) of key k spans
 // entries col_base[k] .. col_base[k+1]; x is written in (frame, r, e, a)
@@ -353,7 +360,8 @@ hipError_t launch_forward_sell(const RayDesc &rd, const int32_t *perm, const int
 size_t adjoint_csc_ws_bytes(const RayDesc &rd, int B);
 hipError_t launch_adjoint_csc(const RayDesc &rd, const int64_t *col_base, const uint8_t *code,
                               const float *len, int nr, int ne, int na, const float *y, int B,
-                              float *x, void *ws, hipStream_t st);
+                              float *x, void *ws, hipStream_t st,
+                              const KernelEvents *ke = nullptr);
 hipError_t launch_adjoint_atomic(const RayDesc &rd, const int32_t *perm,
                                  const int32_t *cnt_sorted, const int64_t *slice_ptr,
                                  const int32_t *slice_len, const uint8_t *code, const float *len,

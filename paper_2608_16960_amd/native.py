@@ -83,6 +83,7 @@ SIGNATURES = {
     "tsp_backproject_noalloc": (_st, [_vp, _vp, ctypes.c_int32, _vp, _vp]),
     "tsp_segments": (_st, [_vp, _vp, _vp, _vp, _vp]),
     "tsp_rays": (_st, [_vp, _vp, _vp, _vp]),
+    "tsp_set_timing_events": (_st, [_vp, _vp, _vp]),
     "tsp_query": (_st, [_vp, ctypes.POINTER(tsp_info)]),
     "tsp_geometry_destroy": (None, [_vp]),
     "tsp_last_error": (ctypes.c_char_p, []),

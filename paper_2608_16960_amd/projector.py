@@ -126,6 +126,21 @@ class Projector:
         N.check(N.lib.tsp_query(self._h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in N.tsp_info._fields_}
 
+    def set_timing_events(self, start, stop):
+        """Measurement hook: the next forward or backproject call records
+        the torch.cuda.Event pair (timing enabled, on this GPU) around its
+        main kernel (tsp_set_timing_events); (None, None) clears it."""
+        if (start is None) != (stop is None):
+            raise ValueError("start and stop must both be events or both None")
+        hs = [None, None]
+        if start is not None:
+            for i, ev in enumerate((start, stop)):
+                if not ev.cuda_event:   # torch creates the handle on first use
+                    with torch.cuda.device(self.device):
+                        ev.record()
+                hs[i] = ctypes.c_void_p(ev.cuda_event)
+        N.check(N.lib.tsp_set_timing_events(self._h, hs[0], hs[1]))
+
     @property
     def n_rays(self):
         return int(np.prod(self.out_shape))

@@ -155,4 +155,5 @@ def test_null_geometry_calls():
     assert N.lib.tsp_backproject(None, None, 1, None, 1, None) == N.TSP_E_INVALID
     info = N.tsp_info()
     assert N.lib.tsp_query(None, ctypes.byref(info)) == N.TSP_E_INVALID
+    assert N.lib.tsp_set_timing_events(None, None, None) == N.TSP_E_INVALID
     N.lib.tsp_geometry_destroy(None)

@@ -1,6 +1,8 @@
 """Error paths of the C ABI that need a device: state errors, the device-memory
 cap (TSP_MAX_DEVICE_BYTES) with the on-the-fly fallback, unsupported
-combinations.  Every case returns an error code; no kernel is made to fail."""
+combinations.  Every case returns an error code; no kernel is made to fail.
+Also the timing hook (tsp_set_timing_events): the events bracket the main
+kernel only, once, and leave the results as they are."""
 import ctypes
 import os
 
@@ -121,3 +123,58 @@ def test_object_frame_errors():
             N.TSP_E_UNSUPPORTED
     finally:
         N.lib.tsp_geometry_destroy(h2)
+
+
+def test_timing_events_bracket_the_main_kernel():
+    """Medium workload, batch 1, stored lists.  The kernel's own time lies
+    inside the call's (torch events on the same stream around the call), the
+    events are recorded by one call only, and the results are bitwise those
+    of calls without events.  On the fly they bracket the whole launch."""
+    from paper_2608_16960_amd import native as N
+    from paper_2608_16960_amd.projector import Projector
+    w = W.medium()
+    P = Projector(w.grid, views=w.views)
+    rho = torch.from_numpy(w.rho[:1]).cuda()
+    y0 = P.forward(rho)
+    x0 = P.backproject(y0, "deterministic")
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    try:
+        for op in ("forward", "adjoint"):
+            ks, ke, cs, ce = ev(), ev(), ev(), ev()
+            P.set_timing_events(ks, ke)
+            cs.record()
+            out = P.forward(rho) if op == "forward" else P.backproject(y0, "deterministic")
+            ce.record()
+            torch.cuda.synchronize()
+            assert torch.equal(out, y0 if op == "forward" else x0)
+            tk, tc = ks.elapsed_time(ke), cs.elapsed_time(ce)
+            print(op, "kernel", tk, "call", tc, flush=True)
+            assert 0 < tk <= tc
+            # one-shot: the next call records nothing
+            P.backproject(y0, "deterministic")
+            torch.cuda.synchronize()
+            assert ks.elapsed_time(ke) == tk
+        # half a pair is refused, on the ABI and in the binding
+        h = ks.cuda_event
+        assert N.lib.tsp_set_timing_events(P._h, ctypes.c_void_p(h), None) == N.TSP_E_INVALID
+        with pytest.raises(ValueError):
+            P.set_timing_events(ks, None)
+        # set and cleared: nothing recorded
+        P.set_timing_events(ks, ke)
+        P.set_timing_events(None, None)
+        P.forward(rho)
+        torch.cuda.synchronize()
+        assert ks.elapsed_time(ke) == tk
+        # on the fly: the events bracket the whole launch
+        P.retrace("onthefly")
+        ks, ke = ev(), ev()
+        P.set_timing_events(ks, ke)
+        yo = P.forward(rho)
+        torch.cuda.synchronize()
+        assert ks.elapsed_time(ke) > 0
+        assert float((yo - y0).abs().max()) <= 1e-5 * float(y0.abs().max())
+    finally:
+        P.close()
