@@ -206,6 +206,26 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _kernel_ms(P, fn, reps, warm=1):
+    """Mean duration of the main kernel of P's call fn (a forward or an
+    adjoint), from the HIP events the library records around it on the
+    call's stream (tsp_set_timing_events); the calls run back to back."""
+    import torch
+    for _ in range(warm):
+        fn()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        b.record()
+    torch.cuda.synchronize()
+    for a, b in evs:
+        P.set_timing_events(a, b)
+        fn()
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / reps
+
+
 def _time_ms(fn, reps, warm=1):
     import torch
     for _ in range(warm):
@@ -354,6 +374,8 @@ def extra_large_csr(reps=5):
     x = torch.empty_like(rho)
     f_ms = _time_ms(lambda: P.forward(rho, out=y), reps)
     a_ms = _time_ms(lambda: P.backproject(y, "deterministic", out=x), reps)
+    fk = _kernel_ms(P, lambda: P.forward(rho, out=y), reps)
+    ak = _kernel_ms(P, lambda: P.backproject(y, "deterministic", out=x), reps)
     fb, ab = 8 * S + 8 * R + 4 * B * R + 4 * B * V, 8 * S + 8 * V + 4 * B * V + 4 * B * R
     P.close()
     del y, x, rho
@@ -361,6 +383,10 @@ def extra_large_csr(reps=5):
     return {"workload": f"large from stored lists: {R} rays, {S} segments, batch {B}",
             "trace_s": trace_s, "device_GB": inf["device_bytes"] / 1e9,
             "forward_ms": f_ms, "adjoint_ms": a_ms,
+            # the main kernels alone (k_fwd_sell<4>, k_adj_csc<4>)
+            "forward_kernel_ms": fk, "adjoint_kernel_ms": ak,
+            "forward_kernel_hbm_frac": fb / fk / 1e6 / HBM_PEAK_GBS,
+            "adjoint_kernel_hbm_frac": ab / ak / 1e6 / HBM_PEAK_GBS,
             "forward_rays_per_s": B * R / f_ms * 1e3, "adjoint_rays_per_s": B * R / a_ms * 1e3,
             "forward_hbm_frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
             "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS}
@@ -382,8 +408,12 @@ def extra_diff_csr():
     rho = torch.from_numpy(w.rho).cuda()
     y = P.forward(rho)
     x = torch.empty_like(rho)
-    f_ms = _time_ms(lambda: P.forward(rho, out=y), 10)
-    a_ms = _time_ms(lambda: P.backproject(y, "deterministic", out=x), 10)
+    # the main kernels alone (k_fwd_sell<1>, k_adj_csc<1>), as the step's
+    # roofline takes them; the whole calls beside them
+    f_ms = _kernel_ms(P, lambda: P.forward(rho, out=y), 10)
+    a_ms = _kernel_ms(P, lambda: P.backproject(y, "deterministic", out=x), 10)
+    f_call = _time_ms(lambda: P.forward(rho, out=y), 10)
+    a_call = _time_ms(lambda: P.backproject(y, "deterministic", out=x), 10)
     fb, ab = 8 * S + 8 * R + 4 * R + 4 * V, 8 * S + 8 * V + 4 * V + 4 * R
     P.close()
     torch.cuda.empty_cache()
@@ -394,7 +424,9 @@ def extra_diff_csr():
     return {"workload": f"diff: grid {P.shape}, {w.views.n_views} cone views "
                         f"{w.views.H}x{w.views.W}, {R} rays, {S} segments, batch 1",
             "trace_s": trace_s, "forward_ms": f_ms, "adjoint_ms": a_ms,
-            "rays_per_s": R / (f_ms + a_ms) * 1e3, "segments_per_s": S / (f_ms + a_ms) * 1e3,
+            "forward_call_ms": f_call, "adjoint_call_ms": a_call,
+            "rays_per_s": R / (f_call + a_call) * 1e3,
+            "segments_per_s": S / (f_call + a_call) * 1e3,
             "forward_hbm_frac": fb / f_ms / 1e6 / HBM_PEAK_GBS,
             "adjoint_hbm_frac": ab / a_ms / 1e6 / HBM_PEAK_GBS,
             "forward_traffic_frac": None if traffic["forward"] is None
